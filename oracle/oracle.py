@@ -1,0 +1,249 @@
+"""ctypes front end of the FP64 CPU oracle (oracle/vct_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline of the benchmark. It takes a trial dict (plain numbers) and returns
+numpy arrays; it never touches the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+NP, NX, NPOUT, MAX_SLOTS = 15, 11, 19, 4
+INT_EM, INT_RK4 = 0, 1
+
+
+class OrcConfig(C.Structure):
+    _fields_ = [
+        ("pop_seed", C.c_uint64), ("arm_id", C.c_uint32), ("pop_flags", C.c_uint32),
+        ("nominal", C.c_double * NP), ("cv", C.c_double), ("ag", C.c_double), ("tau_cgm", C.c_double),
+        ("g_target", C.c_double),
+        ("n_slots", C.c_int32), ("minute_of_day", C.c_int32 * MAX_SLOTS), ("carbs_mean", C.c_double * MAX_SLOTS),
+        ("carbs_sd", C.c_double * MAX_SLOTS), ("prob", C.c_double * MAX_SLOTS), ("jitter", C.c_int32),
+        ("ctrl_kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
+        ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double),
+        ("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("sigma_q1", C.c_double),
+        ("cgm_var", C.c_double), ("noise_seed", C.c_uint64), ("integrator", C.c_int32), ("rk4_sub", C.c_int32),
+        ("x0_offset", C.c_double * NX), ("guard_rel", C.c_double),
+    ]
+
+
+_P = C.POINTER
+
+
+class OrcOutputs(C.Structure):
+    _fields_ = [
+        ("bins", _P(C.c_int32)), ("events", _P(C.c_int32)), ("sum_g", _P(C.c_double)), ("min_g", _P(C.c_double)),
+        ("argmin_k", _P(C.c_int32)), ("sum_u", _P(C.c_double)), ("status", _P(C.c_uint32)),
+        ("n_near", _P(C.c_int32)), ("ctrl_margin", _P(C.c_double)), ("params", _P(C.c_double)),
+        ("n_traj", C.c_int32), ("traj_g", _P(C.c_double)), ("traj_y", _P(C.c_double)), ("traj_u", _P(C.c_double)),
+        ("traj_x", _P(C.c_double)),
+    ]
+
+
+class OrcSummary(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64), ("k", C.c_int64), ("bins", C.c_uint64 * 5), ("events", C.c_uint64 * 3),
+        ("q_count", C.c_int64 * 5), ("mean_tir", C.c_double), ("mean_bg", C.c_double),
+        ("worst_patient", C.c_int64), ("worst_min_g", C.c_double), ("worst_k", C.c_int32),
+        ("status_count", C.c_int64 * 3),
+    ]
+
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    """Load the oracle library, compiling it first only if it is not built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = C.CDLL(_build.LIB)
+        L.orc_philox4x32_10.argtypes = [_P(C.c_uint32), _P(C.c_uint32), _P(C.c_uint32)]
+        L.orc_uniform.argtypes = [C.c_uint32]
+        L.orc_uniform.restype = C.c_double
+        L.orc_normals4.argtypes = [_P(C.c_uint32), _P(C.c_uint32), _P(C.c_double)]
+        L.orc_sample_population.argtypes = [_P(OrcConfig), C.c_int64, C.c_int64, _P(C.c_double)]
+        L.orc_basal.argtypes = [_P(OrcConfig), _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_double)]
+        L.orc_basal.restype = C.c_int
+        L.orc_rhs.argtypes = [_P(OrcConfig), _P(C.c_double), _P(C.c_double), C.c_double, C.c_double,
+                              _P(C.c_double)]
+        L.orc_simulate.argtypes = [_P(OrcConfig), C.c_int64, C.c_int64, C.c_int, _P(OrcOutputs)]
+        L.orc_simulate.restype = C.c_int
+        L.orc_em_ou.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int64,
+                                C.c_uint64, _P(C.c_double)]
+        L.orc_reduce.argtypes = [C.c_int64, C.c_int64, _P(C.c_int32), _P(C.c_int32), _P(C.c_double),
+                                 _P(C.c_double), _P(C.c_int32), _P(C.c_uint32), _P(OrcSummary)]
+        L.orc_meals.argtypes = [_P(OrcConfig), C.c_uint32, C.c_int32, _P(C.c_double)]
+        L.orc_pid_run.argtypes = [_P(OrcConfig), C.c_double, C.c_int32, _P(C.c_double), _P(C.c_double),
+                                  _P(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _ptr(a: np.ndarray | None, ctype):
+    if a is None:
+        return C.cast(None, _P(ctype))
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_P(ctype))
+
+
+def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=None,
+           guard_rel: float = 1e-4) -> OrcConfig:
+    c = OrcConfig()
+    c.pop_seed = int(trial["pop_seed"])
+    c.arm_id = int(trial["arm_id"])
+    c.pop_flags = int(trial["pop_flags"])
+    for i, v in enumerate(trial["nominal"]):
+        c.nominal[i] = float(v)
+    c.cv, c.ag, c.tau_cgm, c.g_target = (float(trial[k]) for k in ("cv", "ag", "tau_cgm", "g_target"))
+    c.n_slots = int(trial["n_slots"])
+    for m in range(MAX_SLOTS):
+        c.minute_of_day[m] = int(trial["minute_of_day"][m])
+        c.carbs_mean[m] = float(trial["carbs_mean"][m])
+        c.carbs_sd[m] = float(trial["carbs_sd"][m])
+        c.prob[m] = float(trial["prob"][m])
+    c.jitter = int(trial["jitter"])
+    c.ctrl_kind = int(trial["ctrl_kind"])
+    for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel", "sigma_q1", "cgm_var"):
+        setattr(c, k, float(trial[k]))
+    c.n_days, c.em_per_ctrl, c.ts_min = int(trial["n_days"]), int(trial["em_per_ctrl"]), int(trial["ts_min"])
+    c.noise_seed = int(trial["noise_seed"])
+    c.integrator = int(integrator)
+    c.rk4_sub = int(rk4_sub)
+    if x0_offset is not None:
+        for i, v in enumerate(x0_offset):
+            c.x0_offset[i] = float(v)
+    c.guard_rel = float(guard_rel)
+    return c
+
+
+# ---------------------------------------------------------------- primitives
+def philox(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_uint32 * 4)()
+    lib().orc_philox4x32_10(c, k, o)
+    return np.array(list(o), dtype=np.uint32)
+
+
+def uniform(x: int) -> float:
+    return lib().orc_uniform(int(x) & 0xFFFFFFFF)
+
+
+def normals4(ctr, key) -> np.ndarray:
+    c = (C.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (C.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (C.c_double * 4)()
+    lib().orc_normals4(c, k, o)
+    return np.array(list(o))
+
+
+def sample_population(trial: dict, first: int = 0, count: int | None = None) -> np.ndarray:
+    n = int(trial["n_patients"]) - first if count is None else int(count)
+    out = np.zeros((n, NPOUT))
+    cfg = config(trial)
+    lib().orc_sample_population(C.byref(cfg), first, n, _ptr(out, C.c_double))
+    return out
+
+
+def basal(trial: dict, p) -> tuple[bool, float, float, np.ndarray]:
+    cfg = config(trial)
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    i_star, u_b = C.c_double(), C.c_double()
+    x0 = np.zeros(NX)
+    ok = lib().orc_basal(C.byref(cfg), _ptr(pa, C.c_double), C.byref(i_star), C.byref(u_b), _ptr(x0, C.c_double))
+    return bool(ok), i_star.value, u_b.value, x0
+
+
+def rhs(trial: dict, p, x, u: float, d: float) -> np.ndarray:
+    cfg = config(trial)
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64)
+    dx = np.zeros(NX)
+    lib().orc_rhs(C.byref(cfg), _ptr(pa, C.c_double), _ptr(xa, C.c_double), float(u), float(d),
+                  _ptr(dx, C.c_double))
+    return dx
+
+
+def em_ou(theta: float, s: float, x0: float, h: float, n_steps: int, n_paths: int, seed: int) -> np.ndarray:
+    out = np.zeros(n_paths)
+    lib().orc_em_ou(theta, s, x0, h, n_steps, n_paths, seed, _ptr(out, C.c_double))
+    return out
+
+
+def meals(trial: dict, patient: int, day: int) -> np.ndarray:
+    out = np.zeros((int(trial["n_slots"]), 4))
+    cfg = config(trial)
+    lib().orc_meals(C.byref(cfg), int(patient), int(day), _ptr(out, C.c_double))
+    return out
+
+
+def pid_run(trial: dict, u_b: float, y) -> tuple[np.ndarray, np.ndarray]:
+    ya = np.ascontiguousarray(y, dtype=np.float64)
+    u = np.zeros_like(ya)
+    integ = np.zeros_like(ya)
+    cfg = config(trial)
+    lib().orc_pid_run(C.byref(cfg), float(u_b), len(ya), _ptr(ya, C.c_double), _ptr(u, C.c_double),
+                      _ptr(integ, C.c_double))
+    return u, integ
+
+
+# ------------------------------------------------------------------ simulate
+def simulate(trial: dict, first: int = 0, count: int | None = None, threads: int | None = None,
+             n_traj: int = 0, record_x: bool = False, integrator: int = INT_EM, rk4_sub: int = 64,
+             x0_offset=None, guard_rel: float = 1e-4) -> dict:
+    """Run patients [first, first+count) of the trial; returns per-patient arrays."""
+    n = int(trial["n_patients"]) - first if count is None else int(count)
+    K = int(trial["n_days"]) * (1440 // int(trial["ts_min"]))
+    nt = min(int(n_traj), n)
+    r = {
+        "bins": np.zeros((n, 5), np.int32), "events": np.zeros((n, 3), np.int32),
+        "sum_g": np.zeros(n), "min_g": np.zeros(n), "argmin_k": np.zeros(n, np.int32), "sum_u": np.zeros(n),
+        "status": np.zeros(n, np.uint32), "n_near": np.zeros(n, np.int32), "ctrl_margin": np.zeros(n),
+        "params": np.zeros((n, NPOUT)),
+    }
+    if nt:
+        r["traj_g"] = np.zeros((nt, K))
+        r["traj_y"] = np.zeros((nt, K))
+        r["traj_u"] = np.zeros((nt, K))
+        if record_x:
+            r["traj_x"] = np.zeros((nt, K, NX))
+    o = OrcOutputs()
+    o.bins, o.events = _ptr(r["bins"], C.c_int32), _ptr(r["events"], C.c_int32)
+    o.sum_g, o.min_g = _ptr(r["sum_g"], C.c_double), _ptr(r["min_g"], C.c_double)
+    o.argmin_k, o.sum_u = _ptr(r["argmin_k"], C.c_int32), _ptr(r["sum_u"], C.c_double)
+    o.status, o.n_near = _ptr(r["status"], C.c_uint32), _ptr(r["n_near"], C.c_int32)
+    o.ctrl_margin, o.params = _ptr(r["ctrl_margin"], C.c_double), _ptr(r["params"], C.c_double)
+    o.n_traj = nt
+    o.traj_g = _ptr(r.get("traj_g"), C.c_double)
+    o.traj_y = _ptr(r.get("traj_y"), C.c_double)
+    o.traj_u = _ptr(r.get("traj_u"), C.c_double)
+    o.traj_x = _ptr(r.get("traj_x"), C.c_double)
+    cfg = config(trial, integrator=integrator, rk4_sub=rk4_sub, x0_offset=x0_offset, guard_rel=guard_rel)
+    if threads is None:
+        threads = os.cpu_count() or 1
+    rc = lib().orc_simulate(C.byref(cfg), first, n, int(threads), C.byref(o))
+    if rc != 0:
+        raise ValueError("oracle rejected the trial description")
+    r["K"] = K
+    r["threads"] = int(threads)
+    return r
+
+
+def reduce(r: dict) -> dict:
+    n = r["bins"].shape[0]
+    s = OrcSummary()
+    lib().orc_reduce(n, int(r["K"]), _ptr(r["bins"], C.c_int32), _ptr(r["events"], C.c_int32),
+                     _ptr(r["sum_g"], C.c_double), _ptr(r["min_g"], C.c_double), _ptr(r["argmin_k"], C.c_int32),
+                     _ptr(r["status"], C.c_uint32), C.byref(s))
+    return {
+        "n": s.n, "k": s.k, "bins": list(s.bins), "events": list(s.events), "q_count": list(s.q_count),
+        "mean_tir": s.mean_tir, "mean_bg": s.mean_bg, "worst_patient": s.worst_patient,
+        "worst_min_g": s.worst_min_g, "worst_k": s.worst_k, "status_count": list(s.status_count),
+    }

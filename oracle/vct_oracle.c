@@ -1,0 +1,636 @@
+/*
+ * vct_oracle.c -- plain FP64 CPU oracle for closed-loop virtual clinical trials.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the tests, the smoke check and the CPU
+ * baseline of the benchmark. It shares no code with the GPU library.
+ *
+ * The method (paper, Sec. III): closed-loop Monte Carlo over independent virtual
+ * patients. Each patient is the SDE of Sec. III-A eq. (1) with piecewise-constant
+ * inputs (eq. 2), driven by a sampled controller (Sec. III-B eq. 3); the ranges of
+ * Sec. IV-A are accumulated while the simulation runs (Sec. III-C). The patient
+ * model is the Hovorka core extended with a one-state CGM model (Sec. IV-B); the
+ * model equations, the parameter distribution, the noise levels, the meal
+ * protocol and the controller are the project's stated readings of what the paper
+ * leaves open, written out below next to the code that uses them.
+ *
+ * Everything is FP64 and follows the definitions literally: no blocking, no
+ * reordering, no fused tricks.
+ */
+#include "vct_oracle.h"
+
+#include <math.h>
+#include <pthread.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------ RNG ---- */
+/* Philox4x32-10, from the description of Salmon et al. (SC'11): a 4-word counter
+ * and a 2-word key; each of the 10 rounds multiplies words 0 and 2 by the two
+ * round multipliers, splits the 64-bit products into high and low halves, and
+ * mixes the high halves with the other two words and the round key; the key is
+ * advanced by the two Weyl constants between rounds. */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += PHILOX_W0;
+        k1 += PHILOX_W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* u = (2 m + 1) 2^-24 with m the top 23 bits of x: exactly representable in FP32
+ * and FP64, never 0 or 1. */
+double orc_uniform(uint32_t x)
+{
+    uint32_t m = x >> 9;
+    return (double)(2u * m + 1u) * (1.0 / 16777216.0);
+}
+
+/* Box-Muller (1958): z0 = sqrt(-2 ln u0) cos(2 pi u1), z1 = sqrt(-2 ln u0) sin(2 pi u1). */
+static void box_muller(double u0, double u1, double *z0, double *z1)
+{
+    const double two_pi = 6.283185307179586476925286766559;
+    double r = sqrt(-2.0 * log(u0));
+    *z0 = r * cos(two_pi * u1);
+    *z1 = r * sin(two_pi * u1);
+}
+
+void orc_normals4(const uint32_t ctr[4], const uint32_t key[2], double z[4])
+{
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    box_muller(orc_uniform(x[0]), orc_uniform(x[1]), &z[0], &z[1]);
+    box_muller(orc_uniform(x[2]), orc_uniform(x[3]), &z[2], &z[3]);
+}
+
+/* Stream layout: key = (seed low word, seed high word XOR arm id);
+ * counter = (index, patient, tag, sub-index). */
+#define TAG_PARAM 0u
+#define TAG_MEAL  1u
+#define TAG_DIFF  2u
+
+static void make_key(uint64_t seed, uint32_t arm, uint32_t key[2])
+{
+    key[0] = (uint32_t)(seed & 0xffffffffu);
+    key[1] = (uint32_t)(seed >> 32) ^ arm;
+}
+
+/* --------------------------------------------------------------- model ---- */
+/* Parameter order of a sampled vector. EGP0, F01, VI, VG are per kg of body weight. */
+enum { P_EGP0, P_F01, P_K12, P_KA1, P_KA2, P_KA3, P_SIT, P_SID, P_SIE, P_KE, P_VI, P_VG,
+       P_TMAXI, P_TMAXG, P_BW };
+/* State order. */
+enum { X_D1, X_D2, X_S1, X_S2, X_I, X_X1, X_X2, X_X3, X_Q1, X_Q2, X_GI };
+
+/* Hovorka core (glucose absorption, subcutaneous insulin, insulin action on
+ * transport, disposal and endogenous production, two glucose compartments) and
+ * the one-state sensor model of the extension in Sec. IV-B:
+ *   G = Q1/VG, U_G = D2/tmaxG, U_I = S2/tmaxI,
+ *   F01c = F01 min(1, G/4.5), F_R = 0.003 max(0, G - 9) VG,
+ *   dD1 = AG D - D1/tmaxG,         dD2 = (D1 - D2)/tmaxG,
+ *   dS1 = u - S1/tmaxI,            dS2 = (S1 - S2)/tmaxI,
+ *   dI  = U_I/VI - ke I,
+ *   dx_j = -ka_j x_j + ka_j S_j I  (S_1,S_2,S_3 = SIT, SID, SIE),
+ *   dQ1 = -F01c - x1 Q1 + k12 Q2 - F_R + U_G + EGP0 max(0, 1 - x3),
+ *   dQ2 = x1 Q1 - (k12 + x2) Q2,
+ *   dGI = (G - GI)/tau.
+ * Endogenous production is held at zero once insulin action x3 exceeds 1 (a
+ * negative hepatic output has no physical meaning). Units: min, mmol, mU, L;
+ * u in mU/min, D (ingested glucose) in mmol/min. */
+void orc_rhs(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_NX], double u, double d,
+             double dx[ORC_NX])
+{
+    double bw = p[P_BW];
+    double egp0 = p[P_EGP0] * bw, f01 = p[P_F01] * bw;
+    double vi = p[P_VI] * bw, vg = p[P_VG] * bw;
+    double k12 = p[P_K12], ke = p[P_KE];
+    double ka1 = p[P_KA1], ka2 = p[P_KA2], ka3 = p[P_KA3];
+    double sit = p[P_SIT], sid = p[P_SID], sie = p[P_SIE];
+    double tmaxi = p[P_TMAXI], tmaxg = p[P_TMAXG];
+
+    double G = x[X_Q1] / vg;
+    double ug = x[X_D2] / tmaxg;
+    double ui = x[X_S2] / tmaxi;
+    double f01c = f01 * fmin(1.0, G / 4.5);
+    double fr = (G > 9.0) ? 0.003 * (G - 9.0) * vg : 0.0;
+
+    dx[X_D1] = cfg->ag * d - x[X_D1] / tmaxg;
+    dx[X_D2] = (x[X_D1] - x[X_D2]) / tmaxg;
+    dx[X_S1] = u - x[X_S1] / tmaxi;
+    dx[X_S2] = (x[X_S1] - x[X_S2]) / tmaxi;
+    dx[X_I]  = ui / vi - ke * x[X_I];
+    dx[X_X1] = -ka1 * x[X_X1] + ka1 * sit * x[X_I];
+    dx[X_X2] = -ka2 * x[X_X2] + ka2 * sid * x[X_I];
+    dx[X_X3] = -ka3 * x[X_X3] + ka3 * sie * x[X_I];
+    dx[X_Q1] = -f01c - x[X_X1] * x[X_Q1] + k12 * x[X_Q2] - fr + ug + egp0 * fmax(0.0, 1.0 - x[X_X3]);
+    dx[X_Q2] = x[X_X1] * x[X_Q1] - (k12 + x[X_X2]) * x[X_Q2];
+    dx[X_GI] = (G - x[X_GI]) / cfg->tau_cgm;
+}
+
+/* Basal steady state at G* = g_target with D = 0 (and x3* < 1). Setting dQ1 = dQ2 = 0 and
+ * substituting the insulin steady state x_j = S_j I gives, after multiplying by
+ * (k12 + SID I), a I^2 + b I + c = 0 with
+ *   a = SID (SIT Q1* + EGP0 SIE), b = SID (F01c + F_R - EGP0) + EGP0 SIE k12,
+ *   c = k12 (F01c + F_R - EGP0),  Q1* = G* VG.
+ * With a > 0 there is one positive root iff c < 0. Then u_b = I* ke VI. */
+int orc_basal(const orc_config *cfg, const double p[ORC_NP], double *i_star, double *u_b, double x0[ORC_NX])
+{
+    double bw = p[P_BW];
+    double egp0 = p[P_EGP0] * bw, f01 = p[P_F01] * bw;
+    double vi = p[P_VI] * bw, vg = p[P_VG] * bw;
+    double k12 = p[P_K12];
+    double gs = cfg->g_target;
+    double q1 = gs * vg;
+    double f01c = f01 * fmin(1.0, gs / 4.5);
+    double fr = (gs > 9.0) ? 0.003 * (gs - 9.0) * vg : 0.0;
+    double a = p[P_SID] * (p[P_SIT] * q1 + egp0 * p[P_SIE]);
+    double b = p[P_SID] * (f01c + fr - egp0) + egp0 * p[P_SIE] * k12;
+    double c = k12 * (f01c + fr - egp0);
+    if (!(c < 0.0) || !(a > 0.0))
+        return 0;
+    double I = (-b + sqrt(b * b - 4.0 * a * c)) / (2.0 * a);
+    double ub = I * p[P_KE] * vi;
+    *i_star = I;
+    *u_b = ub;
+    if (x0) {
+        double x1 = p[P_SIT] * I, x2 = p[P_SID] * I, x3 = p[P_SIE] * I;
+        x0[X_D1] = 0.0;
+        x0[X_D2] = 0.0;
+        x0[X_S1] = ub * p[P_TMAXI];
+        x0[X_S2] = ub * p[P_TMAXI];
+        x0[X_I]  = I;
+        x0[X_X1] = x1;
+        x0[X_X2] = x2;
+        x0[X_X3] = x3;
+        x0[X_Q1] = q1;
+        x0[X_Q2] = q1 * x1 / (k12 + x2);
+        x0[X_GI] = gs;
+    }
+    return 1;
+}
+
+/* Population: independent lognormal draws with median = nominal and the given CV,
+ * p_j = nom_j exp(s z_j), s = sqrt(ln(1 + CV^2)); z_j is normal j of the four
+ * Philox calls with counter (j/4, patient, PARAM, attempt). An attempt is kept iff
+ * the basal steady state exists (and u_b >= 0.4 U/h when that flag is set, the
+ * rule of Sec. IV-B); up to 32 attempts, else the nominal vector with a status bit.
+ * out = [15 parameters, u_b, I*, attempts, status]. */
+#define MAX_ATTEMPTS 32
+static void sample_patient(const orc_config *cfg, uint32_t patient, double out[ORC_NPOUT])
+{
+    uint32_t key[2];
+    make_key(cfg->pop_seed, cfg->arm_id, key);
+    double s = sqrt(log(1.0 + cfg->cv * cfg->cv));
+    double p[ORC_NP], I = 0.0, ub = 0.0;
+    int attempt;
+    uint32_t status = 0;
+    for (attempt = 0; attempt < MAX_ATTEMPTS; ++attempt) {
+        double z[16];
+        for (uint32_t c = 0; c < 4; ++c) {
+            uint32_t ctr[4] = {c, patient, TAG_PARAM, (uint32_t)attempt};
+            orc_normals4(ctr, key, &z[4 * c]);
+        }
+        for (int j = 0; j < ORC_NP; ++j)
+            p[j] = cfg->nominal[j] * exp(s * z[j]);
+        if (!orc_basal(cfg, p, &I, &ub, NULL))
+            continue;
+        if ((cfg->pop_flags & ORC_POP_MIN_BASAL) && !(ub >= 400.0 / 60.0))
+            continue;
+        break;
+    }
+    if (attempt == MAX_ATTEMPTS) {
+        for (int j = 0; j < ORC_NP; ++j)
+            p[j] = cfg->nominal[j];
+        if (!orc_basal(cfg, p, &I, &ub, NULL)) {
+            I = 0.0;
+            ub = 0.0;
+        }
+        status |= ORC_ST_RESAMPLE;
+    }
+    for (int j = 0; j < ORC_NP; ++j)
+        out[j] = p[j];
+    out[15] = ub;
+    out[16] = I;
+    out[17] = (double)(attempt < MAX_ATTEMPTS ? attempt + 1 : MAX_ATTEMPTS);
+    out[18] = (double)status;
+}
+
+void orc_sample_population(const orc_config *cfg, int64_t first, int64_t count, double *out)
+{
+    for (int64_t j = 0; j < count; ++j)
+        sample_patient(cfg, (uint32_t)(first + j), out + j * ORC_NPOUT);
+}
+
+/* ------------------------------------------------------------- protocol ---- */
+/* One Philox call per (day, slot) with counter (day, patient, MEAL, slot):
+ *   carbs   = max(0, mean + sd z), z the cosine normal of (u0, u1);
+ *   jitter  = floor(u2 (2J + 1)) - J, evaluated exactly in integers;
+ *   present = u3 < prob.
+ * The meal is a glucose intake rate over the control interval that contains the
+ * onset minute (inputs are held constant between samples, eq. 2). */
+typedef struct { int32_t kd; double rate; double carbs; } meal_t;
+
+static void meal_draw(const orc_config *cfg, uint32_t patient, int32_t day, int m, const uint32_t key[2],
+                      int *present, int32_t *kd, double *carbs, int32_t *jit)
+{
+    uint32_t ctr[4] = {(uint32_t)day, patient, TAG_MEAL, (uint32_t)m};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    double z0, z1;
+    box_muller(orc_uniform(x[0]), orc_uniform(x[1]), &z0, &z1);
+    double c = cfg->carbs_mean[m] + cfg->carbs_sd[m] * z0;
+    *carbs = c < 0.0 ? 0.0 : c;
+    uint32_t odd = 2u * (x[2] >> 9) + 1u;
+    *jit = (int32_t)(((uint64_t)odd * (uint64_t)(2 * cfg->jitter + 1)) >> 24) - cfg->jitter;
+    *present = orc_uniform(x[3]) < cfg->prob[m];
+    *kd = (cfg->minute_of_day[m] + *jit) / cfg->ts_min;
+}
+
+static int meals_for_day(const orc_config *cfg, uint32_t patient, int32_t day, const uint32_t key[2],
+                         meal_t meals[ORC_MAX_SLOTS])
+{
+    int n = 0;
+    for (int m = 0; m < cfg->n_slots; ++m) {
+        int present;
+        int32_t kd, jit;
+        double carbs;
+        meal_draw(cfg, patient, day, m, key, &present, &kd, &carbs, &jit);
+        if (!present)
+            continue;
+        meals[n].kd = kd;
+        meals[n].carbs = carbs;
+        meals[n].rate = carbs * (1000.0 / 180.16) / (double)cfg->ts_min;
+        ++n;
+    }
+    return n;
+}
+
+/* Meal draws of one (patient, day), for tests: out [n_slots][4] = (present, sample
+ * index within the day, carbs in g, jitter in min); absent slots keep their draw. */
+void orc_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out)
+{
+    uint32_t key[2];
+    make_key(cfg->noise_seed, cfg->arm_id, key);
+    for (int m = 0; m < cfg->n_slots; ++m) {
+        int present;
+        int32_t kd, jit;
+        double carbs;
+        meal_draw(cfg, patient, day, m, key, &present, &kd, &carbs, &jit);
+        out[4 * m + 0] = present ? 1.0 : 0.0;
+        out[4 * m + 1] = (double)kd;
+        out[4 * m + 2] = carbs;
+        out[4 * m + 3] = (double)jit;
+    }
+}
+
+/* ---------------------------------------------------------- integrators ---- */
+/* One Euler-Maruyama step x <- x + h f + sqrt(h) sigma .* xi (drift evaluated at the
+ * pre-step state for every component). */
+static void em_step(int n, double *x, const double *f, double h, double sqrt_h, const double *sig,
+                    const double *xi)
+{
+    for (int i = 0; i < n; ++i)
+        x[i] = x[i] + h * f[i] + sqrt_h * sig[i] * xi[i];
+}
+
+static void rk4_step(const orc_config *cfg, const double p[ORC_NP], double x[ORC_NX], double u, double d,
+                     double h)
+{
+    double k1[ORC_NX], k2[ORC_NX], k3[ORC_NX], k4[ORC_NX], t[ORC_NX];
+    orc_rhs(cfg, p, x, u, d, k1);
+    for (int i = 0; i < ORC_NX; ++i) t[i] = x[i] + 0.5 * h * k1[i];
+    orc_rhs(cfg, p, t, u, d, k2);
+    for (int i = 0; i < ORC_NX; ++i) t[i] = x[i] + 0.5 * h * k2[i];
+    orc_rhs(cfg, p, t, u, d, k3);
+    for (int i = 0; i < ORC_NX; ++i) t[i] = x[i] + h * k3[i];
+    orc_rhs(cfg, p, t, u, d, k4);
+    for (int i = 0; i < ORC_NX; ++i)
+        x[i] = x[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+void orc_em_ou(double theta, double s, double x0, double h, int32_t n_steps, int64_t n_paths, uint64_t seed,
+               double *x_final)
+{
+    uint32_t key[2];
+    make_key(seed, 0u, key);
+    double sqrt_h = sqrt(h);
+    for (int64_t path = 0; path < n_paths; ++path) {
+        double x = x0;
+        for (int32_t n = 0; n < n_steps; ++n) {
+            uint32_t ctr[4] = {(uint32_t)n, (uint32_t)path, TAG_DIFF, 0u};
+            double z[4];
+            orc_normals4(ctr, key, z);
+            double f = -theta * x;
+            em_step(1, &x, &f, h, sqrt_h, &s, &z[0]);
+        }
+        x_final[path] = x;
+    }
+}
+
+/* --------------------------------------------------------------- metrics ---- */
+/* Ranges of Sec. IV-A, mmol/L: [0] < 3.0, [1] 3.0-3.9, [2] 3.9-10.0 (both ends in
+ * range), [3] 10.0-13.9, [4] > 13.9. The index is the number of edges passed, so a
+ * non-finite G lands in [0] (and raises a status bit). Events: a maximal run of at
+ * least 3 consecutive samples below 3.9, below 3.0, or above 13.9, counted once
+ * when the run reaches 3 samples. */
+static const double EDGE[4] = {3.0, 3.9, 10.0, 13.9};
+
+typedef struct {
+    int32_t bins[5], events[3], run[3];
+    double sum_g, min_g, sum_u;
+    int32_t argmin_k, n_near;
+    uint32_t status;
+    double ctrl_margin;
+} acc_t;
+
+static void acc_sample(acc_t *a, double G, int32_t k, double guard)
+{
+    int b = (G >= EDGE[0]) + (G >= EDGE[1]) + (G > EDGE[2]) + (G > EDGE[3]);
+    a->bins[b] += 1;
+    int cond[3] = {G < 3.9, G < 3.0, G > 13.9};
+    for (int e = 0; e < 3; ++e) {
+        if (cond[e]) {
+            a->run[e] += 1;
+            if (a->run[e] == 3)
+                a->events[e] += 1;
+        } else {
+            a->run[e] = 0;
+        }
+    }
+    a->sum_g += G;
+    if (G < a->min_g) {
+        a->min_g = G;
+        a->argmin_k = k;
+    }
+    for (int e = 0; e < 4; ++e)
+        if (fabs(G - EDGE[e]) <= guard * EDGE[e]) {
+            a->n_near += 1;
+            break;
+        }
+    if (!isfinite(G))
+        a->status |= ORC_ST_NONFINITE;
+    else if (G < 0.0)
+        a->status |= ORC_ST_NEGATIVE_Q1;
+}
+
+/* ------------------------------------------------------------ controller ---- */
+/* PID on the CGM value, gains scaled by the patient's basal rate:
+ *   e = y_k - ybar, u_unc = u_b + Kp e + Ki I_k + Kd (y_k - y_{k-1})/Ts (y_{-1} = y_0),
+ *   u_k = min(max(u_unc, 0), u_max),
+ *   I_{k+1} = I_k + e Ts only if 0 <= u_unc <= u_max (conditional integration).
+ * This is the kappa/lambda form of Sec. III-B with control state (I_k, y_{k-1}). */
+typedef struct { double integ, y_prev; int started; } pid_t_;
+
+static double pid_step(const orc_config *cfg, pid_t_ *c, double y, double ub, double *margin)
+{
+    double kp = cfg->kp * ub, ki = cfg->ki * ub, kd = cfg->kd * ub;
+    double umax = cfg->umax_rel * ub;
+    double ts = (double)cfg->ts_min;
+    if (!c->started) {
+        c->y_prev = y;
+        c->started = 1;
+    }
+    double e = y - cfg->setpoint;
+    double u_unc = ub + kp * e + ki * c->integ + kd * (y - c->y_prev) / ts;
+    double u = u_unc < 0.0 ? 0.0 : u_unc;
+    if (u > umax)
+        u = umax;
+    if (u_unc >= 0.0 && u_unc <= umax)
+        c->integ += e * ts;
+    c->y_prev = y;
+    double m = fmin(fabs(u_unc), fabs(u_unc - umax)) / ub;
+    if (m < *margin)
+        *margin = m;
+    return u;
+}
+
+/* Scripted PID run for tests: u[k] for the measurement sequence y[0..n-1]. */
+void orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *y, double *u, double *integ)
+{
+    pid_t_ c = {0.0, 0.0, 0};
+    double margin = INFINITY;
+    for (int32_t k = 0; k < n; ++k) {
+        u[k] = pid_step(cfg, &c, y[k], ub, &margin);
+        if (integ)
+            integ[k] = c.integ;
+    }
+}
+
+/* ------------------------------------------------------------ main loop ---- */
+static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient, const orc_outputs *out)
+{
+    double prm[ORC_NPOUT];
+    sample_patient(cfg, patient, prm);
+    const double *p = prm;
+    double ub = prm[15], istar, ub2;
+    double x[ORC_NX];
+    acc_t a;
+    memset(&a, 0, sizeof a);
+    a.min_g = INFINITY;
+    a.argmin_k = -1;
+    a.ctrl_margin = INFINITY;
+    a.status = (uint32_t)prm[18];
+    if (!orc_basal(cfg, p, &istar, &ub2, x)) {
+        for (int i = 0; i < ORC_NX; ++i) x[i] = NAN;
+        ub = 0.0;
+    }
+    for (int i = 0; i < ORC_NX; ++i)
+        x[i] += cfg->x0_offset[i];
+
+    uint32_t nkey[2];
+    make_key(cfg->noise_seed, cfg->arm_id, nkey);
+    const int M = cfg->em_per_ctrl;
+    const int32_t ts = cfg->ts_min;
+    const int32_t kday = 1440 / ts;
+    const int64_t K = (int64_t)cfg->n_days * kday;
+    const double h = (double)ts / (double)M;
+    const double sqrt_h = sqrt(h);
+    const double sqrt_r = sqrt(cfg->cgm_var);
+    const int noisy = (cfg->sigma_q1 != 0.0) || (cfg->cgm_var != 0.0);
+    double sig[ORC_NX] = {0};
+    sig[X_Q1] = cfg->sigma_q1;
+    const double vg = p[P_VG] * p[P_BW];
+    pid_t_ pid = {0.0, 0.0, 0};
+    int is_traj = j < out->n_traj;
+
+    for (int32_t day = 0; day < cfg->n_days; ++day) {
+        meal_t meals[ORC_MAX_SLOTS];
+        int nm = meals_for_day(cfg, patient, day, nkey, meals);
+        for (int32_t kd = 0; kd < kday; ++kd) {
+            int64_t k = (int64_t)day * kday + kd;
+            double G = x[X_Q1] / vg;
+            acc_sample(&a, G, (int32_t)k, cfg->guard_rel);
+
+            /* normals of this sample: call c has counter (k, patient, DIFF, c);
+               xi_j = normal j (j < M), v_k = normal M */
+            double z[64] = {0};
+            if (noisy) {
+                int ncall = (M + 1 + 3) / 4;
+                for (int c = 0; c < ncall; ++c) {
+                    uint32_t ctr[4] = {(uint32_t)k, patient, TAG_DIFF, (uint32_t)c};
+                    orc_normals4(ctr, nkey, &z[4 * c]);
+                }
+            }
+            double y = x[X_GI] + sqrt_r * z[M];
+
+            double u;
+            if (cfg->ctrl_kind == ORC_CTRL_PID)
+                u = pid_step(cfg, &pid, y, ub, &a.ctrl_margin);
+            else
+                u = cfg->u_rel * ub;
+
+            double d = 0.0;
+            for (int m = 0; m < nm; ++m)
+                if (meals[m].kd == kd)
+                    d += meals[m].rate;
+
+            if (is_traj) {
+                if (out->traj_g) out->traj_g[j * K + k] = G;
+                if (out->traj_y) out->traj_y[j * K + k] = y;
+                if (out->traj_u) out->traj_u[j * K + k] = u;
+                if (out->traj_x)
+                    for (int i = 0; i < ORC_NX; ++i) out->traj_x[(j * K + k) * ORC_NX + i] = x[i];
+            }
+
+            if (cfg->integrator == ORC_INT_RK4) {
+                double hr = (double)ts / (double)cfg->rk4_sub;
+                for (int s = 0; s < cfg->rk4_sub; ++s)
+                    rk4_step(cfg, p, x, u, d, hr);
+            } else {
+                for (int s = 0; s < M; ++s) {
+                    double f[ORC_NX], xi[ORC_NX] = {0};
+                    orc_rhs(cfg, p, x, u, d, f);
+                    xi[X_Q1] = z[s];
+                    em_step(ORC_NX, x, f, h, sqrt_h, sig, xi);
+                }
+            }
+            a.sum_u += u * (double)ts;
+        }
+        for (int i = 0; i < ORC_NX; ++i)
+            if (!isfinite(x[i]))
+                a.status |= ORC_ST_NONFINITE;
+    }
+
+    for (int b = 0; b < 5; ++b) out->bins[j * 5 + b] = a.bins[b];
+    for (int e = 0; e < 3; ++e) out->events[j * 3 + e] = a.events[e];
+    out->sum_g[j] = a.sum_g;
+    out->min_g[j] = a.min_g;
+    out->argmin_k[j] = a.argmin_k;
+    out->sum_u[j] = a.sum_u;
+    out->status[j] = a.status;
+    if (out->n_near) out->n_near[j] = a.n_near;
+    if (out->ctrl_margin) out->ctrl_margin[j] = a.ctrl_margin;
+    if (out->params)
+        for (int i = 0; i < ORC_NPOUT; ++i) out->params[j * ORC_NPOUT + i] = prm[i];
+}
+
+typedef struct {
+    const orc_config *cfg;
+    const orc_outputs *out;
+    int64_t first, count;
+    int tid, nthreads;
+} job_t;
+
+static void *worker(void *arg)
+{
+    job_t *jb = (job_t *)arg;
+    for (int64_t j = jb->tid; j < jb->count; j += jb->nthreads)
+        simulate_patient(jb->cfg, j, (uint32_t)(jb->first + j), jb->out);
+    return NULL;
+}
+
+int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out)
+{
+    if (cfg->ts_min <= 0 || 1440 % cfg->ts_min != 0 || cfg->em_per_ctrl < 1 || cfg->em_per_ctrl > 63)
+        return -1;
+    if (cfg->n_slots < 0 || cfg->n_slots > ORC_MAX_SLOTS || cfg->n_days < 0 || count < 0)
+        return -1;
+    for (int m = 0; m < cfg->n_slots; ++m)
+        if (cfg->minute_of_day[m] - cfg->jitter < 0 || cfg->minute_of_day[m] + cfg->jitter >= 1440)
+            return -1;
+    if (cfg->integrator == ORC_INT_RK4 && (cfg->sigma_q1 != 0.0 || cfg->cgm_var != 0.0 || cfg->rk4_sub < 1))
+        return -1;
+    if (n_threads < 1)
+        n_threads = 1;
+    if (n_threads > 256)
+        n_threads = 256;
+    pthread_t th[256];
+    job_t jobs[256];
+    for (int t = 0; t < n_threads; ++t) {
+        jobs[t].cfg = cfg;
+        jobs[t].out = out;
+        jobs[t].first = first;
+        jobs[t].count = count;
+        jobs[t].tid = t;
+        jobs[t].nthreads = n_threads;
+    }
+    if (n_threads == 1) {
+        worker(&jobs[0]);
+        return 0;
+    }
+    for (int t = 0; t < n_threads; ++t)
+        pthread_create(&th[t], NULL, worker, &jobs[t]);
+    for (int t = 0; t < n_threads; ++t)
+        pthread_join(th[t], NULL);
+    return 0;
+}
+
+/* ------------------------------------------------------------ reduction ---- */
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Population summary. Quantile p (percent) is the nearest rank: the value at
+ * position ceil(p n / 100) of the sorted per-patient in-range counts. The worst
+ * patient is the lexicographic minimum of (min G, patient index). */
+void orc_reduce(int64_t n, int64_t k, const int32_t *bins, const int32_t *events, const double *sum_g,
+                const double *min_g, const int32_t *argmin_k, const uint32_t *status, orc_summary *s)
+{
+    memset(s, 0, sizeof *s);
+    s->n = n;
+    s->k = k;
+    s->worst_patient = -1;
+    s->worst_min_g = INFINITY;
+    double total_g = 0.0;
+    int32_t *tir = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int b = 0; b < 5; ++b) s->bins[b] += (uint64_t)bins[i * 5 + b];
+        for (int e = 0; e < 3; ++e) s->events[e] += (uint64_t)events[i * 3 + e];
+        total_g += sum_g[i];
+        tir[i] = bins[i * 5 + 2];
+        if (min_g[i] < s->worst_min_g) {
+            s->worst_min_g = min_g[i];
+            s->worst_patient = i;
+            s->worst_k = argmin_k[i];
+        }
+        for (int t = 0; t < 3; ++t)
+            if (status[i] & (1u << t)) s->status_count[t] += 1;
+    }
+    qsort(tir, (size_t)n, sizeof(int32_t), cmp_i32);
+    static const int64_t pct[5] = {5, 25, 50, 75, 95};
+    for (int q = 0; q < 5; ++q) {
+        int64_t r = (pct[q] * n + 99) / 100;
+        s->q_count[q] = n > 0 ? tir[r - 1] : 0;
+    }
+    s->mean_tir = (n > 0 && k > 0) ? (double)s->bins[2] / ((double)n * (double)k) : 0.0;
+    s->mean_bg = (n > 0 && k > 0) ? total_g / ((double)n * (double)k) : 0.0;
+    free(tir);
+}

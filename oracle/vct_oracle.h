@@ -1,0 +1,149 @@
+/*
+ * vct_oracle.h -- plain FP64 CPU oracle for closed-loop virtual clinical trials.
+ *
+ * TEST INFRASTRUCTURE. Only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark may load this library. The GPU product path never calls it,
+ * shares no source with it, and must fail if its own HIP library is missing.
+ *
+ * What it computes (paper: "High-performance Uncertainty Quantification in
+ * Large-scale Virtual Clinical Trials of Closed-loop Diabetes Treatment"):
+ *   - the stochastic patient model in the general SDE form of Sec. III-A, eq. (1):
+ *     x(t0)=x0, dx = f dt + sigma dw, z = h(x), y_k = g(x(t_k)) + v_k,
+ *     dw ~ N(0, I dt), v_k ~ N(0, R), with inputs held constant between samples (eq. 2);
+ *     f is the Hovorka core model extended with a one-state CGM model (Sec. IV-B);
+ *   - a discrete-time controller in the kappa/lambda form of Sec. III-B (eq. 3);
+ *   - the five glucose ranges of Sec. IV-A accumulated on the fly, one simulation at a
+ *     time, as the low-memory scheme of Sec. III-C does;
+ *   - closed-loop Monte Carlo over independent patients (Sec. III, III-C).
+ * Everything is FP64, written step by step in the order the method defines.
+ */
+#ifndef VCT_ORACLE_H
+#define VCT_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_NP 15          /* sampled patient parameters                       */
+#define ORC_NX 11          /* model states                                     */
+#define ORC_NPOUT 19       /* 15 parameters + u_b, I*, attempts, status        */
+#define ORC_MAX_SLOTS 4
+
+/* controller kinds */
+#define ORC_CTRL_OPEN 0    /* constant u = u_rel * u_b (test mode)              */
+#define ORC_CTRL_PID  1
+#define ORC_CTRL_MPC  2
+#define ORC_CTRL_MLP  3
+
+/* integrators */
+#define ORC_INT_EM  0      /* Euler-Maruyama with em_per_ctrl substeps          */
+#define ORC_INT_RK4 1      /* classical RK4, rk4_sub substeps per sample; noise must be off */
+
+/* status bits per patient */
+#define ORC_ST_NONFINITE   1u
+#define ORC_ST_NEGATIVE_Q1 2u
+#define ORC_ST_RESAMPLE    4u
+
+/* population flag */
+#define ORC_POP_MIN_BASAL 1u   /* additionally require u_b >= 0.4 U/h (6.6667 mU/min) */
+
+typedef struct {
+    /* (1)+(4) population and parameter values */
+    uint64_t pop_seed;
+    uint32_t arm_id;
+    uint32_t pop_flags;
+    double   nominal[ORC_NP];   /* EGP0 F01 k12 ka1 ka2 ka3 SIT SID SIE ke VI VG tmaxI tmaxG BW */
+    double   cv;                /* coefficient of variation of the lognormal draws          */
+    double   ag;                /* carbohydrate bioavailability (shared by all patients)    */
+    double   tau_cgm;           /* sensor lag time constant, min (shared)                    */
+    double   g_target;          /* glucose level of the basal steady state, mmol/L          */
+    /* (2) protocol: meal slots, one draw per (day, slot) */
+    int32_t  n_slots;
+    int32_t  minute_of_day[ORC_MAX_SLOTS];
+    double   carbs_mean[ORC_MAX_SLOTS];
+    double   carbs_sd[ORC_MAX_SLOTS];
+    double   prob[ORC_MAX_SLOTS];
+    int32_t  jitter;            /* onset jitter uniform on the integers [-jitter, jitter] min */
+    /* (5) controller */
+    int32_t  ctrl_kind;
+    double   setpoint;          /* mmol/L */
+    double   kp, ki, kd;        /* relative to u_b: u_b/(mmol/L), u_b/(mmol/L min), u_b min/(mmol/L) */
+    double   umax_rel;          /* u_max = umax_rel * u_b */
+    double   u_rel;             /* open-loop mode: u = u_rel * u_b */
+    /* (3) model + simulation settings */
+    int32_t  n_days;
+    int32_t  em_per_ctrl;       /* EM substeps per control interval */
+    int32_t  ts_min;            /* control interval, integer minutes dividing 1440 */
+    double   sigma_q1;          /* diffusion on Q1, mmol min^-1/2 */
+    double   cgm_var;           /* R, (mmol/L)^2 */
+    uint64_t noise_seed;
+    int32_t  integrator;        /* ORC_INT_EM / ORC_INT_RK4 */
+    int32_t  rk4_sub;
+    double   x0_offset[ORC_NX]; /* added to the basal steady state (tests only) */
+    double   guard_rel;         /* band used for the near-decision diagnostics */
+} orc_config;
+
+typedef struct {
+    int32_t  *bins;        /* [count][5] samples per glucose range          */
+    int32_t  *events;      /* [count][3] runs >= 3 samples: <3.9, <3.0, >13.9 */
+    double   *sum_g;       /* [count] sum of G over samples, mmol/L          */
+    double   *min_g;       /* [count]                                         */
+    int32_t  *argmin_k;    /* [count] first sample index of min_g            */
+    double   *sum_u;       /* [count] delivered insulin, mU                   */
+    uint32_t *status;      /* [count]                                         */
+    int32_t  *n_near;      /* [count] samples within guard_rel of a range edge */
+    double   *ctrl_margin; /* [count] min |u_unc|/u_b, |u_unc-u_max|/u_b over samples */
+    double   *params;      /* [count][ORC_NPOUT] or NULL                      */
+    int32_t   n_traj;      /* trajectories for the first n_traj patients      */
+    double   *traj_g, *traj_y, *traj_u;   /* [n_traj][K] (any may be NULL)   */
+    double   *traj_x;      /* [n_traj][K][ORC_NX] state at each sample or NULL */
+} orc_outputs;
+
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
+void     orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Uniform on (0,1): odd multiples of 2^-24 built from the top 23 bits. */
+double   orc_uniform(uint32_t x);
+/* Four normals of one Philox call, Box-Muller pairs (u0,u1) and (u2,u3). */
+void     orc_normals4(const uint32_t ctr[4], const uint32_t key[2], double z[4]);
+
+/* Population: sampled parameters of patients [first, first+count). out: [count][ORC_NPOUT]. */
+void     orc_sample_population(const orc_config *cfg, int64_t first, int64_t count, double *out);
+/* Basal steady state for one parameter vector (absolute units built inside). Returns 1 if feasible. */
+int      orc_basal(const orc_config *cfg, const double p[ORC_NP], double *i_star, double *u_b, double x0[ORC_NX]);
+/* Drift f(x, u, D) of the patient model for parameter vector p (per-kg units as sampled). */
+void     orc_rhs(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_NX], double u, double d, double dx[ORC_NX]);
+
+/* Test hooks: the meal draws of one (patient, day) -> [n_slots][4] = (present, sample index
+   in the day, carbs g, jitter min); a PID run over a scripted measurement sequence. */
+void     orc_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out);
+void     orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *y, double *u, double *integ);
+
+/* Closed-loop Monte Carlo for patients [first, first+count) on n_threads threads. */
+int      orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out);
+
+/* Generic Euler-Maruyama on the Ornstein-Uhlenbeck SDE dX = -theta X dt + s dW, X(0)=x0,
+   path p uses the same Philox stream layout (counter (n, p, 2, 0), normal #0). Writes X_n. */
+void     orc_em_ou(double theta, double s, double x0, double h, int32_t n_steps, int64_t n_paths,
+                   uint64_t seed, double *x_final);
+
+/* Population summary: exact integer totals, nearest-rank quantiles of per-patient in-range counts. */
+typedef struct {
+    int64_t  n, k;
+    uint64_t bins[5];
+    uint64_t events[3];
+    int64_t  q_count[5];          /* 5/25/50/75/95 % nearest rank, in samples */
+    double   mean_tir;            /* bins[2] / (n k) */
+    double   mean_bg;             /* sum of sum_g / (n k) */
+    int64_t  worst_patient;       /* lexicographic min (min_g, patient) */
+    double   worst_min_g;
+    int32_t  worst_k;
+    int64_t  status_count[3];
+} orc_summary;
+void     orc_reduce(int64_t n, int64_t k, const int32_t *bins, const int32_t *events, const double *sum_g,
+                    const double *min_g, const int32_t *argmin_k, const uint32_t *status, orc_summary *s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,108 @@
+"""Seeded synthetic trial descriptions (inputs only, no model arithmetic).
+
+A trial is a flat dict of plain numbers that both the GPU library and the CPU
+oracle take as input: population size and seeds, the nominal parameter vector,
+the meal protocol, the controller settings and the simulation settings. The five
+named workloads mirror the configurations the project is measured on; every
+value the paper leaves open is a stated reading (see the model notes in the
+repository's design document).
+
+The paper's trial is (1) a population, (2) a protocol, (3) a model, (4)
+parameter values and (5) one or more controllers (Sec. II). The fields below are
+grouped the same way.
+"""
+from __future__ import annotations
+
+import copy
+
+# Hovorka core parameters, in the order both implementations use.
+# EGP0, F01 (mmol/kg/min) and VI, VG (L/kg) are per kg of body weight.
+PARAM_NAMES = ("EGP0", "F01", "k12", "ka1", "ka2", "ka3", "SIT", "SID", "SIE",
+               "ke", "VI", "VG", "tmaxI", "tmaxG", "BW")
+NOMINAL = (0.0161, 0.0097, 0.066, 0.006, 0.06, 0.03, 51.2e-4, 8.2e-4, 520e-4,
+           0.138, 0.12, 0.16, 55.0, 40.0, 70.0)
+
+# State order of the model (documentation for users of trajectory dumps).
+STATE_NAMES = ("D1", "D2", "S1", "S2", "I", "x1", "x2", "x3", "Q1", "Q2", "GI")
+
+CTRL_OPEN, CTRL_PID, CTRL_MPC, CTRL_MLP = 0, 1, 2, 3
+FP64, FP32 = 0, 1
+
+MG_PER_DL_PER_MMOL = 18.0
+
+
+def base_trial() -> dict:
+    """1,000 patients x 7 days, three meals, PID, FP64 -- the small parity case."""
+    return {
+        # (1) population + (4) parameter values
+        "n_patients": 1000,
+        "pop_seed": 0,
+        "arm_id": 0,
+        "pop_flags": 0,
+        "nominal": list(NOMINAL),
+        "cv": 0.20,
+        "ag": 0.8,
+        "tau_cgm": 10.0,
+        "g_target": 6.0,
+        # (2) protocol: 07:00 / 12:00 / 18:00, N(50, 10) g clipped at 0, jitter +-30 min
+        "n_slots": 3,
+        "minute_of_day": [420, 720, 1080, 1260],
+        "carbs_mean": [50.0, 50.0, 50.0, 20.0],
+        "carbs_sd": [10.0, 10.0, 10.0, 5.0],
+        "prob": [1.0, 1.0, 1.0, 0.0],
+        "jitter": 30,
+        # (5) controller: PID on CGM, gains relative to the basal rate
+        "ctrl_kind": CTRL_PID,
+        "setpoint": 6.0,
+        "kp": 0.5,
+        "ki": 0.5 / 600.0,
+        "kd": 30.0,
+        "umax_rel": 3.0,
+        "u_rel": 1.0,
+        # (3) model + simulation settings
+        "n_days": 7,
+        "em_per_ctrl": 5,
+        "ts_min": 5,
+        "sigma_q1": 1.0,
+        "cgm_var": 2.0 / MG_PER_DL_PER_MMOL ** 2,
+        "noise_seed": 0,
+        "precision": FP64,
+    }
+
+
+def with_(trial: dict, **kw) -> dict:
+    t = copy.deepcopy(trial)
+    for k, v in kw.items():
+        if k not in t:
+            raise KeyError(k)
+        t[k] = v
+    return t
+
+
+def noise_free(trial: dict) -> dict:
+    """The ODE special case (sigma = 0) with a noise-free sensor."""
+    return with_(trial, sigma_q1=0.0, cgm_var=0.0)
+
+
+def c1_fp64_pid() -> dict:
+    """1,000 patients x 7 days, FP64 state, seed 0."""
+    return base_trial()
+
+
+def c2_fp32_pid() -> dict:
+    """100,000 patients x 28 days, FP32 state / FP64 accumulators, seed 1."""
+    return with_(base_trial(), n_patients=100_000, n_days=28, pop_seed=1, noise_seed=1, precision=FP32)
+
+
+def c3_paper_scale() -> dict:
+    """1,000,000 patients x 364 days, plus a 21:00 snack with probability 0.2, N(20, 5) g."""
+    return with_(base_trial(), n_patients=1_000_000, n_days=364, pop_seed=2, noise_seed=2, precision=FP32,
+                 n_slots=4, prob=[1.0, 1.0, 1.0, 0.2])
+
+
+def days_patients(trial: dict) -> int:
+    return int(trial["n_patients"]) * int(trial["n_days"])
+
+
+def samples_per_day(trial: dict) -> int:
+    return 1440 // int(trial["ts_min"])
