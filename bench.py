@@ -1,0 +1,141 @@
+"""Benchmark: patient-days simulated per second on one MI355X.
+
+A step is one pass of the whole hot path over the paper-scale trial (1,000,000
+virtual patients x 364 days, PID every 5 min, EM step 1 min, FP32 state / FP64
+metric accumulators, three meals + an evening snack with probability 0.2):
+population creation -> closed-loop simulation -> population reduction, all in the
+HIP library through its C ABI, inputs synthetic and already resident.
+
+The JSON line also carries
+* roofline -- the simulation kernel's algorithmic FP32 FLOP (104,256 per patient-day)
+  over its own average launch time (HIP events on its stream) against the 157.3
+  TFLOP/s FP32 vector peak;
+* cpu_baseline -- the FP64 oracle on a bounded sample of the same trial, timed on
+  this host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+FLOP_PER_PATIENT_DAY = 1440 * 64 + 288 * (6 * 4.5 + 15)   # EM steps + normals + sensor/PID
+PEAK_FP32 = 157.3e12
+PEAK_FP32_NONPACKED = 78.6e12
+ORACLE_SAMPLE = (4000, 364)   # patients 0..3999 of the same trial, full horizon
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(trial: dict) -> dict:
+    from oracle import oracle
+    from paper_2202_13927_amd import workloads as W
+    n, d = ORACLE_SAMPLE
+    threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    t = W.with_(trial, n_patients=n, n_days=d)
+    t0 = time.perf_counter()
+    oracle.simulate(t, 0, n, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": n * d / dt, "unit": "patient-days/s", "cores": threads, "kind": "oracle",
+            "sample": f"patients 0..{n - 1} of the trial, full {d}-day horizon, FP64 oracle ({dt:.1f} s)"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--patients", type=int, default=None, help="override the population size")
+    ap.add_argument("--days", type=int, default=None, help="override the horizon")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
+              "the multi-GPU sharding is a design note only", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_2202_13927_amd import trial as T, vct, workloads as W
+
+    trial = W.c3_paper_scale()
+    if args.patients:
+        trial = W.with_(trial, n_patients=args.patients)
+    if args.days:
+        trial = W.with_(trial, n_days=args.days)
+    n, days = trial["n_patients"], trial["n_days"]
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    bufs = T.TrialBuffers(trial, dev)
+    sim_ms = []
+
+    def step():
+        pop = T.create_population(trial, bufs, stream)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        T.simulate(trial, pop, bufs, stream)
+        e1.record(stream)
+        s = T.read_metrics(bufs, stream)     # synchronises the stream
+        vct.vct_destroy_population(pop)
+        sim_ms.append(e0.elapsed_time(e1))
+        return s
+
+    log(f"[bench] trial {n} patients x {days} days, warmup {args.warmup}, steps {args.steps}")
+    for i in range(args.warmup):
+        s = step()
+        log(f"[bench] warmup {i}: simulate {sim_ms[-1]:.1f} ms, mean TIR {s['mean_tir']:.4f}")
+    sim_ms.clear()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        s = step()
+        log(f"[bench] step {i}: simulate {sim_ms[-1]:.1f} ms")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    pdays = n * days
+    value = pdays * args.steps / dt
+    kern_s = sum(sim_ms) / len(sim_ms) / 1e3
+    achieved = FLOP_PER_PATIENT_DAY * pdays / kern_s
+    out = {
+        "metric": "patient-days simulated/s (1 GPU)",
+        "value": value,
+        "unit": "patient-days/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic (seeded lognormal population, Philox noise and meals)",
+        "config": {"workload": f"paper-scale PID trial: {n} patients x {days} days, EM 1 min, PID 5 min, "
+                               "FP32 state / FP64 metrics, 3 meals + 20% snack", "patients": n, "days": days,
+                   "parallelism": "one patient per lane, 1 GPU"},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "kernel": "simulate_kernel<float, PID, noisy>", "kernel_ms": kern_s * 1e3,
+                     "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
+                     "flop_per_patient_day": FLOP_PER_PATIENT_DAY},
+        "summary": {"mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"], "mean_bg_mmol": s["mean_bg"],
+                    "worst_min_g": s["worst_min_g"], "status_count": s["status_count"]},
+        "paper_context": {"patient_days_per_s": 3.64e8 / 4920.0,
+                          "note": "1M patients x 52 weeks in 1 h 22 min on 2x EPYC 7542, dual-hormone AP, 30 s step"},
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] timing the FP64 oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline(trial)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

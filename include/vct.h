@@ -1,0 +1,186 @@
+/*
+ * vct.h -- C ABI of the MI355X (gfx950) closed-loop virtual clinical trial library.
+ *
+ * The arguments follow the paper's statement of a virtual trial (Sec. II): (1) a
+ * population of patients, (2) a protocol of disturbances, (3) a patient model,
+ * (4) values of the model parameters and (5) a controller ("artificial pancreas").
+ * The patient model is the SDE of Sec. III-A, eq. (1), with inputs held constant
+ * between sampling instants (eq. 2); the controller has the sampled form of
+ * Sec. III-B, eq. (3); the indicators are the five glucose ranges of Sec. IV-A,
+ * accumulated while each simulation runs and reduced over the population as in the
+ * low-memory scheme of Sec. III-C.
+ *
+ * Conventions (all entry points):
+ *  - Every device buffer is owned by the caller (allocated e.g. with torch) and
+ *    only borrowed for the duration of the call or of the handle that names it.
+ *    The library never frees caller memory.
+ *  - Descriptors are read during the call and not retained.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    vct_create_population and vct_simulate are asynchronous on it;
+ *    vct_read_metrics synchronises it before returning.
+ *  - Argument errors return VCT_EINVAL before any device work is queued.
+ *    A HIP runtime failure returns VCT_EHIP. vct_last_error() then holds a message.
+ *  - Numerical trouble inside a simulation (non-finite state, negative Q1,
+ *    exhausted parameter resampling) is reported per patient in the `status`
+ *    metric and counted in vct_summary; it is not a return code.
+ *  - No entry point is thread-safe with respect to the same handle.
+ */
+#ifndef VCT_H
+#define VCT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VCT_ABI_VERSION 1
+#define VCT_NP 15          /* sampled parameters per patient                         */
+#define VCT_NX 11          /* model states per patient                               */
+#define VCT_NPARAM_ROWS 19 /* rows of the population buffer: 15 parameters, u_b, I*, attempts, status */
+#define VCT_MAX_SLOTS 4    /* meal slots per day                                     */
+
+typedef enum {
+    VCT_OK = 0,
+    VCT_EINVAL = -1,   /* invalid argument                                   */
+    VCT_ENOMEM = -2,   /* the library could not allocate its own scratch     */
+    VCT_EHIP = -3,     /* a HIP runtime call failed                          */
+    VCT_ESTATE = -4,   /* handle in the wrong state                          */
+    VCT_ENOTSUP = -5   /* valid but not supported by this build              */
+} vct_status;
+
+/* Controllers (Sec. III-B): constant open-loop rate (tests), PID, linear MPC, learned MLP. */
+enum { VCT_CTRL_OPEN = 0, VCT_CTRL_PID = 1, VCT_CTRL_MPC = 2, VCT_CTRL_MLP = 3 };
+/* Working precision of the patient state; accumulators are always FP64. */
+enum { VCT_FP64 = 0, VCT_FP32 = 1 };
+/* Population flags. */
+enum { VCT_POP_MIN_BASAL = 1 };   /* also require u_b >= 0.4 U/h (Sec. IV-B) */
+
+/*
+ * (1) population + (4) parameter values -- Sec. II-A, Sec. IV-B.
+ * Parameter order (model units; EGP0, F01 per kg, VI, VG in L/kg):
+ *   EGP0 F01 k12 ka1 ka2 ka3 SIT SID SIE ke VI VG tmaxI tmaxG BW.
+ * Each patient's vector is drawn lognormal with median `nominal` and coefficient
+ * of variation `cv`; a draw is kept iff the basal steady state at `g_target`
+ * exists (and, with VCT_POP_MIN_BASAL, its rate is >= 0.4 U/h); up to 32 draws,
+ * then the nominal vector with a status bit. Random numbers: Philox4x32-10 with
+ * key (seed low word, seed high word ^ arm_id), counter (j/4, patient, 0, attempt).
+ */
+typedef struct {
+    int64_t  n_patients;       /* >= 1, < 2^31                                       */
+    uint64_t seed;
+    uint32_t arm_id;
+    uint32_t flags;            /* VCT_POP_*                                            */
+    double   nominal[VCT_NP];  /* all > 0                                              */
+    double   cv;               /* >= 0                                                 */
+    double   ag;               /* carbohydrate bioavailability, shared, in (0, 1]      */
+    double   tau_cgm;          /* sensor time constant, min, shared, > 0               */
+    double   g_target;         /* basal steady-state glucose, mmol/L, > 0              */
+} vct_population_desc;
+
+/* (2) protocol -- Sec. II-B: disturbances with type, size and time. Each day and slot
+ * draws one Philox block (counter (day, patient, 1, slot), simulation key):
+ * carbs = max(0, mean + sd z), onset = minute_of_day + jitter with jitter uniform on
+ * the integers [-jitter_min, jitter_min], present with probability prob. The meal is
+ * a constant glucose intake over the sampling interval that contains the onset.
+ * Slots must be in increasing time order, non-overlapping after jitter. */
+typedef struct {
+    int32_t n_slots;                        /* 0..VCT_MAX_SLOTS                    */
+    int32_t minute_of_day[VCT_MAX_SLOTS];
+    double  carbs_mean_g[VCT_MAX_SLOTS];
+    double  carbs_sd_g[VCT_MAX_SLOTS];
+    double  prob[VCT_MAX_SLOTS];            /* in [0, 1]                           */
+    int32_t jitter_min;                     /* 0..120                              */
+} vct_protocol;
+
+/* (5) controller -- Sec. III-B. PID on the sensor value y_k, gains relative to the
+ * patient's basal rate u_b:
+ *   u_k = clamp(u_b + kp u_b e + ki u_b I_k + kd u_b (y_k - y_{k-1})/Ts, 0, umax_rel u_b),
+ *   e = y_k - setpoint, I_{k+1} = I_k + e Ts only while the unclamped value is in range. */
+typedef struct {
+    int32_t kind;          /* VCT_CTRL_*                                           */
+    double  setpoint;      /* mmol/L                                               */
+    double  kp, ki, kd;    /* u_b/(mmol/L), u_b/(mmol/L min), u_b min/(mmol/L)     */
+    double  umax_rel;      /* > 0                                                  */
+    double  u_rel;         /* open-loop mode: u = u_rel u_b                        */
+} vct_controller;
+
+/* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl
+ * steps of ts_min/em_per_ctrl minutes per sampling interval; diffusion sigma_q1 on
+ * Q1 only; sensor noise variance cgm_var. Noise: per sample k the Philox blocks
+ * (k, patient, 2, 0) and (k, patient, 2, 1) give the EM normals xi_0..xi_4 and the
+ * sensor normal v_k (normals #0..#4 and #5 of the 8).
+ *
+ * metrics_dev: caller buffer of vct_metrics_bytes(n) bytes, per-patient SoA:
+ *   double sum_g[n]   sum of G over the K samples (mmol/L)
+ *   double min_g[n]   minimum sampled G
+ *   double sum_u[n]   delivered insulin over the horizon (mU)
+ *   int32  bins[5][n] samples per range: <3.0, 3.0-3.9, 3.9-10.0, 10.0-13.9, >13.9 mmol/L
+ *                     (3.9 and 10.0 count as in range)
+ *   int32  events[3][n] runs of >= 3 consecutive samples <3.9, <3.0, >13.9
+ *   int32  argmin_k[n] first sample index of min_g
+ *   uint32 status[n]  bit0 non-finite state, bit1 negative Q1, bit2 resampling exhausted
+ * traj_dev (optional, NULL = off): double [3][traj_patients][K] = G, y, u of the
+ *   first traj_patients patients at every sample, K = n_days * 1440 / ts_min. */
+typedef struct {
+    int32_t  n_days;          /* >= 1                                               */
+    int32_t  em_per_ctrl;     /* 5 (the supported EM substep count)                 */
+    int32_t  ts_min;          /* 5                                                  */
+    int32_t  precision;       /* VCT_FP64 | VCT_FP32                               */
+    double   sigma_q1;        /* mmol min^-1/2, >= 0                                */
+    double   cgm_var;         /* (mmol/L)^2, >= 0                                   */
+    uint64_t noise_seed;      /* key (low, high ^ arm_id) for meals and noise       */
+    void    *metrics_dev;
+    int32_t  traj_patients;   /* 0..64                                              */
+    void    *traj_dev;
+} vct_sim;
+
+/* Population summary (Sec. III-C indicators, Sec. IV-A ranges). Quantiles are nearest
+ * rank over the per-patient in-range counts: q_p = smallest c with #{count <= c} >=
+ * ceil(p n / 100). The worst patient is the lexicographic minimum of (min G, index). */
+typedef struct {
+    int64_t  n_patients;
+    int64_t  n_samples;        /* K per patient                                     */
+    uint64_t bins[5];
+    uint64_t events[3];
+    int64_t  q_count[5];       /* 5/25/50/75/95 %                                   */
+    double   q_frac[5];        /* q_count / K                                       */
+    double   mean_tir;         /* bins[2] / (n K)                                   */
+    double   mean_bg;          /* sum of sum_g / (n K), fixed-order FP64 tree       */
+    double   mean_insulin;     /* mean of sum_u, mU                                 */
+    int64_t  worst_patient;
+    double   worst_min_g;
+    int32_t  worst_k;
+    int32_t  _pad;
+    int64_t  status_count[3];
+} vct_summary;
+
+typedef struct vct_population vct_population;   /* opaque, owned by the library */
+
+int         vct_abi_version(void);
+/* Message of the last failed call on this thread ("" if none). */
+const char *vct_last_error(void);
+
+/* Byte sizes of caller-owned buffers. */
+size_t      vct_population_bytes(int64_t n_patients);   /* VCT_NPARAM_ROWS * n doubles, SoA */
+size_t      vct_metrics_bytes(int64_t n_patients);      /* 64 * n                        */
+size_t      vct_traj_bytes(int32_t traj_patients, int32_t n_days, int32_t ts_min);
+
+/* Draw the population into params_dev (SoA [VCT_NPARAM_ROWS][n] doubles: the 15
+ * parameters, u_b in mU/min, I* in mU/L, attempts used, status) and return a handle
+ * that borrows params_dev. */
+vct_status  vct_create_population(const vct_population_desc *desc, void *params_dev, void *stream,
+                                  vct_population **out);
+/* Closed-loop Monte Carlo of every patient of the population (Sec. III). */
+vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol, const vct_controller *ctrl,
+                         const vct_sim *sim, void *stream);
+/* Reduce the per-patient metrics of n patients with K samples each into *host_out. */
+vct_status  vct_read_metrics(const void *metrics_dev, int64_t n_patients, int64_t n_samples,
+                             vct_summary *host_out, void *stream);
+void        vct_destroy_population(vct_population *pop);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,278 @@
+// abi.hip -- host runtime behind include/vct.h: argument validation, launch planning,
+// error mapping and the population handle.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/vct.h"
+#include "internal.hpp"
+
+struct vct_population {
+    int64_t n;
+    double *params;
+    uint32_t arm_id;
+    uint32_t flags;
+    double ag, tau, g_target;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+vct_status fail(vct_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+vct_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(VCT_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+void split_key(uint64_t seed, uint32_t arm, uint32_t &k0, uint32_t &k1)
+{
+    k0 = (uint32_t)(seed & 0xffffffffu);
+    k1 = (uint32_t)(seed >> 32) ^ arm;
+}
+
+const int64_t kMaxPatients = (int64_t)1 << 31;
+
+}  // namespace
+
+extern "C" {
+
+int vct_abi_version(void) { return VCT_ABI_VERSION; }
+
+const char *vct_last_error(void) { return g_err.c_str(); }
+
+size_t vct_population_bytes(int64_t n) { return n > 0 ? (size_t)n * VCT_NPARAM_ROWS * sizeof(double) : 0; }
+
+size_t vct_metrics_bytes(int64_t n) { return n > 0 ? (size_t)n * 64u : 0; }
+
+size_t vct_traj_bytes(int32_t traj_patients, int32_t n_days, int32_t ts_min)
+{
+    if (traj_patients <= 0 || n_days <= 0 || ts_min <= 0 || 1440 % ts_min != 0)
+        return 0;
+    return (size_t)3 * traj_patients * (size_t)n_days * (size_t)(1440 / ts_min) * sizeof(double);
+}
+
+vct_status vct_create_population(const vct_population_desc *d, void *params_dev, void *stream,
+                                 vct_population **out)
+{
+    g_err.clear();
+    if (!d || !params_dev || !out)
+        return fail(VCT_EINVAL, "vct_create_population: null argument");
+    if (d->n_patients < 1 || d->n_patients >= kMaxPatients)
+        return fail(VCT_EINVAL, "vct_create_population: n_patients %lld out of [1, 2^31)",
+                    (long long)d->n_patients);
+    for (int q = 0; q < VCT_NP; ++q)
+        if (!finite_pos(d->nominal[q]))
+            return fail(VCT_EINVAL, "vct_create_population: nominal[%d] must be finite and > 0", q);
+    if (!(std::isfinite(d->cv) && d->cv >= 0.0))
+        return fail(VCT_EINVAL, "vct_create_population: cv must be finite and >= 0");
+    if (!(finite_pos(d->ag) && d->ag <= 1.0) || !finite_pos(d->tau_cgm) || !finite_pos(d->g_target))
+        return fail(VCT_EINVAL, "vct_create_population: ag in (0,1], tau_cgm > 0, g_target > 0 required");
+    if (d->flags & ~(uint32_t)VCT_POP_MIN_BASAL)
+        return fail(VCT_EINVAL, "vct_create_population: unknown flags 0x%x", d->flags);
+
+    vct::PopArgs a{};
+    a.params = (double *)params_dev;
+    a.n = d->n_patients;
+    a.patient_base = 0;
+    split_key(d->seed, d->arm_id, a.key0, a.key1);
+    a.flags = d->flags;
+    for (int q = 0; q < VCT_NP; ++q)
+        a.nominal[q] = d->nominal[q];
+    a.s = std::sqrt(std::log1p(d->cv * d->cv));
+    a.g_target = d->g_target;
+    hipError_t e = vct::launch_population(a, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_create_population: launch");
+
+    vct_population *p = new (std::nothrow) vct_population;
+    if (!p)
+        return fail(VCT_ENOMEM, "vct_create_population: out of host memory");
+    p->n = d->n_patients;
+    p->params = (double *)params_dev;
+    p->arm_id = d->arm_id;
+    p->flags = d->flags;
+    p->ag = d->ag;
+    p->tau = d->tau_cgm;
+    p->g_target = d->g_target;
+    *out = p;
+    return VCT_OK;
+}
+
+void vct_destroy_population(vct_population *p) { delete p; }
+
+static vct_status check_protocol(const vct_protocol *pr, int32_t ts)
+{
+    if (pr->n_slots < 0 || pr->n_slots > VCT_MAX_SLOTS)
+        return fail(VCT_EINVAL, "protocol: n_slots %d out of [0, %d]", pr->n_slots, VCT_MAX_SLOTS);
+    if (pr->jitter_min < 0 || pr->jitter_min > 120)
+        return fail(VCT_EINVAL, "protocol: jitter_min %d out of [0, 120]", pr->jitter_min);
+    for (int m = 0; m < pr->n_slots; ++m) {
+        const int lo = pr->minute_of_day[m] - pr->jitter_min, hi = pr->minute_of_day[m] + pr->jitter_min;
+        if (lo < 0 || hi >= 1440)
+            return fail(VCT_EINVAL, "protocol: slot %d onset range [%d, %d] leaves the day", m, lo, hi);
+        if (!(std::isfinite(pr->carbs_mean_g[m]) && std::isfinite(pr->carbs_sd_g[m]) && pr->carbs_sd_g[m] >= 0.0))
+            return fail(VCT_EINVAL, "protocol: slot %d carbs distribution invalid", m);
+        if (!(pr->prob[m] >= 0.0 && pr->prob[m] <= 1.0))
+            return fail(VCT_EINVAL, "protocol: slot %d prob outside [0, 1]", m);
+        if (m > 0 && pr->minute_of_day[m] - pr->minute_of_day[m - 1] < 2 * pr->jitter_min + ts)
+            return fail(VCT_EINVAL, "protocol: slots %d and %d must be ordered and at least 2*jitter+ts apart",
+                        m - 1, m);
+    }
+    return VCT_OK;
+}
+
+vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const vct_controller *ctrl,
+                        const vct_sim *sim, void *stream)
+{
+    g_err.clear();
+    if (!pop || !pr || !ctrl || !sim)
+        return fail(VCT_EINVAL, "vct_simulate: null argument");
+    if (!sim->metrics_dev)
+        return fail(VCT_EINVAL, "vct_simulate: metrics_dev is null");
+    if (sim->n_days < 1 || sim->n_days > 100000)
+        return fail(VCT_EINVAL, "vct_simulate: n_days %d out of [1, 100000]", sim->n_days);
+    if (sim->ts_min < 1 || 1440 % sim->ts_min != 0)
+        return fail(VCT_EINVAL, "vct_simulate: ts_min %d must divide 1440", sim->ts_min);
+    if (sim->em_per_ctrl != 5)
+        return fail(VCT_ENOTSUP, "vct_simulate: em_per_ctrl %d (only 5 EM steps per sample)", sim->em_per_ctrl);
+    if (sim->precision != VCT_FP64 && sim->precision != VCT_FP32)
+        return fail(VCT_EINVAL, "vct_simulate: precision %d", sim->precision);
+    if (!(std::isfinite(sim->sigma_q1) && sim->sigma_q1 >= 0.0 && std::isfinite(sim->cgm_var) &&
+          sim->cgm_var >= 0.0))
+        return fail(VCT_EINVAL, "vct_simulate: sigma_q1 and cgm_var must be finite and >= 0");
+    if (sim->traj_patients < 0 || sim->traj_patients > 64 || sim->traj_patients > pop->n ||
+        (sim->traj_patients > 0 && !sim->traj_dev))
+        return fail(VCT_EINVAL, "vct_simulate: traj_patients %d invalid (0..min(64, n), buffer required)",
+                    sim->traj_patients);
+    const int64_t K = (int64_t)sim->n_days * (1440 / sim->ts_min);
+    if (K >= ((int64_t)1 << 31))
+        return fail(VCT_EINVAL, "vct_simulate: horizon too long");
+    if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID) {
+        if (ctrl->kind == VCT_CTRL_MPC || ctrl->kind == VCT_CTRL_MLP)
+            return fail(VCT_ENOTSUP, "vct_simulate: controller kind %d not in this entry point", ctrl->kind);
+        return fail(VCT_EINVAL, "vct_simulate: controller kind %d", ctrl->kind);
+    }
+    if (!(std::isfinite(ctrl->setpoint) && std::isfinite(ctrl->kp) && std::isfinite(ctrl->ki) &&
+          std::isfinite(ctrl->kd) && finite_pos(ctrl->umax_rel) && std::isfinite(ctrl->u_rel) && ctrl->u_rel >= 0))
+        return fail(VCT_EINVAL, "vct_simulate: controller gains must be finite, umax_rel > 0, u_rel >= 0");
+    vct_status st = check_protocol(pr, sim->ts_min);
+    if (st != VCT_OK)
+        return st;
+
+    vct::SimArgs a{};
+    a.params = pop->params;
+    a.n = pop->n;
+    a.patient_base = 0;
+    a.n_days = sim->n_days;
+    a.kday = 1440 / sim->ts_min;
+    split_key(sim->noise_seed, pop->arm_id, a.key0, a.key1);
+    a.n_slots = pr->n_slots;
+    for (int m = 0; m < VCT_MAX_SLOTS; ++m) {
+        a.minute_of_day[m] = pr->minute_of_day[m];
+        a.carbs_mean[m] = pr->carbs_mean_g[m];
+        a.carbs_sd[m] = pr->carbs_sd_g[m];
+        a.prob[m] = pr->prob[m];
+        a.prob_thresh[m] = m < pr->n_slots ? (uint32_t)std::ceil(pr->prob[m] * 16777216.0) : 0u;
+    }
+    a.rate_per_g = (1000.0 / 180.16) / (double)sim->ts_min;
+    a.jitter = pr->jitter_min;
+    a.ag = pop->ag;
+    a.tau = pop->tau;
+    a.g_target = pop->g_target;
+    a.ctrl = ctrl->kind;
+    a.setpoint = ctrl->setpoint;
+    a.kp = ctrl->kp;
+    a.ki = ctrl->ki;
+    a.kd = ctrl->kd;
+    a.umax_rel = ctrl->umax_rel;
+    a.u_rel = ctrl->u_rel;
+    a.ts_min = sim->ts_min;
+    a.em_per_ctrl = sim->em_per_ctrl;
+    a.h = (double)sim->ts_min / (double)sim->em_per_ctrl;
+    a.sig_sqh = std::sqrt(a.h) * sim->sigma_q1;
+    a.sqrt_r = std::sqrt(sim->cgm_var);
+    char *m = (char *)sim->metrics_dev;
+    const int64_t n = pop->n;
+    a.sum_g = (double *)(m);
+    a.min_g = (double *)(m + 8 * n);
+    a.sum_u = (double *)(m + 16 * n);
+    a.bins = (int32_t *)(m + 24 * n);
+    a.events = (int32_t *)(m + 44 * n);
+    a.argmin_k = (int32_t *)(m + 56 * n);
+    a.status = (uint32_t *)(m + 60 * n);
+    a.out_stride = n;
+    a.n_traj = sim->traj_patients;
+    a.traj = sim->traj_patients > 0 ? (double *)sim->traj_dev : nullptr;
+    a.K = K;
+    hipError_t e = vct::launch_simulate(a, sim->precision, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_simulate: launch");
+    return VCT_OK;
+}
+
+vct_status vct_read_metrics(const void *metrics_dev, int64_t n, int64_t K, vct_summary *out, void *stream)
+{
+    g_err.clear();
+    if (!metrics_dev || !out)
+        return fail(VCT_EINVAL, "vct_read_metrics: null argument");
+    if (n < 1 || n >= kMaxPatients || K < 1 || K >= ((int64_t)1 << 31))
+        return fail(VCT_EINVAL, "vct_read_metrics: n %lld or K %lld out of range", (long long)n, (long long)K);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t ws_bytes = vct::reduce_workspace_bytes(n, K) + sizeof(vct::ReduceOut);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, ws_bytes, s);
+    if (e != hipSuccess)
+        return fail(VCT_ENOMEM, "vct_read_metrics: workspace of %zu bytes: %s", ws_bytes, hipGetErrorString(e));
+    vct::ReduceOut *dres = (vct::ReduceOut *)((char *)ws + vct::reduce_workspace_bytes(n, K));
+    const char *m = (const char *)metrics_dev;
+    e = vct::launch_reduce((const double *)m, (const double *)(m + 8 * n), (const double *)(m + 16 * n),
+                           (const int32_t *)(m + 24 * n), (const int32_t *)(m + 44 * n),
+                           (const int32_t *)(m + 56 * n), (const uint32_t *)(m + 60 * n), n, K, ws, dres, s);
+    vct::ReduceOut h{};
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(&h, dres, sizeof h, hipMemcpyDeviceToHost, s);
+    hipError_t e2 = hipFreeAsync(ws, s);
+    hipError_t e3 = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_read_metrics: reduction");
+    if (e2 != hipSuccess)
+        return hip_fail(e2, "vct_read_metrics: free");
+    if (e3 != hipSuccess)
+        return hip_fail(e3, "vct_read_metrics: synchronize");
+
+    std::memset(out, 0, sizeof *out);
+    out->n_patients = n;
+    out->n_samples = K;
+    for (int q = 0; q < 5; ++q) out->bins[q] = h.bins[q];
+    for (int q = 0; q < 3; ++q) out->events[q] = h.events[q];
+    for (int q = 0; q < 5; ++q) {
+        out->q_count[q] = h.q_count[q];
+        out->q_frac[q] = (double)h.q_count[q] / (double)K;
+    }
+    out->mean_tir = (double)h.bins[2] / ((double)n * (double)K);
+    out->mean_bg = h.sum_g / ((double)n * (double)K);
+    out->mean_insulin = h.sum_u / (double)n;
+    out->worst_patient = h.worst_patient;
+    out->worst_min_g = h.worst_min_g;
+    out->worst_k = h.worst_k;
+    for (int q = 0; q < 3; ++q) out->status_count[q] = h.status_count[q];
+    return VCT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// internal.hpp -- host-side launch descriptors shared by the ABI layer and the kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vct {
+
+struct PopArgs {
+    double *params;       // SoA [kRows][n]
+    int64_t n;
+    int64_t patient_base; // global index of patient 0 (Philox counter word 1)
+    uint32_t key0, key1;
+    uint32_t flags;
+    double nominal[15];
+    double s;             // sqrt(ln(1 + cv^2))
+    double g_target;
+};
+
+struct SimArgs {
+    const double *params; // SoA [kRows][n], FP64
+    int64_t n;
+    int64_t patient_base;
+    int32_t n_days, kday; // samples per day
+    uint32_t key0, key1;  // simulation key (meals + noise)
+    // protocol
+    int32_t n_slots;
+    int32_t minute_of_day[4];
+    double carbs_mean[4], carbs_sd[4], prob[4];
+    uint32_t prob_thresh[4];  // ceil(prob 2^24): presence iff (2m + 1) < thresh
+    double rate_per_g;        // mmol/min of glucose per gram held over one interval
+    int32_t jitter;
+    // shared model constants
+    double ag, tau, g_target;
+    // controller
+    int32_t ctrl;
+    double setpoint, kp, ki, kd, umax_rel, u_rel;
+    // integration
+    int32_t ts_min, em_per_ctrl;
+    double h, sig_sqh, sqrt_r;
+    // outputs (SoA views of the metrics buffer)
+    double *sum_g, *min_g, *sum_u;
+    int32_t *bins, *events, *argmin_k;
+    uint32_t *status;
+    int64_t out_stride;   // n of the metrics buffer (row stride of bins/events)
+    int32_t n_traj;
+    double *traj;         // [3][n_traj][K] or null
+    int64_t K;
+};
+
+// Launchers (kernels.hip). They only enqueue work; they return the launch error.
+hipError_t launch_population(const PopArgs &a, hipStream_t s);
+hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s);
+
+struct ReduceOut {
+    uint64_t bins[5];
+    uint64_t events[3];
+    int64_t q_count[5];
+    double sum_g;
+    double sum_u;
+    double worst_min_g;
+    int64_t worst_patient;
+    int32_t worst_k;
+    int32_t pad;
+    int64_t status_count[3];
+};
+
+// Reduce metrics; writes one ReduceOut to dev_out. Workspace: see reduce_workspace_bytes.
+size_t reduce_workspace_bytes(int64_t n, int64_t K);
+hipError_t launch_reduce(const double *sum_g, const double *min_g, const double *sum_u, const int32_t *bins,
+                         const int32_t *events, const int32_t *argmin_k, const uint32_t *status, int64_t n,
+                         int64_t K, void *workspace, ReduceOut *dev_out, hipStream_t s);
+
+}  // namespace vct

@@ -1,0 +1,303 @@
+// kernels.hip -- population and closed-loop simulation kernels (gfx950 / CDNA4).
+//
+// One patient per lane, the whole horizon in one launch: the 11 states, ~25 derived
+// constants, the controller state and the metric accumulators stay in VGPRs; a patient
+// reads its 19 FP64 parameters once (coalesced SoA) and writes its 64-byte metric
+// record once. Noise is drawn in the loop from Philox counters, never stored.
+#include "internal.hpp"
+#include "model.hpp"
+#include "rng.hpp"
+
+namespace vct {
+
+// ---------------------------------------------------------------- population ----
+// Lognormal draws with median = nominal: p_j = nom_j exp(s z_j), z_j normal j of the
+// Philox blocks (j/4, patient, PARAM, attempt). Kept iff the basal steady state at G*
+// exists (Sec. IV-B keeps only parameter sets with a valid basal rate).
+__device__ __forceinline__ bool basal_rate(const double *p, double g, double &I, double &ub)
+{
+    const double bw = p[kBW];
+    const double egp0 = p[kEGP0] * bw, f01 = p[kF01] * bw, vg = p[kVG] * bw, vi = p[kVI] * bw;
+    const double q1 = g * vg;
+    const double f01c = f01 * fmin(1.0, g / 4.5);
+    const double fr = g > 9.0 ? 0.003 * (g - 9.0) * vg : 0.0;
+    // dQ1 = dQ2 = 0 with x_j = S_j I, multiplied by (k12 + SID I): a I^2 + b I + c = 0
+    const double a = p[kSID] * (p[kSIT] * q1 + egp0 * p[kSIE]);
+    const double b = p[kSID] * (f01c + fr - egp0) + egp0 * p[kSIE] * p[kK12];
+    const double c = p[kK12] * (f01c + fr - egp0);
+    if (!(c < 0.0) || !(a > 0.0))
+        return false;
+    const double sq = sqrt(b * b - 4.0 * a * c);
+    // the positive root, in the form without cancellation
+    I = b >= 0.0 ? (2.0 * c) / (-b - sq) : (-b + sq) / (2.0 * a);
+    ub = I * p[kKe] * vi;
+    return true;
+}
+
+__global__ __launch_bounds__(256) void population_kernel(const PopArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n)
+        return;
+    const uint32_t pid = (uint32_t)(a.patient_base + j);
+    double p[15];
+    double I = 0.0, ub = 0.0;
+    uint32_t status = 0;
+    int attempt = 0;
+    for (; attempt < 32; ++attempt) {
+        double z[16];
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+            const U4 r = philox4x32_10((uint32_t)c, pid, kTagParam, (uint32_t)attempt, a.key0, a.key1);
+            box_muller_f64(uniform_f64(r.x), uniform_f64(r.y), z[4 * c], z[4 * c + 1]);
+            box_muller_f64(uniform_f64(r.z), uniform_f64(r.w), z[4 * c + 2], z[4 * c + 3]);
+        }
+#pragma unroll
+        for (int q = 0; q < 15; ++q)
+            p[q] = a.nominal[q] * exp(a.s * z[q]);
+        if (basal_rate(p, a.g_target, I, ub) && (!(a.flags & 1u) || ub >= 400.0 / 60.0))
+            break;
+    }
+    if (attempt == 32) {
+#pragma unroll
+        for (int q = 0; q < 15; ++q)
+            p[q] = a.nominal[q];
+        if (!basal_rate(p, a.g_target, I, ub)) {
+            I = 0.0;
+            ub = 0.0;
+        }
+        status |= kStResample;
+    }
+    double *out = a.params;
+#pragma unroll
+    for (int q = 0; q < 15; ++q)
+        out[(int64_t)q * a.n + j] = p[q];
+    out[(int64_t)kUb * a.n + j] = ub;
+    out[(int64_t)kIstar * a.n + j] = I;
+    out[(int64_t)kAttempts * a.n + j] = (double)(attempt < 32 ? attempt + 1 : 32);
+    out[(int64_t)kStatus * a.n + j] = (double)status;
+}
+
+hipError_t launch_population(const PopArgs &a, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    hipLaunchKernelGGL(population_kernel, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- simulation ----
+enum { kCtrlOpen = 0, kCtrlPid = 1 };
+
+// Meals of one (patient, day): Philox block (day, patient, MEAL, slot) gives
+// carbs = max(0, mean + sd z) (cosine normal of u0, u1), integer jitter
+// floor(u2 (2J + 1)) - J and presence u3 < prob. The present meals are returned in
+// slot order in (k0..k3, r0..r3): sample index within the day and the held glucose
+// intake rate (mmol/min); absent entries have k = -1. The normal is drawn in the
+// kernel's precision; jitter and presence are exact integer tests (u3 < prob is
+// (2m + 1) < ceil(prob 2^24), precomputed on the host).
+template <typename R> struct DayMeals {
+    int32_t k0, k1, k2, k3;
+    R r0, r1, r2, r3;
+};
+
+template <typename R>
+__device__ __forceinline__ DayMeals<R> draw_meals(const SimArgs &a, uint32_t pid, int32_t day)
+{
+    DayMeals<R> d{-1, -1, -1, -1, R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int m = 3; m >= 0; --m) {
+        if (m < a.n_slots) {
+            const U4 r = philox4x32_10((uint32_t)day, pid, kTagMeal, (uint32_t)m, a.key0, a.key1);
+            const uint32_t odd3 = (r.w >> 8) | 1u;
+            if (odd3 < a.prob_thresh[m]) {
+                R z0, z1;
+                Rng<R>::box_muller(Rng<R>::uniform(r.x), Rng<R>::uniform(r.y), z0, z1);
+                const R carbs = vmax(R(0), R(a.carbs_mean[m]) + R(a.carbs_sd[m]) * z0);
+                const uint32_t odd2 = (r.z >> 8) | 1u;
+                const int32_t jit = (int32_t)(((uint64_t)odd2 * (uint64_t)(2 * a.jitter + 1)) >> 24) - a.jitter;
+                d.k3 = d.k2; d.r3 = d.r2;
+                d.k2 = d.k1; d.r2 = d.r1;
+                d.k1 = d.k0; d.r1 = d.r0;
+                d.k0 = (a.minute_of_day[m] + jit) / a.ts_min;
+                d.r0 = carbs * R(a.rate_per_g);
+            }
+        }
+    }
+    return d;
+}
+
+template <typename R>
+__device__ __forceinline__ bool all_finite(const State<R> &s)
+{
+    return isfinite(s.D1) && isfinite(s.D2) && isfinite(s.S1) && isfinite(s.S2) && isfinite(s.I) &&
+           isfinite(s.x1) && isfinite(s.x2) && isfinite(s.x3) && isfinite(s.Q1) && isfinite(s.Q2) &&
+           isfinite(s.GI);
+}
+
+template <typename R, int CTRL, bool NOISY, bool TRAJ>
+__global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n)
+        return;
+    const uint32_t pid = (uint32_t)(a.patient_base + j);
+
+    double p[15];
+#pragma unroll
+    for (int q = 0; q < 15; ++q)
+        p[q] = a.params[(int64_t)q * a.n + j];
+    const double ub_d = a.params[(int64_t)kUb * a.n + j];
+    const double istar = a.params[(int64_t)kIstar * a.n + j];
+    uint32_t status = (uint32_t)a.params[(int64_t)kStatus * a.n + j];
+
+    State<R> s;
+    basal_state<R>(p, istar, ub_d, a.g_target, s);
+    if (!(ub_d > 0.0)) {   // no basal state exists even for the nominal vector
+        const R nan = R(NAN);
+        s = State<R>{nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan};
+    }
+    StepConst<R> c;
+    step_constants<R>(p, a.h, a.ag, a.tau, c);
+
+    // controller constants (gains relative to u_b)
+    const R kp = R(a.kp * ub_d), ki = R(a.ki * ub_d), kd_ts = R(a.kd * ub_d / (double)a.ts_min);
+    const R umax = R(a.umax_rel * ub_d), ub = R(ub_d), sp = R(a.setpoint), u_open = R(a.u_rel * ub_d);
+    const R ts = R(a.ts_min), h = R(a.h), h_ag = R(a.h * a.ag);
+    const R sig_sqh = R(a.sig_sqh), sqrt_r = R(a.sqrt_r);
+    const double ts_d = (double)a.ts_min;
+    R integ = R(0), y_prev = R(0);
+
+    // metric accumulators: cumulative edge counters (bins follow by differences),
+    // run lengths and event counts, FP64 sums, first minimum
+    int32_t c30 = 0, c39 = 0, c100 = 0, c139 = 0;
+    int32_t r_hypo = 0, r_sev = 0, r_hyper = 0, e_hypo = 0, e_sev = 0, e_hyper = 0;
+    double sum_g = 0.0, sum_u = 0.0;
+    R min_g = R(INFINITY);
+    int32_t argmin = -1;
+    const bool traj_lane = TRAJ && j < a.n_traj;
+
+    for (int32_t day = 0; day < a.n_days; ++day) {
+        DayMeals<R> ml = draw_meals<R>(a, pid, day);
+        for (int32_t kk = 0; kk < a.kday; ++kk) {
+            const int32_t k = day * a.kday + kk;
+
+            // indicators on the true glucose at t_k (Sec. IV-A ranges)
+            const R G = s.Q1 * c.inv_vg;
+            c30 += G >= R(3.0);
+            c39 += G >= R(3.9);
+            c100 += G > R(10.0);
+            c139 += G > R(13.9);
+            r_hypo = G < R(3.9) ? r_hypo + 1 : 0;
+            r_sev = G < R(3.0) ? r_sev + 1 : 0;
+            r_hyper = G > R(13.9) ? r_hyper + 1 : 0;
+            e_hypo += r_hypo == 3;
+            e_sev += r_sev == 3;
+            e_hyper += r_hyper == 3;
+            sum_g += (double)G;
+            if (G < min_g) {
+                min_g = G;
+                argmin = k;
+            }
+            if (G < R(0))
+                status |= kStNegQ1;
+
+            // the sample's normals: blocks (k, patient, DIFF, 0) and (k, patient, DIFF, 1)
+            R xi0 = R(0), xi1 = R(0), xi2 = R(0), xi3 = R(0), xi4 = R(0), v = R(0);
+            if (NOISY) {
+                const U4 b0 = philox4x32_10((uint32_t)k, pid, kTagDiff, 0u, a.key0, a.key1);
+                const U4 b1 = philox4x32_10((uint32_t)k, pid, kTagDiff, 1u, a.key0, a.key1);
+                Rng<R>::box_muller(Rng<R>::uniform(b0.x), Rng<R>::uniform(b0.y), xi0, xi1);
+                Rng<R>::box_muller(Rng<R>::uniform(b0.z), Rng<R>::uniform(b0.w), xi2, xi3);
+                Rng<R>::box_muller(Rng<R>::uniform(b1.x), Rng<R>::uniform(b1.y), xi4, v);
+            }
+            const R y = s.GI + sqrt_r * v;   // sensor value y_k = g(x(t_k)) + v_k
+
+            // controller (Sec. III-B form): control state (integral, previous y)
+            R u;
+            if (CTRL == kCtrlPid) {
+                if (k == 0)
+                    y_prev = y;
+                const R e = y - sp;
+                const R u_unc = ub + kp * e + ki * integ + kd_ts * (y - y_prev);
+                u = vmin(vmax(u_unc, R(0)), umax);
+                if (u_unc >= R(0) && u_unc <= umax)
+                    integ += e * ts;
+                y_prev = y;
+            } else {
+                u = u_open;
+            }
+
+            // held meal input of this interval
+            R dr = R(0);
+            if (kk == ml.k0) {
+                dr = ml.r0;
+                ml.k0 = ml.k1; ml.r0 = ml.r1;
+                ml.k1 = ml.k2; ml.r1 = ml.r2;
+                ml.k2 = ml.k3; ml.r2 = ml.r3;
+                ml.k3 = -1;
+            }
+            if (TRAJ && traj_lane) {
+                a.traj[(0 * (int64_t)a.n_traj + j) * a.K + k] = (double)G;
+                a.traj[(1 * (int64_t)a.n_traj + j) * a.K + k] = (double)y;
+                a.traj[(2 * (int64_t)a.n_traj + j) * a.K + k] = (double)u;
+            }
+
+            const R hu = h * u, hagd = h_ag * dr;
+            em_step<R>(s, c, hu, hagd, sig_sqh * xi0);
+            em_step<R>(s, c, hu, hagd, sig_sqh * xi1);
+            em_step<R>(s, c, hu, hagd, sig_sqh * xi2);
+            em_step<R>(s, c, hu, hagd, sig_sqh * xi3);
+            em_step<R>(s, c, hu, hagd, sig_sqh * xi4);
+            sum_u += (double)u * ts_d;
+        }
+        if (!all_finite(s))
+            status |= kStNonFinite;
+    }
+
+    const int64_t st = a.out_stride;
+    const int32_t K = (int32_t)a.K;
+    a.sum_g[j] = sum_g;
+    a.min_g[j] = (double)min_g;
+    a.sum_u[j] = sum_u;
+    a.bins[0 * st + j] = K - c30;
+    a.bins[1 * st + j] = c30 - c39;
+    a.bins[2 * st + j] = c39 - c100;
+    a.bins[3 * st + j] = c100 - c139;
+    a.bins[4 * st + j] = c139;
+    a.events[0 * st + j] = e_hypo;
+    a.events[1 * st + j] = e_sev;
+    a.events[2 * st + j] = e_hyper;
+    a.argmin_k[j] = argmin;
+    a.status[j] = status;
+}
+
+template <typename R, int CTRL>
+static hipError_t launch_sim_t(const SimArgs &a, bool noisy, hipStream_t s)
+{
+    const unsigned blocks = (unsigned)((a.n + 255) / 256);
+    const bool traj = a.traj != nullptr && a.n_traj > 0;
+    if (noisy) {
+        if (traj)
+            hipLaunchKernelGGL((simulate_kernel<R, CTRL, true, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((simulate_kernel<R, CTRL, true, false>), dim3(blocks), dim3(256), 0, s, a);
+    } else {
+        if (traj)
+            hipLaunchKernelGGL((simulate_kernel<R, CTRL, false, true>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((simulate_kernel<R, CTRL, false, false>), dim3(blocks), dim3(256), 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s)
+{
+    const bool noisy = a.sig_sqh != 0.0 || a.sqrt_r != 0.0;
+    if (precision == 1)
+        return a.ctrl == kCtrlPid ? launch_sim_t<float, kCtrlPid>(a, noisy, s)
+                                  : launch_sim_t<float, kCtrlOpen>(a, noisy, s);
+    return a.ctrl == kCtrlPid ? launch_sim_t<double, kCtrlPid>(a, noisy, s)
+                              : launch_sim_t<double, kCtrlOpen>(a, noisy, s);
+}
+
+}  // namespace vct

@@ -1,0 +1,91 @@
+// rng.hpp -- counter-based noise for the simulation kernels (gfx950).
+//
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11): 4x32-bit counter, 2x32-bit key,
+// ten rounds; a round multiplies words 0 and 2 by the two round multipliers, keeps
+// the low halves as the new words 3 and 1, and XORs the high halves with the other
+// two words and the round key into the new words 0 and 2; the key advances by the
+// two Weyl increments between rounds. Every draw in the trial is addressed by
+// (index, patient, tag, sub-index) so any patient's stream can be replayed anywhere.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vct {
+
+enum : uint32_t { kTagParam = 0u, kTagMeal = 1u, kTagDiff = 2u };
+
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                     uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+        const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)b;
+        c3 = (uint32_t)a;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// Uniform on (0, 1): (2m + 1) 2^-24 with m the top 23 bits -- exact in both precisions.
+// FP32: the bit pattern 1 + m 2^-23 minus (1 - 2^-24) is that value, and the
+// subtraction is exact because the result has at most 24 significant bits.
+__device__ __forceinline__ float uniform_f32(uint32_t x)
+{
+    return __uint_as_float((x >> 9) | 0x3F800000u) - 0.99999994039535522f;
+}
+
+__device__ __forceinline__ double uniform_f64(uint32_t x)
+{
+    return (double)((x >> 8) | 1u) * 5.9604644775390625e-08;
+}
+
+// Box-Muller: r = sqrt(-2 ln u0), z0 = r cos(2 pi u1), z1 = r sin(2 pi u1).
+// FP32 uses the hardware log2 / sqrt / sin / cos (the trigonometric instructions take
+// their argument in revolutions, so 2 pi u1 is never formed).
+__device__ __forceinline__ void box_muller_f32(float u0, float u1, float &z0, float &z1)
+{
+    const float r = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u0));
+    z0 = r * __builtin_amdgcn_cosf(u1);
+    z1 = r * __builtin_amdgcn_sinf(u1);
+}
+
+__device__ __forceinline__ void box_muller_f64(double u0, double u1, double &z0, double &z1)
+{
+    const double r = sqrt(-2.0 * log(u0));
+    double s, c;
+    sincospi(2.0 * u1, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
+template <typename R> struct Rng;
+
+template <> struct Rng<float> {
+    static __device__ __forceinline__ float uniform(uint32_t x) { return uniform_f32(x); }
+    static __device__ __forceinline__ void box_muller(float u0, float u1, float &z0, float &z1)
+    {
+        box_muller_f32(u0, u1, z0, z1);
+    }
+};
+
+template <> struct Rng<double> {
+    static __device__ __forceinline__ double uniform(uint32_t x) { return uniform_f64(x); }
+    static __device__ __forceinline__ void box_muller(double u0, double u1, double &z0, double &z1)
+    {
+        box_muller_f64(u0, u1, z0, z1);
+    }
+};
+
+}  // namespace vct

@@ -1,0 +1,63 @@
+"""Run one trial end to end through the C ABI: torch allocates the device buffers,
+the HIP library does every step (population, closed-loop simulation, reduction).
+"""
+from __future__ import annotations
+
+import torch
+
+from . import vct
+from .workloads import samples_per_day
+
+
+class TrialBuffers:
+    """Caller-owned device buffers of one trial (the library only borrows them)."""
+
+    def __init__(self, trial: dict, device="cuda", traj_patients: int = 0):
+        n = int(trial["n_patients"])
+        self.n = n
+        self.K = int(trial["n_days"]) * samples_per_day(trial)
+        self.params = torch.empty(vct.vct_population_bytes(n) // 8, dtype=torch.float64, device=device)
+        self.metrics = torch.empty(vct.vct_metrics_bytes(n), dtype=torch.uint8, device=device)
+        self.traj_patients = int(traj_patients)
+        tb = vct.vct_traj_bytes(self.traj_patients, int(trial["n_days"]), int(trial["ts_min"]))
+        self.traj = torch.empty(tb // 8, dtype=torch.float64, device=device) if tb else None
+
+
+def create_population(trial: dict, bufs: TrialBuffers, stream=None):
+    return vct.vct_create_population(vct.population_desc(trial), bufs.params, stream)
+
+
+def simulate(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
+    sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj)
+    vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial), sim, stream)
+
+
+def read_metrics(bufs: TrialBuffers, stream=None) -> dict:
+    return vct.vct_read_metrics(bufs.metrics, bufs.n, bufs.K, stream).as_dict()
+
+
+def run(trial: dict, device="cuda", traj_patients: int = 0, stream=None, bufs: TrialBuffers | None = None):
+    """Population -> simulation -> reduction. Returns (summary dict, buffers)."""
+    bufs = bufs or TrialBuffers(trial, device, traj_patients)
+    pop = create_population(trial, bufs, stream)
+    try:
+        simulate(trial, pop, bufs, stream)
+        summary = read_metrics(bufs, stream)
+    finally:
+        vct.vct_destroy_population(pop)
+    return summary, bufs
+
+
+def to_host(bufs: TrialBuffers) -> dict:
+    """Per-patient arrays (numpy) in the oracle's layout, for comparisons."""
+    torch.cuda.synchronize()
+    m = {k: v.cpu().numpy() for k, v in vct.metric_views(bufs.metrics, bufs.n).items()}
+    out = {
+        "bins": m["bins"].T.copy(), "events": m["events"].T.copy(), "sum_g": m["sum_g"], "min_g": m["min_g"],
+        "argmin_k": m["argmin_k"], "sum_u": m["sum_u"], "status": m["status"].view("uint32"),
+        "params": bufs.params.view(vct.VCT_NPARAM_ROWS, bufs.n).cpu().numpy().T.copy(), "K": bufs.K,
+    }
+    if bufs.traj is not None:
+        t = bufs.traj.view(3, bufs.traj_patients, bufs.K).cpu().numpy()
+        out["traj_g"], out["traj_y"], out["traj_u"] = t[0], t[1], t[2]
+    return out

@@ -1,0 +1,229 @@
+"""Thin ctypes binding of the C ABI in include/vct.h (argument marshalling only).
+
+Every step of the trial runs in the HIP library ``libvct.so``; this module only
+fills the C structs, passes device pointers (torch tensors are accepted and their
+``data_ptr()`` is used) and stream handles, and turns error codes into
+exceptions. Importing it does not load the library; the first call does, and it
+raises if the library has not been built -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libvct.so")
+
+VCT_NP, VCT_NX, VCT_NPARAM_ROWS, VCT_MAX_SLOTS = 15, 11, 19, 4
+VCT_OK, VCT_EINVAL, VCT_ENOMEM, VCT_EHIP, VCT_ESTATE, VCT_ENOTSUP = 0, -1, -2, -3, -4, -5
+VCT_CTRL_OPEN, VCT_CTRL_PID, VCT_CTRL_MPC, VCT_CTRL_MLP = 0, 1, 2, 3
+VCT_FP64, VCT_FP32 = 0, 1
+VCT_POP_MIN_BASAL = 1
+
+# byte offsets of the per-patient metric arrays inside a metrics buffer of n patients
+METRIC_LAYOUT = (("sum_g", "f8", 0, 1), ("min_g", "f8", 8, 1), ("sum_u", "f8", 16, 1),
+                 ("bins", "i4", 24, 5), ("events", "i4", 44, 3), ("argmin_k", "i4", 56, 1),
+                 ("status", "u4", 60, 1))
+
+
+class vct_population_desc(C.Structure):
+    _fields_ = [("n_patients", C.c_int64), ("seed", C.c_uint64), ("arm_id", C.c_uint32), ("flags", C.c_uint32),
+                ("nominal", C.c_double * VCT_NP), ("cv", C.c_double), ("ag", C.c_double),
+                ("tau_cgm", C.c_double), ("g_target", C.c_double)]
+
+
+class vct_protocol(C.Structure):
+    _fields_ = [("n_slots", C.c_int32), ("minute_of_day", C.c_int32 * VCT_MAX_SLOTS),
+                ("carbs_mean_g", C.c_double * VCT_MAX_SLOTS), ("carbs_sd_g", C.c_double * VCT_MAX_SLOTS),
+                ("prob", C.c_double * VCT_MAX_SLOTS), ("jitter_min", C.c_int32)]
+
+
+class vct_controller(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
+                ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double)]
+
+
+class vct_sim(C.Structure):
+    _fields_ = [("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("precision", C.c_int32),
+                ("sigma_q1", C.c_double), ("cgm_var", C.c_double), ("noise_seed", C.c_uint64),
+                ("metrics_dev", C.c_void_p), ("traj_patients", C.c_int32), ("traj_dev", C.c_void_p)]
+
+
+class vct_summary(C.Structure):
+    _fields_ = [("n_patients", C.c_int64), ("n_samples", C.c_int64), ("bins", C.c_uint64 * 5),
+                ("events", C.c_uint64 * 3), ("q_count", C.c_int64 * 5), ("q_frac", C.c_double * 5),
+                ("mean_tir", C.c_double), ("mean_bg", C.c_double), ("mean_insulin", C.c_double),
+                ("worst_patient", C.c_int64), ("worst_min_g", C.c_double), ("worst_k", C.c_int32),
+                ("_pad", C.c_int32), ("status_count", C.c_int64 * 3)]
+
+    def as_dict(self) -> dict:
+        return {
+            "n_patients": self.n_patients, "n_samples": self.n_samples, "bins": list(self.bins),
+            "events": list(self.events), "q_count": list(self.q_count), "q_frac": list(self.q_frac),
+            "mean_tir": self.mean_tir, "mean_bg": self.mean_bg, "mean_insulin": self.mean_insulin,
+            "worst_patient": self.worst_patient, "worst_min_g": self.worst_min_g, "worst_k": self.worst_k,
+            "status_count": list(self.status_count),
+        }
+
+
+class VctError(RuntimeError):
+    def __init__(self, fn: str, code: int, msg: str):
+        super().__init__(f"{fn} failed ({code}): {msg}")
+        self.code = code
+
+
+# every symbol include/vct.h declares
+EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_metrics_bytes", "vct_traj_bytes",
+           "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population")
+
+_lib = None
+
+
+def lib() -> C.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} (run __graft_entry__.build())")
+        L = C.CDLL(LIB_PATH)
+        L.vct_abi_version.restype = C.c_int
+        L.vct_last_error.restype = C.c_char_p
+        L.vct_population_bytes.argtypes = [C.c_int64]
+        L.vct_population_bytes.restype = C.c_size_t
+        L.vct_metrics_bytes.argtypes = [C.c_int64]
+        L.vct_metrics_bytes.restype = C.c_size_t
+        L.vct_traj_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+        L.vct_traj_bytes.restype = C.c_size_t
+        L.vct_create_population.argtypes = [C.POINTER(vct_population_desc), C.c_void_p, C.c_void_p,
+                                             C.POINTER(C.c_void_p)]
+        L.vct_create_population.restype = C.c_int
+        L.vct_simulate.argtypes = [C.c_void_p, C.POINTER(vct_protocol), C.POINTER(vct_controller),
+                                   C.POINTER(vct_sim), C.c_void_p]
+        L.vct_simulate.restype = C.c_int
+        L.vct_read_metrics.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(vct_summary), C.c_void_p]
+        L.vct_read_metrics.restype = C.c_int
+        L.vct_destroy_population.argtypes = [C.c_void_p]
+        L.vct_destroy_population.restype = None
+        _lib = L
+    return _lib
+
+
+def _ptr(x) -> int | None:
+    """Device pointer of a torch tensor, or an int address, or None."""
+    if x is None:
+        return None
+    if hasattr(x, "data_ptr"):
+        return int(x.data_ptr())
+    return int(x)
+
+
+def _stream(s) -> int | None:
+    if s is None:
+        return None
+    if hasattr(s, "cuda_stream"):
+        return int(s.cuda_stream)
+    return int(s)
+
+
+def _check(fn: str, rc: int) -> None:
+    if rc != VCT_OK:
+        raise VctError(fn, rc, lib().vct_last_error().decode())
+
+
+# ------------------------------------------------------------------ the ABI
+def vct_abi_version() -> int:
+    return lib().vct_abi_version()
+
+
+def vct_last_error() -> str:
+    return lib().vct_last_error().decode()
+
+
+def vct_population_bytes(n: int) -> int:
+    return lib().vct_population_bytes(n)
+
+
+def vct_metrics_bytes(n: int) -> int:
+    return lib().vct_metrics_bytes(n)
+
+
+def vct_traj_bytes(traj_patients: int, n_days: int, ts_min: int) -> int:
+    return lib().vct_traj_bytes(traj_patients, n_days, ts_min)
+
+
+def vct_create_population(desc: vct_population_desc, params_dev, stream=None) -> C.c_void_p:
+    h = C.c_void_p()
+    _check("vct_create_population",
+           lib().vct_create_population(C.byref(desc), _ptr(params_dev), _stream(stream), C.byref(h)))
+    return h
+
+
+def vct_simulate(pop, protocol: vct_protocol, ctrl: vct_controller, sim: vct_sim, stream=None) -> None:
+    _check("vct_simulate", lib().vct_simulate(pop, C.byref(protocol), C.byref(ctrl), C.byref(sim), _stream(stream)))
+
+
+def vct_read_metrics(metrics_dev, n_patients: int, n_samples: int, stream=None) -> vct_summary:
+    out = vct_summary()
+    _check("vct_read_metrics",
+           lib().vct_read_metrics(_ptr(metrics_dev), n_patients, n_samples, C.byref(out), _stream(stream)))
+    return out
+
+
+def vct_destroy_population(pop) -> None:
+    if pop:
+        lib().vct_destroy_population(pop)
+
+
+# ------------------------------------------------- marshalling of trial dicts
+def population_desc(trial: dict) -> vct_population_desc:
+    d = vct_population_desc()
+    d.n_patients = int(trial["n_patients"])
+    d.seed = int(trial["pop_seed"])
+    d.arm_id = int(trial["arm_id"])
+    d.flags = int(trial["pop_flags"])
+    for i, v in enumerate(trial["nominal"]):
+        d.nominal[i] = float(v)
+    d.cv, d.ag, d.tau_cgm, d.g_target = (float(trial[k]) for k in ("cv", "ag", "tau_cgm", "g_target"))
+    return d
+
+
+def protocol(trial: dict) -> vct_protocol:
+    p = vct_protocol()
+    p.n_slots = int(trial["n_slots"])
+    for m in range(VCT_MAX_SLOTS):
+        p.minute_of_day[m] = int(trial["minute_of_day"][m])
+        p.carbs_mean_g[m] = float(trial["carbs_mean"][m])
+        p.carbs_sd_g[m] = float(trial["carbs_sd"][m])
+        p.prob[m] = float(trial["prob"][m])
+    p.jitter_min = int(trial["jitter"])
+    return p
+
+
+def controller(trial: dict) -> vct_controller:
+    c = vct_controller()
+    c.kind = int(trial["ctrl_kind"])
+    for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel"):
+        setattr(c, k, float(trial[k]))
+    return c
+
+
+def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None) -> vct_sim:
+    s = vct_sim()
+    s.n_days, s.em_per_ctrl, s.ts_min = int(trial["n_days"]), int(trial["em_per_ctrl"]), int(trial["ts_min"])
+    s.precision = int(trial["precision"])
+    s.sigma_q1, s.cgm_var = float(trial["sigma_q1"]), float(trial["cgm_var"])
+    s.noise_seed = int(trial["noise_seed"])
+    s.metrics_dev = _ptr(metrics_dev)
+    s.traj_patients = int(traj_patients)
+    s.traj_dev = _ptr(traj_dev)
+    return s
+
+
+def metric_views(buf, n: int) -> dict:
+    """Per-patient views (torch) into a metrics buffer laid out as documented in vct.h."""
+    import torch
+    dt = {"f8": torch.float64, "i4": torch.int32, "u4": torch.int32}
+    out = {}
+    for name, kind, off, rows in METRIC_LAYOUT:
+        v = buf[off * n:(off + (8 if kind == "f8" else 4) * rows) * n].view(dt[kind])
+        out[name] = v.view(rows, n) if rows > 1 else v
+    return out

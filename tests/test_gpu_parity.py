@@ -1,0 +1,196 @@
+"""GPU vs FP64 oracle parity through the C ABI (closed-loop Monte Carlo, Sec. III).
+
+Bars (the tolerances the project states for this path):
+* FP64 state (1,000 patients x 7 days): integer metrics exactly equal, sampled-glucose
+  trajectories within 1e-4 relative (observed ~1e-12), sums within 1e-9 relative;
+* FP32 state, noise-free: counts equal up to samples the oracle flags as lying within
+  1e-4 (relative) of a range edge, for every patient whose PID never came within 1e-3
+  u_b of a clamp edge; trajectories within 1e-4 relative;
+* FP32 state, stochastic (same Philox stream): population TIR within 0.1 pp;
+* the reduction equals numpy over the per-patient records (exact integers).
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2202_13927_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2202_13927_amd import trial as T
+    return T
+
+
+def run_gpu(T, trial, traj=0):
+    _say(f"[gpu] n={trial['n_patients']} days={trial['n_days']} prec={trial['precision']} "
+         f"sigma={trial['sigma_q1']} R={trial['cgm_var']} ctrl={trial['ctrl_kind']}")
+    s, bufs = T.run(trial, traj_patients=traj)
+    return s, T.to_host(bufs)
+
+
+def numpy_summary(r):
+    n, K = r["bins"].shape[0], r["K"]
+    tir = r["bins"][:, 2]
+    q = [int(np.percentile(tir, p, method="inverted_cdf")) for p in (5, 25, 50, 75, 95)]
+    mg = np.where(np.isfinite(r["min_g"]), r["min_g"], np.inf)
+    w = int(np.lexsort((np.arange(n), mg))[0])
+    return {"bins": list(r["bins"].sum(0).astype(np.uint64)), "events": list(r["events"].sum(0)), "q_count": q,
+            "worst_patient": w, "worst_k": int(r["argmin_k"][w])}
+
+
+def test_population_matches_oracle(gpu, orc):
+    t = W.with_(W.c1_fp64_pid(), n_patients=3000)
+    _, g = run_gpu(gpu, W.with_(t, n_days=1))
+    o = orc.sample_population(t)
+    assert np.array_equal(g["params"][:, 17:], o[:, 17:])        # attempts, status
+    assert np.allclose(g["params"][:, :17], o[:, :17], rtol=1e-13, atol=0)
+
+
+def test_c1_fp64_exact(gpu, orc):
+    t = W.c1_fp64_pid()
+    s, g = run_gpu(gpu, t, traj=8)
+    o = orc.simulate(t, n_traj=8, threads=THREADS, guard_rel=1e-9)
+    assert np.all(o["n_near"] == 0)
+    for k in ("bins", "events", "argmin_k", "status"):
+        assert np.array_equal(g[k], o[k]), k
+    for k in ("sum_g", "min_g", "sum_u"):
+        assert np.allclose(g[k], o[k], rtol=1e-9, atol=0), k
+    rel = np.abs(g["traj_g"] - o["traj_g"]) / np.abs(o["traj_g"])
+    _say("C1 FP64 max rel traj error", rel.max())
+    assert rel.max() < 1e-4
+    assert np.allclose(g["traj_u"], o["traj_u"], rtol=1e-6, atol=1e-9)
+    so = orc.reduce(o)
+    assert s["bins"] == so["bins"] and s["events"] == so["events"] and s["q_count"] == so["q_count"]
+    assert s["worst_patient"] == so["worst_patient"] and s["worst_k"] == so["worst_k"]
+    assert s["mean_bg"] == pytest.approx(so["mean_bg"], rel=1e-12)
+    assert s["mean_tir"] == pytest.approx(so["mean_tir"], rel=0)
+
+
+def _fp32_slice(noisy):
+    t = W.with_(W.c2_fp32_pid(), n_patients=4099)      # several blocks and a ragged tail
+    return t if noisy else W.noise_free(t)
+
+
+def test_c2_noise_free_fp32(gpu, orc):
+    t = _fp32_slice(False)
+    s, g = run_gpu(gpu, t, traj=8)
+    o = orc.simulate(t, n_traj=8, threads=THREADS, guard_rel=1e-4)
+    clean = o["ctrl_margin"] > 1e-3
+    _say("FP32 noise-free: patients near a clamp edge", int((~clean).sum()), "of", len(clean))
+    assert clean.mean() > 0.9
+    d = np.abs(g["bins"].astype(np.int64) - o["bins"]).sum(1)
+    assert np.all(d[clean] <= 2 * o["n_near"][clean])
+    exact = clean & (o["n_near"] == 0)
+    assert np.array_equal(g["bins"][exact], o["bins"][exact])
+    assert np.array_equal(g["events"][exact], o["events"][exact])
+    assert np.allclose(g["sum_g"][clean], o["sum_g"][clean], rtol=1e-4)
+    tr = clean[:8]
+    rel = np.abs(g["traj_g"][tr] - o["traj_g"][tr]) / np.abs(o["traj_g"][tr])
+    _say("FP32 noise-free max rel traj error", rel.max())
+    assert rel.max() < 1e-4
+    tir_g = g["bins"][:, 2].sum() / g["bins"].sum()
+    tir_o = o["bins"][:, 2].sum() / o["bins"].sum()
+    assert abs(tir_g - tir_o) < 1e-3
+
+
+def test_c2_stochastic_fp32(gpu, orc):
+    t = _fp32_slice(True)
+    s, g = run_gpu(gpu, t, traj=4)
+    o = orc.simulate(t, n_traj=4, threads=THREADS)
+    K = o["K"]
+    dtir = (g["bins"][:, 2].astype(np.int64) - o["bins"][:, 2]) / K
+    _say("FP32 stochastic per-patient |dTIR| max", np.abs(dtir).max(), "mean", np.abs(dtir).mean())
+    assert abs(dtir.mean()) < 1e-3                       # population TIR within 0.1 pp
+    assert np.mean(np.abs(dtir) <= 1e-3) > 0.95           # most patients within 0.1 pp themselves
+    assert np.array_equal(g["status"], o["status"])
+    rel = np.abs(g["traj_g"][:, :288] - o["traj_g"][:, :288]) / np.abs(o["traj_g"][:, :288])
+    assert rel.max() < 1e-3                                # first day, before any branch can diverge
+
+
+def test_reduction_matches_numpy(gpu):
+    t = W.with_(W.c2_fp32_pid(), n_patients=50_001, n_days=3)
+    s, g = run_gpu(gpu, t)
+    ref = numpy_summary(g)
+    assert [int(v) for v in s["bins"]] == [int(v) for v in ref["bins"]]
+    assert [int(v) for v in s["events"]] == [int(v) for v in ref["events"]]
+    assert s["q_count"] == ref["q_count"]
+    assert s["worst_patient"] == ref["worst_patient"] and s["worst_k"] == ref["worst_k"]
+    assert s["mean_bg"] == pytest.approx(g["sum_g"].sum() / (t["n_patients"] * g["K"]), rel=1e-12)
+    assert all(sum(s["bins"]) == t["n_patients"] * g["K"] for _ in [0])
+
+
+def test_deterministic(gpu):
+    t = W.with_(W.c2_fp32_pid(), n_patients=20_000, n_days=2)
+    _, a = run_gpu(gpu, t)
+    _, b = run_gpu(gpu, t)
+    for k in ("bins", "events", "sum_g", "min_g", "sum_u", "argmin_k", "status"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("case", ["one_patient", "ragged", "no_meals", "no_jitter", "cv0", "open_loop",
+                                  "min_basal", "snack", "infeasible_nominal"])
+def test_edge_cases_fp64(gpu, orc, case):
+    t = W.with_(W.c1_fp64_pid(), n_patients=300, n_days=2)
+    t = {
+        "one_patient": lambda: W.with_(t, n_patients=1),
+        "ragged": lambda: W.with_(t, n_patients=257),
+        "no_meals": lambda: W.with_(t, n_slots=0),
+        "no_jitter": lambda: W.with_(t, jitter=0),
+        "cv0": lambda: W.with_(t, cv=0.0),
+        "open_loop": lambda: W.with_(t, ctrl_kind=W.CTRL_OPEN, u_rel=1.3),
+        "min_basal": lambda: W.with_(t, pop_flags=1),
+        "snack": lambda: W.with_(t, n_slots=4, prob=[1.0, 1.0, 0.5, 0.2]),
+        "infeasible_nominal": lambda: W.with_(t, n_patients=64, cv=1e-9,
+                                              nominal=[W.NOMINAL[0], W.NOMINAL[0] * 1.5, *W.NOMINAL[2:]]),
+    }[case]()
+    s, g = run_gpu(gpu, t)
+    o = orc.simulate(t, threads=THREADS, guard_rel=1e-9)
+    assert np.array_equal(g["status"], o["status"])
+    if case == "infeasible_nominal":
+        assert np.all(g["status"] & 4) and np.all(g["status"] & 1)
+        return
+    ok = o["n_near"] == 0
+    assert ok.mean() > 0.99
+    for k in ("bins", "events", "argmin_k"):
+        assert np.array_equal(g[k][ok], o[k][ok]), k
+    assert np.allclose(g["sum_g"], o["sum_g"], rtol=1e-9)
+
+
+def test_full_size_c3_sampled(gpu, orc):
+    """1,000,000 patients x 364 days in the benchmark's launch configuration; a sample of
+    patients spread over the index range is recomputed by the oracle one by one."""
+    t = W.c3_paper_scale()
+    s, g = run_gpu(gpu, t)
+    K = g["K"]
+    assert K == 104_832
+    assert np.all(g["bins"].sum(1) == K)
+    assert s["n_patients"] == 1_000_000 and sum(s["bins"]) == 1_000_000 * K
+    idx = np.linspace(0, t["n_patients"] - 1, 24).astype(int)
+    dt = []
+    for i in idx:
+        o = orc.simulate(t, first=int(i), count=1, threads=1)
+        assert np.array_equal(g["params"][i, 17:], o["params"][0, 17:])
+        assert np.allclose(g["params"][i, :17], o["params"][0, :17], rtol=1e-13)
+        dt.append((int(g["bins"][i, 2]) - int(o["bins"][0, 2])) / K)
+        assert g["status"][i] == o["status"][0]
+    dt = np.array(dt)
+    _say("C3 sampled |dTIR| max", np.abs(dt).max())
+    assert np.abs(dt).max() < 5e-3
+    assert abs(dt.mean()) < 2e-3
+    assert 0.3 < s["mean_tir"] < 0.95 and math.isfinite(s["mean_bg"])
