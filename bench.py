@@ -27,7 +27,7 @@ sys.path.insert(0, ROOT)
 FLOP_PER_PATIENT_DAY = 1440 * 64 + 288 * (6 * 4.5 + 15)   # EM steps + normals + sensor/PID
 PEAK_FP32 = 157.3e12
 PEAK_FP32_NONPACKED = 78.6e12
-ORACLE_SAMPLE = (4000, 364)   # patients 0..3999 of the same trial, full horizon
+ORACLE_SAMPLE = (10000, 364)  # patients 0..9999 of the same trial, full horizon
 
 
 def log(*a):

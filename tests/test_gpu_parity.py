@@ -4,8 +4,9 @@ Bars (the tolerances the project states for this path):
 * FP64 state (1,000 patients x 7 days): integer metrics exactly equal, sampled-glucose
   trajectories within 1e-4 relative (observed ~1e-12), sums within 1e-9 relative;
 * FP32 state, noise-free: counts equal up to samples the oracle flags as lying within
-  1e-4 (relative) of a range edge, for every patient whose PID never came within 1e-3
-  u_b of a clamp edge; trajectories within 1e-4 relative;
+  1e-4 (relative) of a range edge, for every patient whose PID never came within 1e-4
+  u_b of a clamp edge (FP32 rounding can switch such a clamp); trajectories within 1e-4
+  relative;
 * FP32 state, stochastic (same Philox stream): population TIR within 0.1 pp;
 * the reduction equals numpy over the per-patient records (exact integers).
 """
@@ -91,16 +92,19 @@ def test_c2_noise_free_fp32(gpu, orc):
     t = _fp32_slice(False)
     s, g = run_gpu(gpu, t, traj=8)
     o = orc.simulate(t, n_traj=8, threads=THREADS, guard_rel=1e-4)
-    clean = o["ctrl_margin"] > 1e-3
-    _say("FP32 noise-free: patients near a clamp edge", int((~clean).sum()), "of", len(clean))
-    assert clean.mean() > 0.9
     d = np.abs(g["bins"].astype(np.int64) - o["bins"]).sum(1)
-    assert np.all(d[clean] <= 2 * o["n_near"][clean])
-    exact = clean & (o["n_near"] == 0)
+    near_edge = d <= 2 * o["n_near"]          # each flagged sample can move one count
+    near_clamp = o["ctrl_margin"] <= 1e-4     # a PID clamp decision FP32 rounding can switch
+    _say("FP32 noise-free: patients with any count difference", int((d > 0).sum()), "of", len(d),
+         "| not explained by flagged samples", int((~near_edge).sum()),
+         "| of those near a clamp edge", int((~near_edge & near_clamp).sum()))
+    assert np.all(near_edge | near_clamp)
+    assert np.mean(d == 0) > 0.95
+    exact = (o["n_near"] == 0) & ~near_clamp
     assert np.array_equal(g["bins"][exact], o["bins"][exact])
     assert np.array_equal(g["events"][exact], o["events"][exact])
-    assert np.allclose(g["sum_g"][clean], o["sum_g"][clean], rtol=1e-4)
-    tr = clean[:8]
+    assert np.allclose(g["sum_g"][~near_clamp], o["sum_g"][~near_clamp], rtol=1e-4)
+    tr = ~near_clamp[:8]
     rel = np.abs(g["traj_g"][tr] - o["traj_g"][tr]) / np.abs(o["traj_g"][tr])
     _say("FP32 noise-free max rel traj error", rel.max())
     assert rel.max() < 1e-4
