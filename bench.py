@@ -55,6 +55,8 @@ def main() -> int:
     ap.add_argument("--patients", type=int, default=None, help="override the population size")
     ap.add_argument("--days", type=int, default=None, help="override the horizon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one plain device copy of this size first (scales HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -86,6 +88,15 @@ def main() -> int:
         vct.vct_destroy_population(pop)
         sim_ms.append(e0.elapsed_time(e1))
         return s
+
+    if args.copy_probe_mib:
+        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+        stream.synchronize()
+        log(f"[bench] copy probe: {args.copy_probe_mib} MiB read + {args.copy_probe_mib} MiB written")
+        del src, dst
 
     log(f"[bench] trial {n} patients x {days} days, warmup {args.warmup}, steps {args.steps}")
     for i in range(args.warmup):

@@ -477,14 +477,17 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
             double G = x[X_Q1] / vg;
             acc_sample(&a, G, (int32_t)k, cfg->guard_rel);
 
-            /* normals of this sample: call c has counter (k, patient, DIFF, c);
-               xi_j = normal j (j < M), v_k = normal M */
-            double z[64] = {0};
+            /* normals of this sample: samples are drawn in pairs (2j, 2j+1); pair j takes
+               the blocks with counter (j, patient, DIFF, c), c = 0, 1, ..., numbers their
+               normals in order, gives normals 0..M to sample 2j and M+1..2M+1 to sample
+               2j+1; within a sample xi_s = normal s (s < M) and v_k = normal M */
+            double zall[64] = {0};
+            const double *z = zall + (k & 1) * (M + 1);
             if (noisy) {
-                int ncall = (M + 1 + 3) / 4;
+                int ncall = (2 * (M + 1) + 3) / 4;
                 for (int c = 0; c < ncall; ++c) {
-                    uint32_t ctr[4] = {(uint32_t)k, patient, TAG_DIFF, (uint32_t)c};
-                    orc_normals4(ctr, nkey, &z[4 * c]);
+                    uint32_t ctr[4] = {(uint32_t)(k >> 1), patient, TAG_DIFF, (uint32_t)c};
+                    orc_normals4(ctr, nkey, &zall[4 * c]);
                 }
             }
             double y = x[X_GI] + sqrt_r * z[M];
@@ -557,7 +560,7 @@ static void *worker(void *arg)
 
 int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out)
 {
-    if (cfg->ts_min <= 0 || 1440 % cfg->ts_min != 0 || cfg->em_per_ctrl < 1 || cfg->em_per_ctrl > 63)
+    if (cfg->ts_min <= 0 || 1440 % cfg->ts_min != 0 || cfg->em_per_ctrl < 1 || cfg->em_per_ctrl > 31)
         return -1;
     if (cfg->n_slots < 0 || cfg->n_slots > ORC_MAX_SLOTS || cfg->n_days < 0 || count < 0)
         return -1;

@@ -123,7 +123,7 @@ void     orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *
 int      orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out);
 
 /* Generic Euler-Maruyama on the Ornstein-Uhlenbeck SDE dX = -theta X dt + s dW, X(0)=x0,
-   path p uses the same Philox stream layout (counter (n, p, 2, 0), normal #0). Writes X_n. */
+   path p draws step n's normal as normal #0 of the block with counter (n, p, 2, 0). Writes X_n. */
 void     orc_em_ou(double theta, double s, double x0, double h, int32_t n_steps, int64_t n_paths,
                    uint64_t seed, double *x_final);
 

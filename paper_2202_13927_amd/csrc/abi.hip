@@ -149,6 +149,8 @@ vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const
         return fail(VCT_EINVAL, "vct_simulate: n_days %d out of [1, 100000]", sim->n_days);
     if (sim->ts_min < 1 || 1440 % sim->ts_min != 0)
         return fail(VCT_EINVAL, "vct_simulate: ts_min %d must divide 1440", sim->ts_min);
+    if ((1440 / sim->ts_min) % 2 != 0)
+        return fail(VCT_ENOTSUP, "vct_simulate: samples per day must be even (noise is drawn per sample pair)");
     if (sim->em_per_ctrl != 5)
         return fail(VCT_ENOTSUP, "vct_simulate: em_per_ctrl %d (only 5 EM steps per sample)", sim->em_per_ctrl);
     if (sim->precision != VCT_FP64 && sim->precision != VCT_FP32)

@@ -130,8 +130,91 @@ template <typename R>
 __device__ __forceinline__ bool all_finite(const State<R> &s)
 {
     return isfinite(s.D1) && isfinite(s.D2) && isfinite(s.S1) && isfinite(s.S2) && isfinite(s.I) &&
-           isfinite(s.x1) && isfinite(s.x2) && isfinite(s.x3) && isfinite(s.Q1) && isfinite(s.Q2) &&
+           isfinite(s.x1h) && isfinite(s.x2h) && isfinite(s.x3) && isfinite(s.Q1) && isfinite(s.Q2) &&
            isfinite(s.GI);
+}
+
+// Loop-carried state of one patient besides the model state: controller, meal queue,
+// metric accumulators.
+template <typename R> struct Lane {
+    R integ, y_prev;
+    int32_t c30, c39, c100, c139;                 // cumulative edge counters (bins by differences)
+    int32_t r_hypo, r_sev, r_hyper, e_hypo, e_sev, e_hyper;
+    double sum_g, sum_u;
+    R min_g;
+    int32_t argmin;
+    uint32_t status;
+};
+
+// Per-patient constants of the controller and of the sampled inputs.
+template <typename R> struct CtrlConst {
+    R kp, ki, kd_ts, umax, ub, sp, u_open, ts, h, h_ag, sig_sqh, sqrt_r;
+    double ts_d;
+};
+
+// One sampling instant t_k: indicators on the true glucose, sensor value, controller,
+// held inputs, then the EM steps of [t_k, t_k+1). z[0..4] are the EM normals, z[5] the
+// sensor normal.
+template <typename R, int CTRL, bool TRAJ>
+__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t kk, int32_t k, const R *z,
+                                            State<R> &s, const StepConst<R> &c, const CtrlConst<R> &cc,
+                                            DayMeals<R> &ml, Lane<R> &L)
+{
+    // indicators (Sec. IV-A ranges) on G(t_k)
+    const R G = s.Q1 * c.inv_vg;
+    L.c30 += G >= R(3.0);
+    L.c39 += G >= R(3.9);
+    L.c100 += G > R(10.0);
+    L.c139 += G > R(13.9);
+    L.r_hypo = G < R(3.9) ? L.r_hypo + 1 : 0;
+    L.r_sev = G < R(3.0) ? L.r_sev + 1 : 0;
+    L.r_hyper = G > R(13.9) ? L.r_hyper + 1 : 0;
+    L.e_hypo += L.r_hypo == 3;
+    L.e_sev += L.r_sev == 3;
+    L.e_hyper += L.r_hyper == 3;
+    L.sum_g += (double)G;
+    if (G < L.min_g) {
+        L.min_g = G;
+        L.argmin = k;
+    }
+    if (G < R(0))
+        L.status |= kStNegQ1;
+
+    const R y = fmaf_t(cc.sqrt_r, z[5], s.GI);   // y_k = g(x(t_k)) + v_k
+
+    R u;
+    if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
+        if (k == 0)
+            L.y_prev = y;
+        const R e = y - cc.sp;
+        const R u_unc = cc.ub + cc.kp * e + cc.ki * L.integ + cc.kd_ts * (y - L.y_prev);
+        u = vmin(vmax(u_unc, R(0)), cc.umax);
+        if (u_unc >= R(0) && u_unc <= cc.umax)
+            L.integ += e * cc.ts;
+        L.y_prev = y;
+    } else {
+        u = cc.u_open;
+    }
+
+    R dr = R(0);   // held meal input of this interval
+    if (kk == ml.k0) {
+        dr = ml.r0;
+        ml.k0 = ml.k1; ml.r0 = ml.r1;
+        ml.k1 = ml.k2; ml.r1 = ml.r2;
+        ml.k2 = ml.k3; ml.r2 = ml.r3;
+        ml.k3 = -1;
+    }
+    if (TRAJ && j < a.n_traj) {
+        a.traj[(0 * (int64_t)a.n_traj + j) * a.K + k] = (double)G;
+        a.traj[(1 * (int64_t)a.n_traj + j) * a.K + k] = (double)y;
+        a.traj[(2 * (int64_t)a.n_traj + j) * a.K + k] = (double)u;
+    }
+
+    const R hu = cc.h * u, hagd = cc.h_ag * dr;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        em_step<R>(s, c, hu, hagd, cc.sig_sqh * z[q]);
+    L.sum_u += (double)u * cc.ts_d;
 }
 
 template <typename R, int CTRL, bool NOISY, bool TRAJ>
@@ -148,127 +231,81 @@ __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
         p[q] = a.params[(int64_t)q * a.n + j];
     const double ub_d = a.params[(int64_t)kUb * a.n + j];
     const double istar = a.params[(int64_t)kIstar * a.n + j];
-    uint32_t status = (uint32_t)a.params[(int64_t)kStatus * a.n + j];
+
+    Lane<R> L{};
+    L.status = (uint32_t)a.params[(int64_t)kStatus * a.n + j];
+    L.min_g = R(INFINITY);
+    L.argmin = -1;
 
     State<R> s;
-    basal_state<R>(p, istar, ub_d, a.g_target, s);
+    basal_state<R>(p, istar, ub_d, a.g_target, a.h, s);
     if (!(ub_d > 0.0)) {   // no basal state exists even for the nominal vector
         const R nan = R(NAN);
         s = State<R>{nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan};
     }
     StepConst<R> c;
-    step_constants<R>(p, a.h, a.ag, a.tau, c);
+    step_constants<R>(p, a.h, a.tau, c);
 
-    // controller constants (gains relative to u_b)
-    const R kp = R(a.kp * ub_d), ki = R(a.ki * ub_d), kd_ts = R(a.kd * ub_d / (double)a.ts_min);
-    const R umax = R(a.umax_rel * ub_d), ub = R(ub_d), sp = R(a.setpoint), u_open = R(a.u_rel * ub_d);
-    const R ts = R(a.ts_min), h = R(a.h), h_ag = R(a.h * a.ag);
-    const R sig_sqh = R(a.sig_sqh), sqrt_r = R(a.sqrt_r);
-    const double ts_d = (double)a.ts_min;
-    R integ = R(0), y_prev = R(0);
-
-    // metric accumulators: cumulative edge counters (bins follow by differences),
-    // run lengths and event counts, FP64 sums, first minimum
-    int32_t c30 = 0, c39 = 0, c100 = 0, c139 = 0;
-    int32_t r_hypo = 0, r_sev = 0, r_hyper = 0, e_hypo = 0, e_sev = 0, e_hyper = 0;
-    double sum_g = 0.0, sum_u = 0.0;
-    R min_g = R(INFINITY);
-    int32_t argmin = -1;
-    const bool traj_lane = TRAJ && j < a.n_traj;
+    CtrlConst<R> cc;   // gains relative to u_b
+    cc.kp = R(a.kp * ub_d);
+    cc.ki = R(a.ki * ub_d);
+    cc.kd_ts = R(a.kd * ub_d / (double)a.ts_min);
+    cc.umax = R(a.umax_rel * ub_d);
+    cc.ub = R(ub_d);
+    cc.sp = R(a.setpoint);
+    cc.u_open = R(a.u_rel * ub_d);
+    cc.ts = R(a.ts_min);
+    cc.h = R(a.h);
+    cc.h_ag = R(a.h * a.ag);
+    cc.sig_sqh = R(a.sig_sqh);
+    cc.sqrt_r = R(a.sqrt_r);
+    cc.ts_d = (double)a.ts_min;
 
     for (int32_t day = 0; day < a.n_days; ++day) {
         DayMeals<R> ml = draw_meals<R>(a, pid, day);
-        for (int32_t kk = 0; kk < a.kday; ++kk) {
+        for (int32_t kk = 0; kk < a.kday; kk += 2) {
             const int32_t k = day * a.kday + kk;
-
-            // indicators on the true glucose at t_k (Sec. IV-A ranges)
-            const R G = s.Q1 * c.inv_vg;
-            c30 += G >= R(3.0);
-            c39 += G >= R(3.9);
-            c100 += G > R(10.0);
-            c139 += G > R(13.9);
-            r_hypo = G < R(3.9) ? r_hypo + 1 : 0;
-            r_sev = G < R(3.0) ? r_sev + 1 : 0;
-            r_hyper = G > R(13.9) ? r_hyper + 1 : 0;
-            e_hypo += r_hypo == 3;
-            e_sev += r_sev == 3;
-            e_hyper += r_hyper == 3;
-            sum_g += (double)G;
-            if (G < min_g) {
-                min_g = G;
-                argmin = k;
-            }
-            if (G < R(0))
-                status |= kStNegQ1;
-
-            // the sample's normals: blocks (k, patient, DIFF, 0) and (k, patient, DIFF, 1)
-            R xi0 = R(0), xi1 = R(0), xi2 = R(0), xi3 = R(0), xi4 = R(0), v = R(0);
+            // normals of the sample pair (k, k+1): blocks (k/2, patient, DIFF, 0..2), normals
+            // 0..5 for sample k and 6..11 for sample k+1 (EM normals first, sensor last)
+            R z[12];
             if (NOISY) {
-                const U4 b0 = philox4x32_10((uint32_t)k, pid, kTagDiff, 0u, a.key0, a.key1);
-                const U4 b1 = philox4x32_10((uint32_t)k, pid, kTagDiff, 1u, a.key0, a.key1);
-                Rng<R>::box_muller(Rng<R>::uniform(b0.x), Rng<R>::uniform(b0.y), xi0, xi1);
-                Rng<R>::box_muller(Rng<R>::uniform(b0.z), Rng<R>::uniform(b0.w), xi2, xi3);
-                Rng<R>::box_muller(Rng<R>::uniform(b1.x), Rng<R>::uniform(b1.y), xi4, v);
-            }
-            const R y = s.GI + sqrt_r * v;   // sensor value y_k = g(x(t_k)) + v_k
-
-            // controller (Sec. III-B form): control state (integral, previous y)
-            R u;
-            if (CTRL == kCtrlPid) {
-                if (k == 0)
-                    y_prev = y;
-                const R e = y - sp;
-                const R u_unc = ub + kp * e + ki * integ + kd_ts * (y - y_prev);
-                u = vmin(vmax(u_unc, R(0)), umax);
-                if (u_unc >= R(0) && u_unc <= umax)
-                    integ += e * ts;
-                y_prev = y;
+                const uint32_t jp = (uint32_t)(k >> 1);
+                const U4 b0 = philox4x32_10(jp, pid, kTagDiff, 0u, a.key0, a.key1);
+                const U4 b1 = philox4x32_10(jp, pid, kTagDiff, 1u, a.key0, a.key1);
+                const U4 b2 = philox4x32_10(jp, pid, kTagDiff, 2u, a.key0, a.key1);
+                Rng<R>::box_muller(Rng<R>::uniform(b0.x), Rng<R>::uniform(b0.y), z[0], z[1]);
+                Rng<R>::box_muller(Rng<R>::uniform(b0.z), Rng<R>::uniform(b0.w), z[2], z[3]);
+                Rng<R>::box_muller(Rng<R>::uniform(b1.x), Rng<R>::uniform(b1.y), z[4], z[5]);
+                Rng<R>::box_muller(Rng<R>::uniform(b1.z), Rng<R>::uniform(b1.w), z[6], z[7]);
+                Rng<R>::box_muller(Rng<R>::uniform(b2.x), Rng<R>::uniform(b2.y), z[8], z[9]);
+                Rng<R>::box_muller(Rng<R>::uniform(b2.z), Rng<R>::uniform(b2.w), z[10], z[11]);
             } else {
-                u = u_open;
+#pragma unroll
+                for (int q = 0; q < 12; ++q)
+                    z[q] = R(0);
             }
-
-            // held meal input of this interval
-            R dr = R(0);
-            if (kk == ml.k0) {
-                dr = ml.r0;
-                ml.k0 = ml.k1; ml.r0 = ml.r1;
-                ml.k1 = ml.k2; ml.r1 = ml.r2;
-                ml.k2 = ml.k3; ml.r2 = ml.r3;
-                ml.k3 = -1;
-            }
-            if (TRAJ && traj_lane) {
-                a.traj[(0 * (int64_t)a.n_traj + j) * a.K + k] = (double)G;
-                a.traj[(1 * (int64_t)a.n_traj + j) * a.K + k] = (double)y;
-                a.traj[(2 * (int64_t)a.n_traj + j) * a.K + k] = (double)u;
-            }
-
-            const R hu = h * u, hagd = h_ag * dr;
-            em_step<R>(s, c, hu, hagd, sig_sqh * xi0);
-            em_step<R>(s, c, hu, hagd, sig_sqh * xi1);
-            em_step<R>(s, c, hu, hagd, sig_sqh * xi2);
-            em_step<R>(s, c, hu, hagd, sig_sqh * xi3);
-            em_step<R>(s, c, hu, hagd, sig_sqh * xi4);
-            sum_u += (double)u * ts_d;
+            sample_step<R, CTRL, TRAJ>(a, j, kk, k, z, s, c, cc, ml, L);
+            sample_step<R, CTRL, TRAJ>(a, j, kk + 1, k + 1, z + 6, s, c, cc, ml, L);
         }
         if (!all_finite(s))
-            status |= kStNonFinite;
+            L.status |= kStNonFinite;
     }
 
     const int64_t st = a.out_stride;
     const int32_t K = (int32_t)a.K;
-    a.sum_g[j] = sum_g;
-    a.min_g[j] = (double)min_g;
-    a.sum_u[j] = sum_u;
-    a.bins[0 * st + j] = K - c30;
-    a.bins[1 * st + j] = c30 - c39;
-    a.bins[2 * st + j] = c39 - c100;
-    a.bins[3 * st + j] = c100 - c139;
-    a.bins[4 * st + j] = c139;
-    a.events[0 * st + j] = e_hypo;
-    a.events[1 * st + j] = e_sev;
-    a.events[2 * st + j] = e_hyper;
-    a.argmin_k[j] = argmin;
-    a.status[j] = status;
+    a.sum_g[j] = L.sum_g;
+    a.min_g[j] = (double)L.min_g;
+    a.sum_u[j] = L.sum_u;
+    a.bins[0 * st + j] = K - L.c30;
+    a.bins[1 * st + j] = L.c30 - L.c39;
+    a.bins[2 * st + j] = L.c39 - L.c100;
+    a.bins[3 * st + j] = L.c100 - L.c139;
+    a.bins[4 * st + j] = L.c139;
+    a.events[0 * st + j] = L.e_hypo;
+    a.events[1 * st + j] = L.e_sev;
+    a.events[2 * st + j] = L.e_hyper;
+    a.argmin_k[j] = L.argmin;
+    a.status[j] = L.status;
 }
 
 template <typename R, int CTRL>

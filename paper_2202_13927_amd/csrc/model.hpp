@@ -24,6 +24,8 @@ __device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float fmaf_t(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaf_t(double a, double b, double c) { return fma(a, b, c); }
 
 // Row order of the FP64 population buffer (SoA [row][patient]).
 enum : int {
@@ -33,28 +35,32 @@ enum : int {
 
 enum : uint32_t { kStNonFinite = 1u, kStNegQ1 = 2u, kStResample = 4u };
 
+// x1h = h x1 and x2h = h x2 are kept scaled by the step so the products with Q1, Q2
+// need no extra multiply.
 template <typename R> struct State {
-    R D1, D2, S1, S2, I, x1, x2, x3, Q1, Q2, GI;
+    R D1, D2, S1, S2, I, x1h, x2h, x3, Q1, Q2, GI;
 };
 
-// Per-patient constants of the EM step (already multiplied by h where they are used so).
+// Per-patient constants of the EM step; everything that multiplies h is prescaled.
 template <typename R> struct StepConst {
     R a_g, b_g;        // 1 - h/tmaxG, h/tmaxG
     R a_i, b_i;        // 1 - h/tmaxI, h/tmaxI
     R a_e, c_ui;       // 1 - h ke, h/(tmaxI VI)
-    R a1, b1, a2, b2, a3, b3;   // 1 - h ka_j, h ka_j S_j
-    R a_12, h_k12;     // 1 - h k12, h k12
-    R h;               // step, min
-    R inv_vg;          // 1/VG (absolute)
-    R f01h, f01h_45;   // h F01, h F01/4.5
-    R frh;             // h 0.003 VG
+    R a1, hb1;         // 1 - h ka1, h^2 ka1 SIT      (x1h update)
+    R a2, hb2;         // 1 - h ka2, h^2 ka2 SID      (x2h update)
+    R a3, b3;          // 1 - h ka3, h ka3 SIE
+    R a_12, hk12;      // 1 - h k12, h k12
+    R f01h, f01h_q;    // h F01, h F01/(4.5 VG)      (h F01c = min(h F01, Q1 h F01/(4.5 VG)))
+    R fr1, fr0;        // 0.003 h, 0.027 h VG        (h F_R = max(0, Q1 fr1 - fr0))
     R egp0h;           // h EGP0
-    R a_c, b_c;        // 1 - h/tau, h/tau
+    R a_c, bc_q;       // 1 - h/tau, h/(tau VG)
+    R inv_vg;          // 1/VG, for G at the sampling instants
 };
 
 // x(t0) = basal steady state at G* (closed form of the quadratic in I; see population kernel).
 template <typename R>
-__device__ __forceinline__ void basal_state(const double *p, double I, double ub, double g_target, State<R> &s)
+__device__ __forceinline__ void basal_state(const double *p, double I, double ub, double g_target, double h,
+                                            State<R> &s)
 {
     const double vg = p[kVG] * p[kBW];
     const double x1 = p[kSIT] * I, x2 = p[kSID] * I, x3 = p[kSIE] * I;
@@ -64,8 +70,8 @@ __device__ __forceinline__ void basal_state(const double *p, double I, double ub
     s.S1 = R(ub * p[kTmaxI]);
     s.S2 = R(ub * p[kTmaxI]);
     s.I = R(I);
-    s.x1 = R(x1);
-    s.x2 = R(x2);
+    s.x1h = R(h * x1);
+    s.x2h = R(h * x2);
     s.x3 = R(x3);
     s.Q1 = R(q1);
     s.Q2 = R(q1 * x1 / (p[kK12] + x2));
@@ -73,7 +79,7 @@ __device__ __forceinline__ void basal_state(const double *p, double I, double ub
 }
 
 template <typename R>
-__device__ __forceinline__ void step_constants(const double *p, double h, double ag, double tau, StepConst<R> &c)
+__device__ __forceinline__ void step_constants(const double *p, double h, double tau, StepConst<R> &c)
 {
     const double bw = p[kBW];
     const double vi = p[kVI] * bw, vg = p[kVG] * bw;
@@ -85,48 +91,49 @@ __device__ __forceinline__ void step_constants(const double *p, double h, double
     c.a_e = R(1.0 - h * p[kKe]);
     c.c_ui = R(h / (ti * vi));
     c.a1 = R(1.0 - h * p[kKa1]);
-    c.b1 = R(h * p[kKa1] * p[kSIT]);
+    c.hb1 = R(h * h * p[kKa1] * p[kSIT]);
     c.a2 = R(1.0 - h * p[kKa2]);
-    c.b2 = R(h * p[kKa2] * p[kSID]);
+    c.hb2 = R(h * h * p[kKa2] * p[kSID]);
     c.a3 = R(1.0 - h * p[kKa3]);
     c.b3 = R(h * p[kKa3] * p[kSIE]);
     c.a_12 = R(1.0 - h * p[kK12]);
-    c.h_k12 = R(h * p[kK12]);
-    c.h = R(h);
-    c.inv_vg = R(1.0 / vg);
+    c.hk12 = R(h * p[kK12]);
     c.f01h = R(h * p[kF01] * bw);
-    c.f01h_45 = R(h * p[kF01] * bw / 4.5);
-    c.frh = R(h * 0.003 * vg);
+    c.f01h_q = R(h * p[kF01] * bw / (4.5 * vg));
+    c.fr1 = R(0.003 * h);
+    c.fr0 = R(0.027 * h * vg);
     c.egp0h = R(h * p[kEGP0] * bw);
     c.a_c = R(1.0 - h / tau);
-    c.b_c = R(h / tau);
-    (void)ag;
+    c.bc_q = R(h / (tau * vg));
+    c.inv_vg = R(1.0 / vg);
 }
 
 // One EM step. hu = h u and hagd = h AG D are the held inputs of the current sampling
-// interval; dq = sqrt(h) sigma xi is this step's increment of Q1.
+// interval; dq = sqrt(h) sigma xi is this step's increment of Q1. Every right-hand side
+// uses the pre-step state.
 template <typename R>
 __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R hu, R hagd, R dq)
 {
-    const R G = s.Q1 * c.inv_vg;
-    const R hug = s.D2 * c.b_g;                                     // h U_G
-    const R hf01c = vmin(c.f01h, c.f01h_45 * G);                  // h F01c
-    const R hfr = vmax(R(0), G - R(9)) * c.frh;                   // h F_R
-    const R hegp = vmax(R(0), c.egp0h - c.egp0h * s.x3);          // h EGP
-    const R t = s.x1 * s.Q1;                                        // x1 Q1
-    const R Q1n = s.Q1 - c.h * t + c.h_k12 * s.Q2 - hf01c - hfr + hug + hegp + dq;
-    const R Q2n = s.Q2 * (c.a_12 - c.h * s.x2) + c.h * t;
-    const R GIn = s.GI * c.a_c + G * c.b_c;
-    const R D2n = s.D2 * c.a_g + s.D1 * c.b_g;
-    const R D1n = s.D1 * c.a_g + hagd;
-    const R S2n = s.S2 * c.a_i + s.S1 * c.b_i;
-    const R S1n = s.S1 * c.a_i + hu;
-    const R In = s.I * c.a_e + s.S2 * c.c_ui;
-    const R x1n = s.x1 * c.a1 + s.I * c.b1;
-    const R x2n = s.x2 * c.a2 + s.I * c.b2;
-    const R x3n = s.x3 * c.a3 + s.I * c.b3;
+    const R t = s.x1h * s.Q1;                                       // h x1 Q1
+    // terms that do not depend on Q1 first, so the Q1 chain of each step is short
+    R side = fmaf_t(c.hk12, s.Q2, dq);                              // h k12 Q2 + noise
+    side = fmaf_t(s.D2, c.b_g, side);                               //   + h U_G
+    side = side + vmax(R(0), fmaf_t(-c.egp0h, s.x3, c.egp0h));      //   + h EGP
+    const R hf01c = vmin(c.f01h, s.Q1 * c.f01h_q);                   // h F01c
+    const R hfr = vmax(R(0), fmaf_t(s.Q1, c.fr1, -c.fr0));           // h F_R
+    const R Q1n = ((fmaf_t(-s.x1h, s.Q1, s.Q1) - hf01c) - hfr) + side;
+    const R Q2n = fmaf_t(s.Q2, c.a_12 - s.x2h, t);
+    const R GIn = fmaf_t(s.GI, c.a_c, s.Q1 * c.bc_q);
+    const R D2n = fmaf_t(s.D2, c.a_g, s.D1 * c.b_g);
+    const R D1n = fmaf_t(s.D1, c.a_g, hagd);
+    const R S2n = fmaf_t(s.S2, c.a_i, s.S1 * c.b_i);
+    const R S1n = fmaf_t(s.S1, c.a_i, hu);
+    const R In = fmaf_t(s.I, c.a_e, s.S2 * c.c_ui);
+    const R x1n = fmaf_t(s.x1h, c.a1, s.I * c.hb1);
+    const R x2n = fmaf_t(s.x2h, c.a2, s.I * c.hb2);
+    const R x3n = fmaf_t(s.x3, c.a3, s.I * c.b3);
     s.D1 = D1n; s.D2 = D2n; s.S1 = S1n; s.S2 = S2n; s.I = In;
-    s.x1 = x1n; s.x2 = x2n; s.x3 = x3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GI = GIn;
+    s.x1h = x1n; s.x2h = x2n; s.x3 = x3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GI = GIn;
 }
 
 }  // namespace vct

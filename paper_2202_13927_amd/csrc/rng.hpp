@@ -19,15 +19,22 @@ struct U4 {
     uint32_t x, y, z, w;
 };
 
-__host__ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
-                                                     uint32_t k0, uint32_t k1)
+// The two three-way XORs of a round map to one v_bitop3_b32 each (LUT 0x96 = a ^ b ^ c);
+// the 32x32 -> 64-bit products to one v_mad_u64_u32 each.
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                            uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
         const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-        const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3((uint32_t)(b >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(a >> 32), c3, k1);
         c1 = (uint32_t)b;
         c3 = (uint32_t)a;
         c0 = n0;

@@ -161,7 +161,8 @@ def test_em_converges_closed_loop(orc):
 def test_noise_enters_q1_and_sensor(orc):
     """One-minute samples with one EM step each: after the first step Q1 differs from the
     noise-free run by exactly sigma sqrt(h) xi_0; y_0 = G* + sqrt(R) v_0 where xi_0 and v_0
-    are normals #0 and #1 of the call with counter (0, patient, DIFF, 0)."""
+    are normals #0 and #1 of the block with counter (0, patient, DIFF, 0); sample 1 (the
+    second of the pair) takes normals #2 and #3, sample 2 block (1, patient, DIFF, 0)."""
     t = W.with_(W.base_trial(), n_patients=4, n_days=1, n_slots=0, ts_min=1, em_per_ctrl=1,
                 ctrl_kind=W.CTRL_OPEN, sigma_q1=0.8, cgm_var=0.01, noise_seed=11)
     r = orc.simulate(t, n_traj=4, record_x=True, threads=2)
@@ -171,3 +172,11 @@ def test_noise_enters_q1_and_sensor(orc):
         dq = r["traj_x"][j][1, SX["Q1"]] - r0["traj_x"][j][1, SX["Q1"]]
         assert dq == pytest.approx(0.8 * z[0], rel=1e-9)
         assert r["traj_y"][j][0] - 6.0 == pytest.approx(0.1 * z[1], rel=1e-9)
+        # samples come in pairs: sample 1 takes normals #2 (xi) and #3 (v) of the same block,
+        # and its sensor state is still exactly G* (one EM step of GI from G* = GI)
+        assert r["traj_y"][j][1] - 6.0 == pytest.approx(0.1 * z[3], rel=1e-9)
+        z2 = orc.normals4((1, j, 2, 0), (11, 0))
+        x2 = r["traj_x"][j][2]
+        drift = orc.rhs(t, r["params"][j][:15], x2, r["traj_u"][j][2], 0.0)[SX["Q1"]]
+        q2 = r["traj_x"][j][3, SX["Q1"]] - x2[SX["Q1"]]
+        assert q2 - drift == pytest.approx(0.8 * z2[0], rel=1e-9)
