@@ -47,6 +47,35 @@ def cpu_baseline(trial: dict) -> dict:
             "sample": f"patients 0..{n - 1} of the trial, full {d}-day horizon, FP64 oracle ({dt:.1f} s)"}
 
 
+def batched(stream) -> dict:
+    """64 PID arms (4x4x4 gain grid), log-uniform sizes 1k-200k, 1-52 week horizons, in one
+    persistent graph-captured launch with an autotuned block shape."""
+    import torch
+    from paper_2202_13927_amd import trial as T, workloads as W
+    arms = W.c4_arms()
+    log(f"[bench] batched: {len(arms)} arms, {sum(t['n_patients'] for t in arms)} patients")
+    bt = T.Batch(arms, stream=stream)
+    try:
+        bt.run(stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bt.run(stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1)
+        info = bt.info()
+        log(f"[bench] batched: {ms:.1f} ms, block {info['block']}, tuned {info['tuned']}")
+        return {"workload": "64 PID arms, gains x{0.5,0.75,1,1.5}^3, sizes log-uniform 1k-200k, "
+                            "horizons {1,4,13,26,52} weeks, FP32", "patients": sum(t["n_patients"] for t in arms),
+                "patient_days": bt.patient_days, "ms": ms, "patient_days_per_s": bt.patient_days / ms * 1e3,
+                "block": info["block"], "items": info["n_items"], "grid": info["grid"],
+                "tuned_ms_by_block": info["tuned"]}
+    finally:
+        bt.close()
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +84,7 @@ def main() -> int:
     ap.add_argument("--patients", type=int, default=None, help="override the population size")
     ap.add_argument("--days", type=int, default=None, help="override the horizon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-arm batched trial")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scales HBM byte counters)")
     args = ap.parse_args()
@@ -141,6 +171,9 @@ def main() -> int:
         "paper_context": {"patient_days_per_s": 3.64e8 / 4920.0,
                           "note": "1M patients x 52 weeks in 1 h 22 min on 2x EPYC 7542, dual-hormone AP, 30 s step"},
     }
+    del bufs
+    if not args.no_batched:
+        out["batched"] = batched(stream)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(trial)

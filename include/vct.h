@@ -108,9 +108,9 @@ typedef struct {
 
 /* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl
  * steps of ts_min/em_per_ctrl minutes per sampling interval; diffusion sigma_q1 on
- * Q1 only; sensor noise variance cgm_var. Noise: per sample k the Philox blocks
- * (k, patient, 2, 0) and (k, patient, 2, 1) give the EM normals xi_0..xi_4 and the
- * sensor normal v_k (normals #0..#4 and #5 of the 8).
+ * Q1 only; sensor noise variance cgm_var. Noise is drawn per pair of samples
+ * (2j, 2j+1): the Philox blocks (j, patient, 2, 0..2) give 12 normals, #0..#4 the EM
+ * normals and #5 the sensor normal of sample 2j, #6..#10 and #11 those of sample 2j+1.
  *
  * metrics_dev: caller buffer of vct_metrics_bytes(n) bytes, per-patient SoA:
  *   double sum_g[n]   sum of G over the K samples (mmol/L)
@@ -126,7 +126,7 @@ typedef struct {
 typedef struct {
     int32_t  n_days;          /* >= 1                                               */
     int32_t  em_per_ctrl;     /* 5 (the supported EM substep count)                 */
-    int32_t  ts_min;          /* 5                                                  */
+    int32_t  ts_min;          /* sampling interval, min; must divide 720            */
     int32_t  precision;       /* VCT_FP64 | VCT_FP32                               */
     double   sigma_q1;        /* mmol min^-1/2, >= 0                                */
     double   cgm_var;         /* (mmol/L)^2, >= 0                                   */
@@ -158,6 +158,25 @@ typedef struct {
 
 typedef struct vct_population vct_population;   /* opaque, owned by the library */
 
+/* One arm of a batched trial (scenario comparison, Sec. IV-E; many controller variants,
+ * Sec. III-B): its own population (whose arm_id also keys the arm's noise), horizon,
+ * PID gains and metric buffer (vct_metrics_bytes of its population). */
+typedef struct {
+    const vct_population *pop;
+    int32_t n_days;
+    double  kp, ki, kd;       /* relative to u_b, as in vct_controller            */
+    void   *metrics_dev;
+} vct_arm;
+
+typedef struct vct_batch vct_batch;             /* opaque, owned by the library */
+
+typedef struct {
+    int32_t n_arms, n_items;   /* work items = tiles of `block` patients of one arm  */
+    int32_t block, grid;       /* chosen workgroup size, persistent grid             */
+    int32_t tuned_block[4];    /* candidates the autotuner timed                     */
+    double  tuned_ms[4];       /* their times on the 2-day calibration run (0 = not run) */
+} vct_batch_stats;
+
 int         vct_abi_version(void);
 /* Message of the last failed call on this thread ("" if none). */
 const char *vct_last_error(void);
@@ -179,6 +198,23 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
 vct_status  vct_read_metrics(const void *metrics_dev, int64_t n_patients, int64_t n_samples,
                              vct_summary *host_out, void *stream);
 void        vct_destroy_population(vct_population *pop);
+
+/* Batched heterogeneous trial (many arms of uneven size and horizon) in ONE persistent
+ * launch: the library builds a queue of (arm, tile) work items ordered longest horizon
+ * first, picks the workgroup size (block = 0: autotune by timing 64/128/256/512 on
+ * horizons capped at 2 days, which overwrites the arms' metric buffers; else 64, 128,
+ * 256 or 512), and captures queue reset + launch in a HIP graph. The per-arm controller
+ * kind, set point, limits, protocol and noise settings come from ctrl/protocol/sim
+ * (sim->n_days, metrics_dev and traj_* are ignored). Results per patient are identical
+ * to vct_simulate of that arm. The handle borrows the arms' populations and buffers;
+ * it owns only its work-item table, queue counter and graph. */
+vct_status  vct_batch_create(const vct_arm *arms, int32_t n_arms, const vct_protocol *protocol,
+                             const vct_controller *ctrl, const vct_sim *sim, int32_t block, void *stream,
+                             vct_batch **out);
+/* Replay the captured launch on `stream` (asynchronous). Calls on one handle must not overlap. */
+vct_status  vct_batch_run(vct_batch *batch, void *stream);
+vct_status  vct_batch_info(const vct_batch *batch, vct_batch_stats *out);
+void        vct_batch_destroy(vct_batch *batch);
 
 #ifdef __cplusplus
 }

@@ -4,8 +4,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/vct.h"
 #include "internal.hpp"
@@ -137,47 +139,47 @@ static vct_status check_protocol(const vct_protocol *pr, int32_t ts)
     return VCT_OK;
 }
 
-vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const vct_controller *ctrl,
-                        const vct_sim *sim, void *stream)
+// Validates one (population, protocol, controller, settings) tuple and fills the kernel
+// arguments; metrics_dev/traj are taken from `sim`.
+static vct_status build_sim_args(const vct_population *pop, const vct_protocol *pr, const vct_controller *ctrl,
+                                 const vct_sim *sim, bool need_metrics, vct::SimArgs &a)
 {
-    g_err.clear();
     if (!pop || !pr || !ctrl || !sim)
-        return fail(VCT_EINVAL, "vct_simulate: null argument");
-    if (!sim->metrics_dev)
-        return fail(VCT_EINVAL, "vct_simulate: metrics_dev is null");
+        return fail(VCT_EINVAL, "null argument");
+    if (need_metrics && !sim->metrics_dev)
+        return fail(VCT_EINVAL, "metrics_dev is null");
     if (sim->n_days < 1 || sim->n_days > 100000)
-        return fail(VCT_EINVAL, "vct_simulate: n_days %d out of [1, 100000]", sim->n_days);
+        return fail(VCT_EINVAL, "n_days %d out of [1, 100000]", sim->n_days);
     if (sim->ts_min < 1 || 1440 % sim->ts_min != 0)
-        return fail(VCT_EINVAL, "vct_simulate: ts_min %d must divide 1440", sim->ts_min);
+        return fail(VCT_EINVAL, "ts_min %d must divide 1440", sim->ts_min);
     if ((1440 / sim->ts_min) % 2 != 0)
-        return fail(VCT_ENOTSUP, "vct_simulate: samples per day must be even (noise is drawn per sample pair)");
+        return fail(VCT_ENOTSUP, "samples per day must be even (noise is drawn per sample pair)");
     if (sim->em_per_ctrl != 5)
-        return fail(VCT_ENOTSUP, "vct_simulate: em_per_ctrl %d (only 5 EM steps per sample)", sim->em_per_ctrl);
+        return fail(VCT_ENOTSUP, "em_per_ctrl %d (only 5 EM steps per sample)", sim->em_per_ctrl);
     if (sim->precision != VCT_FP64 && sim->precision != VCT_FP32)
-        return fail(VCT_EINVAL, "vct_simulate: precision %d", sim->precision);
+        return fail(VCT_EINVAL, "precision %d", sim->precision);
     if (!(std::isfinite(sim->sigma_q1) && sim->sigma_q1 >= 0.0 && std::isfinite(sim->cgm_var) &&
           sim->cgm_var >= 0.0))
-        return fail(VCT_EINVAL, "vct_simulate: sigma_q1 and cgm_var must be finite and >= 0");
+        return fail(VCT_EINVAL, "sigma_q1 and cgm_var must be finite and >= 0");
     if (sim->traj_patients < 0 || sim->traj_patients > 64 || sim->traj_patients > pop->n ||
         (sim->traj_patients > 0 && !sim->traj_dev))
-        return fail(VCT_EINVAL, "vct_simulate: traj_patients %d invalid (0..min(64, n), buffer required)",
-                    sim->traj_patients);
+        return fail(VCT_EINVAL, "traj_patients %d invalid (0..min(64, n), buffer required)", sim->traj_patients);
     const int64_t K = (int64_t)sim->n_days * (1440 / sim->ts_min);
     if (K >= ((int64_t)1 << 31))
-        return fail(VCT_EINVAL, "vct_simulate: horizon too long");
+        return fail(VCT_EINVAL, "horizon too long");
     if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID) {
         if (ctrl->kind == VCT_CTRL_MPC || ctrl->kind == VCT_CTRL_MLP)
-            return fail(VCT_ENOTSUP, "vct_simulate: controller kind %d not in this entry point", ctrl->kind);
-        return fail(VCT_EINVAL, "vct_simulate: controller kind %d", ctrl->kind);
+            return fail(VCT_ENOTSUP, "controller kind %d not in this entry point", ctrl->kind);
+        return fail(VCT_EINVAL, "controller kind %d", ctrl->kind);
     }
     if (!(std::isfinite(ctrl->setpoint) && std::isfinite(ctrl->kp) && std::isfinite(ctrl->ki) &&
           std::isfinite(ctrl->kd) && finite_pos(ctrl->umax_rel) && std::isfinite(ctrl->u_rel) && ctrl->u_rel >= 0))
-        return fail(VCT_EINVAL, "vct_simulate: controller gains must be finite, umax_rel > 0, u_rel >= 0");
+        return fail(VCT_EINVAL, "controller gains must be finite, umax_rel > 0, u_rel >= 0");
     vct_status st = check_protocol(pr, sim->ts_min);
     if (st != VCT_OK)
         return st;
 
-    vct::SimArgs a{};
+    a = vct::SimArgs{};
     a.params = pop->params;
     a.n = pop->n;
     a.patient_base = 0;
@@ -222,6 +224,19 @@ vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const
     a.n_traj = sim->traj_patients;
     a.traj = sim->traj_patients > 0 ? (double *)sim->traj_dev : nullptr;
     a.K = K;
+    return VCT_OK;
+}
+
+vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const vct_controller *ctrl,
+                        const vct_sim *sim, void *stream)
+{
+    g_err.clear();
+    vct::SimArgs a;
+    vct_status st = build_sim_args(pop, pr, ctrl, sim, true, a);
+    if (st != VCT_OK) {
+        g_err = "vct_simulate: " + g_err;
+        return st;
+    }
     hipError_t e = vct::launch_simulate(a, sim->precision, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "vct_simulate: launch");
@@ -277,4 +292,250 @@ vct_status vct_read_metrics(const void *metrics_dev, int64_t n, int64_t K, vct_s
     return VCT_OK;
 }
 
+// ------------------------------------------------------------- batched arms ----
+struct vct_batch {
+    int32_t n_arms = 0;
+    int precision = 0, ctrl = 0;
+    bool noisy = false;
+    vct::SimArgs *d_arms = nullptr;
+    vct::BatchItem *d_items = nullptr;
+    uint32_t *d_counter = nullptr;
+    int32_t n_items = 0;
+    int32_t block = 0, grid = 0;
+    double tuned_ms[4] = {0, 0, 0, 0};
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static const int kBlocks[4] = {64, 128, 256, 512};
+
+// Work items of one block size: tiles of `block` patients, longest horizon first (LPT),
+// then arm and patient order.
+static std::vector<vct::BatchItem> make_items(const std::vector<vct::SimArgs> &arms, int block)
+{
+    std::vector<int32_t> order(arms.size());
+    for (size_t q = 0; q < arms.size(); ++q)
+        order[q] = (int32_t)q;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t x, int32_t y) { return arms[x].n_days > arms[y].n_days; });
+    std::vector<vct::BatchItem> items;
+    for (int32_t q : order)
+        for (int64_t f = 0; f < arms[q].n; f += block)
+            items.push_back(vct::BatchItem{q, (int32_t)f});
+    return items;
+}
+
+static void free_batch(vct_batch *b)
+{
+    if (!b)
+        return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->cap) hipStreamDestroy(b->cap);
+    if (b->d_arms) hipFree(b->d_arms);
+    if (b->d_items) hipFree(b->d_items);
+    if (b->d_counter) hipFree(b->d_counter);
+    delete b;
+}
+
+static vct_status upload_items(vct_batch *b, const std::vector<vct::BatchItem> &items)
+{
+    if (b->d_items) {
+        hipFree(b->d_items);
+        b->d_items = nullptr;
+    }
+    hipError_t e = hipMalloc(&b->d_items, items.size() * sizeof(vct::BatchItem));
+    if (e != hipSuccess)
+        return fail(VCT_ENOMEM, "vct_batch_create: item table: %s", hipGetErrorString(e));
+    e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(vct::BatchItem), hipMemcpyHostToDevice);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_batch_create: item upload");
+    b->n_items = (int32_t)items.size();
+    return VCT_OK;
+}
+
+static vct::BatchLaunch launch_of(const vct_batch *b, const vct::SimArgs *arms)
+{
+    vct::BatchLaunch L;
+    L.arms = arms;
+    L.items = b->d_items;
+    L.n_items = b->n_items;
+    L.counter = b->d_counter;
+    L.grid = b->grid;
+    L.block = b->block;
+    L.precision = b->precision;
+    L.ctrl = b->ctrl;
+    L.noisy = b->noisy;
+    return L;
+}
+
+static int grid_for(const vct_batch *b, int block, int n_items)
+{
+    int dev = 0, cus = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    const int per_cu = vct::batch_blocks_per_cu(b->precision, b->ctrl, b->noisy, block);
+    const int resident = std::max(1, cus * std::max(1, per_cu));
+    return std::min(resident, n_items);
+}
+
+vct_status vct_batch_create(const vct_arm *arms, int32_t n_arms, const vct_protocol *pr, const vct_controller *ctrl,
+                            const vct_sim *sim, int32_t block, void *stream, vct_batch **out)
+{
+    g_err.clear();
+    if (!arms || !out || n_arms < 1 || n_arms > 65536)
+        return fail(VCT_EINVAL, "vct_batch_create: need 1..65536 arms and an output handle");
+    if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512)
+        return fail(VCT_EINVAL, "vct_batch_create: block %d (0 = autotune, or 64/128/256/512)", block);
+    std::vector<vct::SimArgs> hargs(n_arms);
+    for (int32_t q = 0; q < n_arms; ++q) {
+        if (!arms[q].pop)
+            return fail(VCT_EINVAL, "vct_batch_create: arm %d has no population", q);
+        vct_sim s = *sim;
+        s.n_days = arms[q].n_days;
+        s.metrics_dev = arms[q].metrics_dev;
+        s.traj_patients = 0;
+        s.traj_dev = nullptr;
+        vct_controller c = *ctrl;
+        c.kp = arms[q].kp;
+        c.ki = arms[q].ki;
+        c.kd = arms[q].kd;
+        vct_status st = build_sim_args(arms[q].pop, pr, &c, &s, true, hargs[q]);
+        if (st != VCT_OK) {
+            g_err = "vct_batch_create: arm " + std::to_string(q) + ": " + g_err;
+            return st;
+        }
+    }
+    vct_batch *b = new (std::nothrow) vct_batch;
+    if (!b)
+        return fail(VCT_ENOMEM, "vct_batch_create: out of host memory");
+    b->n_arms = n_arms;
+    b->precision = sim->precision;
+    b->ctrl = ctrl->kind;
+    b->noisy = sim->sigma_q1 != 0.0 || sim->cgm_var != 0.0;
+    hipStream_t us = (hipStream_t)stream;
+    hipError_t e = hipMalloc(&b->d_arms, sizeof(vct::SimArgs) * (size_t)n_arms * 2);
+    if (e == hipSuccess)
+        e = hipMalloc(&b->d_counter, sizeof(uint32_t));
+    if (e != hipSuccess) {
+        free_batch(b);
+        return fail(VCT_ENOMEM, "vct_batch_create: %s", hipGetErrorString(e));
+    }
+    // second copy of the arm table with horizons capped at 2 days: autotuning runs
+    std::vector<vct::SimArgs> cal = hargs;
+    for (auto &a : cal) {
+        a.n_days = std::min(a.n_days, 2);
+        a.K = (int64_t)a.n_days * a.kday;
+    }
+    vct::SimArgs *d_cal = b->d_arms + n_arms;
+    e = hipMemcpy(b->d_arms, hargs.data(), sizeof(vct::SimArgs) * n_arms, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(d_cal, cal.data(), sizeof(vct::SimArgs) * n_arms, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "vct_batch_create: arm upload");
+    }
+
+    // autotuner: time each block shape on the capped horizons, keep the fastest
+    int chosen = block;
+    if (chosen == 0) {
+        hipEvent_t e0, e1;
+        hipEventCreate(&e0);
+        hipEventCreate(&e1);
+        double best = 1e30;
+        for (int t = 0; t < 4; ++t) {
+            const int blk = kBlocks[t];
+            vct_status st = upload_items(b, make_items(hargs, blk));
+            if (st != VCT_OK) {
+                free_batch(b);
+                return st;
+            }
+            b->block = blk;
+            b->grid = grid_for(b, blk, b->n_items);
+            vct::BatchLaunch L = launch_of(b, d_cal);
+            float ms = 0.0f, best_t = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                hipEventRecord(e0, us);
+                e = vct::launch_batch(L, us);
+                hipEventRecord(e1, us);
+                if (e == hipSuccess)
+                    e = hipEventSynchronize(e1);
+                if (e != hipSuccess) {
+                    hipEventDestroy(e0);
+                    hipEventDestroy(e1);
+                    free_batch(b);
+                    return hip_fail(e, "vct_batch_create: autotune launch");
+                }
+                hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0)
+                    best_t = std::min(best_t, ms);
+            }
+            b->tuned_ms[t] = best_t;
+            if (best_t < best) {
+                best = best_t;
+                chosen = blk;
+            }
+        }
+        hipEventDestroy(e0);
+        hipEventDestroy(e1);
+    }
+    vct_status st = upload_items(b, make_items(hargs, chosen));
+    if (st != VCT_OK) {
+        free_batch(b);
+        return st;
+    }
+    b->block = chosen;
+    b->grid = grid_for(b, chosen, b->n_items);
+
+    // capture counter reset + persistent launch once; vct_batch_run replays it
+    e = hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking);
+    if (e == hipSuccess)
+        e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t el = vct::launch_batch(launch_of(b, b->d_arms), b->cap);
+        e = hipStreamEndCapture(b->cap, &b->graph);
+        if (el != hipSuccess)
+            e = el;
+    }
+    if (e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        free_batch(b);
+        return hip_fail(e, "vct_batch_create: graph capture");
+    }
+    *out = b;
+    return VCT_OK;
+}
+
+vct_status vct_batch_run(vct_batch *b, void *stream)
+{
+    g_err.clear();
+    if (!b || !b->exec)
+        return fail(VCT_EINVAL, "vct_batch_run: invalid batch");
+    hipError_t e = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_batch_run: graph launch");
+    return VCT_OK;
+}
+
+vct_status vct_batch_info(const vct_batch *b, vct_batch_stats *out)
+{
+    g_err.clear();
+    if (!b || !out)
+        return fail(VCT_EINVAL, "vct_batch_info: null argument");
+    out->n_arms = b->n_arms;
+    out->n_items = b->n_items;
+    out->block = b->block;
+    out->grid = b->grid;
+    for (int t = 0; t < 4; ++t) {
+        out->tuned_block[t] = kBlocks[t];
+        out->tuned_ms[t] = b->tuned_ms[t];
+    }
+    return VCT_OK;
+}
+
+void vct_batch_destroy(vct_batch *b) { free_batch(b); }
+
 }  // extern "C"
+

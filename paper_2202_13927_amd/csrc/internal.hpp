@@ -48,9 +48,27 @@ struct SimArgs {
     int64_t K;
 };
 
+// One work item of a batched launch: a tile of consecutive patients of one arm.
+struct BatchItem {
+    int32_t arm;
+    int32_t first;
+};
+
+struct BatchLaunch {
+    const SimArgs *arms;   // device array, one per arm
+    const BatchItem *items;
+    int32_t n_items;
+    uint32_t *counter;     // device queue head, reset by the launch itself
+    int32_t grid, block;
+    int precision, ctrl;
+    bool noisy;
+};
+
 // Launchers (kernels.hip). They only enqueue work; they return the launch error.
 hipError_t launch_population(const PopArgs &a, hipStream_t s);
 hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s);
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
+int batch_blocks_per_cu(int precision, int ctrl, bool noisy, int block);
 
 struct ReduceOut {
     uint64_t bins[5];

@@ -217,12 +217,10 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
     L.sum_u += (double)u * cc.ts_d;
 }
 
+// The whole horizon of patient j of the population described by a (one lane).
 template <typename R, int CTRL, bool NOISY, bool TRAJ>
-__global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
+__device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
 {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n)
-        return;
     const uint32_t pid = (uint32_t)(a.patient_base + j);
 
     double p[15];
@@ -306,6 +304,113 @@ __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
     a.events[2 * st + j] = L.e_hyper;
     a.argmin_k[j] = L.argmin;
     a.status[j] = L.status;
+}
+
+template <typename R, int CTRL, bool NOISY, bool TRAJ>
+__global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < a.n)
+        run_patient<R, CTRL, NOISY, TRAJ>(a, j);
+}
+
+// ------------------------------------------------------------ batched arms ----
+// Persistent kernel over a queue of work items (arm, first patient of a tile of
+// blockDim.x patients), ordered longest horizon first. Thread 0 of a workgroup takes
+// the next item with one atomic; the whole workgroup runs that tile for the arm's full
+// horizon, then takes the next. Every workgroup exits once the queue is drained. Each
+// patient runs exactly the code of simulate_kernel, so results do not depend on the
+// batching.
+template <typename R, int CTRL, bool NOISY, int BLOCK>
+__global__ __launch_bounds__(BLOCK) void batch_kernel(const SimArgs *__restrict__ arms,
+                                                      const BatchItem *__restrict__ items, int32_t n_items,
+                                                      uint32_t *__restrict__ counter)
+{
+    __shared__ int32_t next;
+    for (;;) {
+        if (threadIdx.x == 0)
+            next = (int32_t)atomicAdd(counter, 1u);
+        __syncthreads();
+        const int32_t it = next;
+        __syncthreads();
+        if (it >= n_items)
+            return;
+        const BatchItem w = items[it];
+        const SimArgs &a = arms[w.arm];
+        const int64_t j = (int64_t)w.first + threadIdx.x;
+        if (j < a.n)
+            run_patient<R, CTRL, NOISY, false>(a, j);
+    }
+}
+
+__global__ void zero_counter_kernel(uint32_t *c) { *c = 0u; }
+
+template <typename R, int CTRL, bool NOISY, int BLOCK>
+static hipError_t launch_batch_t(const BatchLaunch &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(zero_counter_kernel, dim3(1), dim3(1), 0, s, b.counter);
+    hipLaunchKernelGGL((batch_kernel<R, CTRL, NOISY, BLOCK>), dim3(b.grid), dim3(BLOCK), 0, s, b.arms, b.items,
+                       b.n_items, b.counter);
+    return hipGetLastError();
+}
+
+template <typename R, int CTRL, bool NOISY>
+static hipError_t launch_batch_b(const BatchLaunch &b, hipStream_t s)
+{
+    switch (b.block) {
+    case 64: return launch_batch_t<R, CTRL, NOISY, 64>(b, s);
+    case 128: return launch_batch_t<R, CTRL, NOISY, 128>(b, s);
+    case 256: return launch_batch_t<R, CTRL, NOISY, 256>(b, s);
+    case 512: return launch_batch_t<R, CTRL, NOISY, 512>(b, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename R>
+static hipError_t launch_batch_r(const BatchLaunch &b, hipStream_t s)
+{
+    if (b.ctrl == kCtrlPid)
+        return b.noisy ? launch_batch_b<R, kCtrlPid, true>(b, s) : launch_batch_b<R, kCtrlPid, false>(b, s);
+    return b.noisy ? launch_batch_b<R, kCtrlOpen, true>(b, s) : launch_batch_b<R, kCtrlOpen, false>(b, s);
+}
+
+hipError_t launch_batch(const BatchLaunch &b, hipStream_t s)
+{
+    return b.precision == 1 ? launch_batch_r<float>(b, s) : launch_batch_r<double>(b, s);
+}
+
+template <typename R, int CTRL, bool NOISY, int BLOCK>
+static int resident_t()
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<R, CTRL, NOISY, BLOCK>, BLOCK, 0) !=
+        hipSuccess)
+        return 0;
+    return per_cu;
+}
+
+template <typename R, int CTRL, bool NOISY>
+static int resident_b(int block)
+{
+    switch (block) {
+    case 64: return resident_t<R, CTRL, NOISY, 64>();
+    case 128: return resident_t<R, CTRL, NOISY, 128>();
+    case 256: return resident_t<R, CTRL, NOISY, 256>();
+    case 512: return resident_t<R, CTRL, NOISY, 512>();
+    default: return 0;
+    }
+}
+
+int batch_blocks_per_cu(int precision, int ctrl, bool noisy, int block)
+{
+    if (precision == 1) {
+        if (ctrl == kCtrlPid)
+            return noisy ? resident_b<float, kCtrlPid, true>(block) : resident_b<float, kCtrlPid, false>(block);
+        return noisy ? resident_b<float, kCtrlOpen, true>(block) : resident_b<float, kCtrlOpen, false>(block);
+    }
+    if (ctrl == kCtrlPid)
+        return noisy ? resident_b<double, kCtrlPid, true>(block) : resident_b<double, kCtrlPid, false>(block);
+    return noisy ? resident_b<double, kCtrlOpen, true>(block) : resident_b<double, kCtrlOpen, false>(block);
 }
 
 template <typename R, int CTRL>

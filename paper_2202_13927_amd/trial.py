@@ -61,3 +61,35 @@ def to_host(bufs: TrialBuffers) -> dict:
         t = bufs.traj.view(3, bufs.traj_patients, bufs.K).cpu().numpy()
         out["traj_g"], out["traj_y"], out["traj_u"] = t[0], t[1], t[2]
     return out
+
+
+class Batch:
+    """Many arms (each a trial dict sharing protocol, controller kind and noise settings)
+    in one persistent, graph-captured launch."""
+
+    def __init__(self, arms: list[dict], device="cuda", block: int = 0, stream=None):
+        self.arms = arms
+        self.bufs = [TrialBuffers(t, device) for t in arms]
+        self.pops = [create_population(t, b, stream) for t, b in zip(arms, self.bufs)]
+        c_arms = [vct.arm(p, t["n_days"], t["kp"], t["ki"], t["kd"], b.metrics)
+                  for p, t, b in zip(self.pops, arms, self.bufs)]
+        t0 = arms[0]
+        sim = vct.sim_settings(t0, None)
+        self.handle = vct.vct_batch_create(c_arms, vct.protocol(t0), vct.controller(t0), sim, block, stream)
+        self.patient_days = sum(int(t["n_patients"]) * int(t["n_days"]) for t in arms)
+
+    def run(self, stream=None) -> None:
+        vct.vct_batch_run(self.handle, stream)
+
+    def info(self) -> dict:
+        return vct.vct_batch_info(self.handle).as_dict()
+
+    def summaries(self, stream=None) -> list[dict]:
+        return [read_metrics(b, stream) for b in self.bufs]
+
+    def close(self) -> None:
+        vct.vct_batch_destroy(self.handle)
+        self.handle = None
+        for p in self.pops:
+            vct.vct_destroy_population(p)
+        self.pops = []

@@ -66,6 +66,20 @@ class vct_summary(C.Structure):
         }
 
 
+class vct_arm(C.Structure):
+    _fields_ = [("pop", C.c_void_p), ("n_days", C.c_int32), ("kp", C.c_double), ("ki", C.c_double),
+                ("kd", C.c_double), ("metrics_dev", C.c_void_p)]
+
+
+class vct_batch_stats(C.Structure):
+    _fields_ = [("n_arms", C.c_int32), ("n_items", C.c_int32), ("block", C.c_int32), ("grid", C.c_int32),
+                ("tuned_block", C.c_int32 * 4), ("tuned_ms", C.c_double * 4)]
+
+    def as_dict(self) -> dict:
+        return {"n_arms": self.n_arms, "n_items": self.n_items, "block": self.block, "grid": self.grid,
+                "tuned": dict(zip(list(self.tuned_block), list(self.tuned_ms)))}
+
+
 class VctError(RuntimeError):
     def __init__(self, fn: str, code: int, msg: str):
         super().__init__(f"{fn} failed ({code}): {msg}")
@@ -74,7 +88,8 @@ class VctError(RuntimeError):
 
 # every symbol include/vct.h declares
 EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_metrics_bytes", "vct_traj_bytes",
-           "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population")
+           "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population",
+           "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy")
 
 _lib = None
 
@@ -103,6 +118,16 @@ def lib() -> C.CDLL:
         L.vct_read_metrics.restype = C.c_int
         L.vct_destroy_population.argtypes = [C.c_void_p]
         L.vct_destroy_population.restype = None
+        L.vct_batch_create.argtypes = [C.POINTER(vct_arm), C.c_int32, C.POINTER(vct_protocol),
+                                       C.POINTER(vct_controller), C.POINTER(vct_sim), C.c_int32, C.c_void_p,
+                                       C.POINTER(C.c_void_p)]
+        L.vct_batch_create.restype = C.c_int
+        L.vct_batch_run.argtypes = [C.c_void_p, C.c_void_p]
+        L.vct_batch_run.restype = C.c_int
+        L.vct_batch_info.argtypes = [C.c_void_p, C.POINTER(vct_batch_stats)]
+        L.vct_batch_info.restype = C.c_int
+        L.vct_batch_destroy.argtypes = [C.c_void_p]
+        L.vct_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -173,6 +198,30 @@ def vct_destroy_population(pop) -> None:
         lib().vct_destroy_population(pop)
 
 
+def vct_batch_create(arms, protocol: vct_protocol, ctrl: vct_controller, sim: vct_sim, block: int = 0,
+                     stream=None) -> C.c_void_p:
+    arr = (vct_arm * len(arms))(*arms)
+    h = C.c_void_p()
+    _check("vct_batch_create", lib().vct_batch_create(arr, len(arms), C.byref(protocol), C.byref(ctrl),
+                                                       C.byref(sim), int(block), _stream(stream), C.byref(h)))
+    return h
+
+
+def vct_batch_run(batch, stream=None) -> None:
+    _check("vct_batch_run", lib().vct_batch_run(batch, _stream(stream)))
+
+
+def vct_batch_info(batch) -> vct_batch_stats:
+    out = vct_batch_stats()
+    _check("vct_batch_info", lib().vct_batch_info(batch, C.byref(out)))
+    return out
+
+
+def vct_batch_destroy(batch) -> None:
+    if batch:
+        lib().vct_batch_destroy(batch)
+
+
 # ------------------------------------------------- marshalling of trial dicts
 def population_desc(trial: dict) -> vct_population_desc:
     d = vct_population_desc()
@@ -216,6 +265,15 @@ def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None
     s.traj_patients = int(traj_patients)
     s.traj_dev = _ptr(traj_dev)
     return s
+
+
+def arm(pop, n_days: int, kp: float, ki: float, kd: float, metrics_dev) -> vct_arm:
+    a = vct_arm()
+    a.pop = pop.value if isinstance(pop, C.c_void_p) else pop
+    a.n_days = int(n_days)
+    a.kp, a.ki, a.kd = float(kp), float(ki), float(kd)
+    a.metrics_dev = _ptr(metrics_dev)
+    return a
 
 
 def metric_views(buf, n: int) -> dict:

@@ -100,6 +100,30 @@ def c3_paper_scale() -> dict:
                  n_slots=4, prob=[1.0, 1.0, 1.0, 0.2])
 
 
+GAIN_MULTIPLIERS = (0.5, 0.75, 1.0, 1.5)
+HORIZON_WEEKS = (1, 4, 13, 26, 52)
+
+
+def c4_arms(seed: int = 4, n_min: int = 1_000, n_max: int = 200_000) -> list[dict]:
+    """64 arms: PID gains on the 4x4x4 grid of multipliers of the nominal (Kp, Ki, Kd),
+    arm a = 16 i + 4 j + l; population sizes log-uniform in [n_min, n_max]; horizons
+    uniform over {1, 4, 13, 26, 52} weeks. Each arm is a trial dict whose arm_id keys its
+    population and noise; sizes and horizons come from numpy's seeded generator."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    u_size = rng.random(64)
+    u_h = rng.integers(0, len(HORIZON_WEEKS), 64)
+    base = with_(base_trial(), pop_seed=seed, noise_seed=seed, precision=FP32)
+    arms = []
+    for a in range(64):
+        i, j, l = a // 16, (a // 4) % 4, a % 4
+        n = int(round(np.exp(np.log(n_min) + u_size[a] * np.log(n_max / n_min))))
+        arms.append(with_(base, arm_id=a, n_patients=n, n_days=7 * HORIZON_WEEKS[int(u_h[a])],
+                          kp=base["kp"] * GAIN_MULTIPLIERS[i], ki=base["ki"] * GAIN_MULTIPLIERS[j],
+                          kd=base["kd"] * GAIN_MULTIPLIERS[l]))
+    return arms
+
+
 def days_patients(trial: dict) -> int:
     return int(trial["n_patients"]) * int(trial["n_days"])
 
