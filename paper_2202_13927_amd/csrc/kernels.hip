@@ -129,9 +129,9 @@ __device__ __forceinline__ DayMeals<R> draw_meals(const SimArgs &a, uint32_t pid
 template <typename R>
 __device__ __forceinline__ bool all_finite(const State<R> &s)
 {
-    return isfinite(s.D1) && isfinite(s.D2) && isfinite(s.S1) && isfinite(s.S2) && isfinite(s.I) &&
+    return isfinite(s.D1s) && isfinite(s.D2) && isfinite(s.S1s) && isfinite(s.S2s) && isfinite(s.I) &&
            isfinite(s.x1h) && isfinite(s.x2h) && isfinite(s.x3) && isfinite(s.Q1) && isfinite(s.Q2) &&
-           isfinite(s.GI);
+           isfinite(s.GIs);
 }
 
 // Loop-carried state of one patient besides the model state: controller, meal queue,
@@ -148,13 +148,15 @@ template <typename R> struct Lane {
 
 // Per-patient constants of the controller and of the sampled inputs.
 template <typename R> struct CtrlConst {
-    R kp, ki, kd_ts, umax, ub, sp, u_open, ts, h, h_ag, sig_sqh, sqrt_r;
+    R kp, ki, kd_ts, umax, ub, sp, u_open, ts;
+    R k_sig;          // Box-Muller constant giving normals scaled by sqrt(h) sigma
+    R sig_sqh, sqrt_r;
     double ts_d;
 };
 
 // One sampling instant t_k: indicators on the true glucose, sensor value, controller,
-// held inputs, then the EM steps of [t_k, t_k+1). z[0..4] are the EM normals, z[5] the
-// sensor normal.
+// held inputs, then the EM steps of [t_k, t_k+1). z[0..4] are the EM noise increments
+// (sqrt(h) sigma xi), z[5] the sensor noise (sqrt(R) v).
 template <typename R, int CTRL, bool TRAJ>
 __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t kk, int32_t k, const R *z,
                                             State<R> &s, const StepConst<R> &c, const CtrlConst<R> &cc,
@@ -180,7 +182,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
     if (G < R(0))
         L.status |= kStNegQ1;
 
-    const R y = fmaf_t(cc.sqrt_r, z[5], s.GI);   // y_k = g(x(t_k)) + v_k
+    const R y = fmaf_t(s.GIs, c.gi_scale, z[5]);   // y_k = g(x(t_k)) + v_k
 
     R u;
     if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
@@ -210,10 +212,10 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
         a.traj[(2 * (int64_t)a.n_traj + j) * a.K + k] = (double)u;
     }
 
-    const R hu = cc.h * u, hagd = cc.h_ag * dr;
+    const R du = c.u_in * u, dd = c.d_in * dr;
 #pragma unroll
     for (int q = 0; q < 5; ++q)
-        em_step<R>(s, c, hu, hagd, cc.sig_sqh * z[q]);
+        em_step<R>(s, c, du, dd, z[q]);
     L.sum_u += (double)u * cc.ts_d;
 }
 
@@ -236,13 +238,13 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
     L.argmin = -1;
 
     State<R> s;
-    basal_state<R>(p, istar, ub_d, a.g_target, a.h, s);
+    basal_state<R>(p, istar, ub_d, a.g_target, a.h, a.tau, s);
     if (!(ub_d > 0.0)) {   // no basal state exists even for the nominal vector
         const R nan = R(NAN);
         s = State<R>{nan, nan, nan, nan, nan, nan, nan, nan, nan, nan, nan};
     }
     StepConst<R> c;
-    step_constants<R>(p, a.h, a.tau, c);
+    step_constants<R>(p, a.h, a.tau, a.ag, c);
 
     CtrlConst<R> cc;   // gains relative to u_b
     cc.kp = R(a.kp * ub_d);
@@ -253,8 +255,7 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
     cc.sp = R(a.setpoint);
     cc.u_open = R(a.u_rel * ub_d);
     cc.ts = R(a.ts_min);
-    cc.h = R(a.h);
-    cc.h_ag = R(a.h * a.ag);
+    cc.k_sig = Rng<R>::scaled_const(a.sig_sqh);
     cc.sig_sqh = R(a.sig_sqh);
     cc.sqrt_r = R(a.sqrt_r);
     cc.ts_d = (double)a.ts_min;
@@ -271,12 +272,19 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
                 const U4 b0 = philox4x32_10(jp, pid, kTagDiff, 0u, a.key0, a.key1);
                 const U4 b1 = philox4x32_10(jp, pid, kTagDiff, 1u, a.key0, a.key1);
                 const U4 b2 = philox4x32_10(jp, pid, kTagDiff, 2u, a.key0, a.key1);
-                Rng<R>::box_muller(Rng<R>::uniform(b0.x), Rng<R>::uniform(b0.y), z[0], z[1]);
-                Rng<R>::box_muller(Rng<R>::uniform(b0.z), Rng<R>::uniform(b0.w), z[2], z[3]);
-                Rng<R>::box_muller(Rng<R>::uniform(b1.x), Rng<R>::uniform(b1.y), z[4], z[5]);
-                Rng<R>::box_muller(Rng<R>::uniform(b1.z), Rng<R>::uniform(b1.w), z[6], z[7]);
-                Rng<R>::box_muller(Rng<R>::uniform(b2.x), Rng<R>::uniform(b2.y), z[8], z[9]);
-                Rng<R>::box_muller(Rng<R>::uniform(b2.z), Rng<R>::uniform(b2.w), z[10], z[11]);
+                // pure diffusion pairs come out scaled by sqrt(h) sigma; the two pairs that
+                // mix an EM normal with the sensor normal are scaled per normal
+                R r0, r1;
+                Rng<R>::box_muller_scaled(Rng<R>::uniform(b0.x), Rng<R>::uniform(b0.y), cc.k_sig, z[0], z[1]);
+                Rng<R>::box_muller_scaled(Rng<R>::uniform(b0.z), Rng<R>::uniform(b0.w), cc.k_sig, z[2], z[3]);
+                Rng<R>::box_muller(Rng<R>::uniform(b1.x), Rng<R>::uniform(b1.y), r0, r1);
+                z[4] = cc.sig_sqh * r0;
+                z[5] = cc.sqrt_r * r1;
+                Rng<R>::box_muller_scaled(Rng<R>::uniform(b1.z), Rng<R>::uniform(b1.w), cc.k_sig, z[6], z[7]);
+                Rng<R>::box_muller_scaled(Rng<R>::uniform(b2.x), Rng<R>::uniform(b2.y), cc.k_sig, z[8], z[9]);
+                Rng<R>::box_muller(Rng<R>::uniform(b2.z), Rng<R>::uniform(b2.w), r0, r1);
+                z[10] = cc.sig_sqh * r0;
+                z[11] = cc.sqrt_r * r1;
             } else {
 #pragma unroll
                 for (int q = 0; q < 12; ++q)

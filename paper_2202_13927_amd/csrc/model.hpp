@@ -10,9 +10,9 @@
 //   dQ1 = -F01c - x1 Q1 + k12 Q2 - F_R + U_G + EGP,   dQ2 = x1 Q1 - (k12 + x2) Q2,
 //   dGI = (G - GI)/tau_CGM,
 // with diffusion sigma on Q1 only. One Euler-Maruyama step x <- x + h f(x) + sqrt(h) sigma xi
-// is written in "decay" form (x (1 - h a) + h b for the linear states) so that every
-// state costs one or two VALU instructions; all reciprocals are precomputed once per
-// patient, so the loop has no divides.
+// is written in "decay" form (x (1 - h a) + h b for the linear states) on rescaled states
+// so that most states cost one FMA; all reciprocals are precomputed once per patient, so
+// the loop has no divides.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,17 +35,21 @@ enum : int {
 
 enum : uint32_t { kStNonFinite = 1u, kStNegQ1 = 2u, kStResample = 4u };
 
-// x1h = h x1 and x2h = h x2 are kept scaled by the step so the products with Q1, Q2
-// need no extra multiply.
+// Several states are carried pre-multiplied by the coefficient through which they act
+// on the next state, so that each linear update is a single FMA:
+//   D1s = (h/tmaxG) D1,  S1s = (h/(tmaxI VI)) (h/tmaxI) S1,  S2s = (h/(tmaxI VI)) S2,
+//   x1h = h x1, x2h = h x2,  GIs = GI (tau VG)/h.
+// Unscaled values are recovered only where they are observed (G at the samples, GI for
+// the sensor).
 template <typename R> struct State {
-    R D1, D2, S1, S2, I, x1h, x2h, x3, Q1, Q2, GI;
+    R D1s, D2, S1s, S2s, I, x1h, x2h, x3, Q1, Q2, GIs;
 };
 
 // Per-patient constants of the EM step; everything that multiplies h is prescaled.
 template <typename R> struct StepConst {
     R a_g, b_g;        // 1 - h/tmaxG, h/tmaxG
-    R a_i, b_i;        // 1 - h/tmaxI, h/tmaxI
-    R a_e, c_ui;       // 1 - h ke, h/(tmaxI VI)
+    R a_i;             // 1 - h/tmaxI
+    R a_e;             // 1 - h ke
     R a1, hb1;         // 1 - h ka1, h^2 ka1 SIT      (x1h update)
     R a2, hb2;         // 1 - h ka2, h^2 ka2 SID      (x2h update)
     R a3, b3;          // 1 - h ka3, h ka3 SIE
@@ -53,33 +57,36 @@ template <typename R> struct StepConst {
     R f01h, f01h_q;    // h F01, h F01/(4.5 VG)      (h F01c = min(h F01, Q1 h F01/(4.5 VG)))
     R fr1, fr0;        // 0.003 h, 0.027 h VG        (h F_R = max(0, Q1 fr1 - fr0))
     R egp0h;           // h EGP0
-    R a_c, bc_q;       // 1 - h/tau, h/(tau VG)
+    R a_c;             // 1 - h/tau
     R inv_vg;          // 1/VG, for G at the sampling instants
+    R gi_scale;        // h/(tau VG): GI = gi_scale GIs
+    R u_in, d_in;      // held inputs -> increments: h^2/(tmaxI^2 VI) per mU/min, h^2 AG/tmaxG per mmol/min
 };
 
 // x(t0) = basal steady state at G* (closed form of the quadratic in I; see population kernel).
 template <typename R>
 __device__ __forceinline__ void basal_state(const double *p, double I, double ub, double g_target, double h,
-                                            State<R> &s)
+                                            double tau, State<R> &s)
 {
-    const double vg = p[kVG] * p[kBW];
+    const double vg = p[kVG] * p[kBW], vi = p[kVI] * p[kBW], ti = p[kTmaxI];
     const double x1 = p[kSIT] * I, x2 = p[kSID] * I, x3 = p[kSIE] * I;
     const double q1 = g_target * vg;
-    s.D1 = R(0);
+    const double c_ui = h / (ti * vi), b_i = h / ti;
+    s.D1s = R(0);
     s.D2 = R(0);
-    s.S1 = R(ub * p[kTmaxI]);
-    s.S2 = R(ub * p[kTmaxI]);
+    s.S1s = R(c_ui * b_i * ub * ti);
+    s.S2s = R(c_ui * ub * ti);
     s.I = R(I);
     s.x1h = R(h * x1);
     s.x2h = R(h * x2);
     s.x3 = R(x3);
     s.Q1 = R(q1);
     s.Q2 = R(q1 * x1 / (p[kK12] + x2));
-    s.GI = R(g_target);
+    s.GIs = R(g_target * tau * vg / h);
 }
 
 template <typename R>
-__device__ __forceinline__ void step_constants(const double *p, double h, double tau, StepConst<R> &c)
+__device__ __forceinline__ void step_constants(const double *p, double h, double tau, double ag, StepConst<R> &c)
 {
     const double bw = p[kBW];
     const double vi = p[kVI] * bw, vg = p[kVG] * bw;
@@ -87,9 +94,7 @@ __device__ __forceinline__ void step_constants(const double *p, double h, double
     c.a_g = R(1.0 - h / tg);
     c.b_g = R(h / tg);
     c.a_i = R(1.0 - h / ti);
-    c.b_i = R(h / ti);
     c.a_e = R(1.0 - h * p[kKe]);
-    c.c_ui = R(h / (ti * vi));
     c.a1 = R(1.0 - h * p[kKa1]);
     c.hb1 = R(h * h * p[kKa1] * p[kSIT]);
     c.a2 = R(1.0 - h * p[kKa2]);
@@ -104,15 +109,17 @@ __device__ __forceinline__ void step_constants(const double *p, double h, double
     c.fr0 = R(0.027 * h * vg);
     c.egp0h = R(h * p[kEGP0] * bw);
     c.a_c = R(1.0 - h / tau);
-    c.bc_q = R(h / (tau * vg));
     c.inv_vg = R(1.0 / vg);
+    c.gi_scale = R(h / (tau * vg));
+    c.u_in = R((h / (ti * vi)) * (h / ti) * h);
+    c.d_in = R((h / tg) * h * ag);
 }
 
-// One EM step. hu = h u and hagd = h AG D are the held inputs of the current sampling
-// interval; dq = sqrt(h) sigma xi is this step's increment of Q1. Every right-hand side
-// uses the pre-step state.
+// One EM step. du = u_in u and dd = d_in D are the held inputs of the sampling interval in
+// the scaled coordinates; dq = sqrt(h) sigma xi is this step's increment of Q1. Every
+// right-hand side uses the pre-step state.
 template <typename R>
-__device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R hu, R hagd, R dq)
+__device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R du, R dd, R dq)
 {
     const R t = s.x1h * s.Q1;                                       // h x1 Q1
     // terms that do not depend on Q1 first, so the Q1 chain of each step is short
@@ -123,17 +130,17 @@ __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R hu
     const R hfr = vmax(R(0), fmaf_t(s.Q1, c.fr1, -c.fr0));           // h F_R
     const R Q1n = ((fmaf_t(-s.x1h, s.Q1, s.Q1) - hf01c) - hfr) + side;
     const R Q2n = fmaf_t(s.Q2, c.a_12 - s.x2h, t);
-    const R GIn = fmaf_t(s.GI, c.a_c, s.Q1 * c.bc_q);
-    const R D2n = fmaf_t(s.D2, c.a_g, s.D1 * c.b_g);
-    const R D1n = fmaf_t(s.D1, c.a_g, hagd);
-    const R S2n = fmaf_t(s.S2, c.a_i, s.S1 * c.b_i);
-    const R S1n = fmaf_t(s.S1, c.a_i, hu);
-    const R In = fmaf_t(s.I, c.a_e, s.S2 * c.c_ui);
+    const R GIn = fmaf_t(s.GIs, c.a_c, s.Q1);
+    const R D2n = fmaf_t(s.D2, c.a_g, s.D1s);
+    const R D1n = fmaf_t(s.D1s, c.a_g, dd);
+    const R S2n = fmaf_t(s.S2s, c.a_i, s.S1s);
+    const R S1n = fmaf_t(s.S1s, c.a_i, du);
+    const R In = fmaf_t(s.I, c.a_e, s.S2s);
     const R x1n = fmaf_t(s.x1h, c.a1, s.I * c.hb1);
     const R x2n = fmaf_t(s.x2h, c.a2, s.I * c.hb2);
     const R x3n = fmaf_t(s.x3, c.a3, s.I * c.b3);
-    s.D1 = D1n; s.D2 = D2n; s.S1 = S1n; s.S2 = S2n; s.I = In;
-    s.x1h = x1n; s.x2h = x2n; s.x3 = x3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GI = GIn;
+    s.D1s = D1n; s.D2 = D2n; s.S1s = S1n; s.S2s = S2n; s.I = In;
+    s.x1h = x1n; s.x2h = x2n; s.x3 = x3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
 }
 
 }  // namespace vct

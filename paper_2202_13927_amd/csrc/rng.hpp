@@ -77,6 +77,25 @@ __device__ __forceinline__ void box_muller_f64(double u0, double u1, double &z0,
     z1 = r * s;
 }
 
+// Radius-scaled variants: r = sqrt(-2 ln u0) s folded into one square root as
+// sqrt(ln u0 * (-2 s^2)); neg2s2 = -2 s^2 is precomputed (FP32 uses log2, so its
+// constant carries ln 2).
+__device__ __forceinline__ void box_muller_scaled_f32(float u0, float u1, float neg2s2_ln2, float &z0, float &z1)
+{
+    const float r = __builtin_amdgcn_sqrtf(neg2s2_ln2 * __builtin_amdgcn_logf(u0));
+    z0 = r * __builtin_amdgcn_cosf(u1);
+    z1 = r * __builtin_amdgcn_sinf(u1);
+}
+
+__device__ __forceinline__ void box_muller_scaled_f64(double u0, double u1, double neg2s2, double &z0, double &z1)
+{
+    const double r = sqrt(neg2s2 * log(u0));
+    double s, c;
+    sincospi(2.0 * u1, &s, &c);
+    z0 = r * c;
+    z1 = r * s;
+}
+
 template <typename R> struct Rng;
 
 template <> struct Rng<float> {
@@ -85,6 +104,12 @@ template <> struct Rng<float> {
     {
         box_muller_f32(u0, u1, z0, z1);
     }
+    // constant for box_muller_scaled: -2 s^2 (times ln 2 for the log2 instruction)
+    static __host__ __device__ __forceinline__ float scaled_const(double s) { return (float)(-2.0 * s * s * 0.69314718055994530942); }
+    static __device__ __forceinline__ void box_muller_scaled(float u0, float u1, float k, float &z0, float &z1)
+    {
+        box_muller_scaled_f32(u0, u1, k, z0, z1);
+    }
 };
 
 template <> struct Rng<double> {
@@ -92,6 +117,11 @@ template <> struct Rng<double> {
     static __device__ __forceinline__ void box_muller(double u0, double u1, double &z0, double &z1)
     {
         box_muller_f64(u0, u1, z0, z1);
+    }
+    static __host__ __device__ __forceinline__ double scaled_const(double s) { return -2.0 * s * s; }
+    static __device__ __forceinline__ void box_muller_scaled(double u0, double u1, double k, double &z0, double &z1)
+    {
+        box_muller_scaled_f64(u0, u1, k, z0, z1);
     }
 };
 
