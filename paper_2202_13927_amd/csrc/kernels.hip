@@ -130,7 +130,7 @@ template <typename R>
 __device__ __forceinline__ bool all_finite(const State<R> &s)
 {
     return isfinite(s.D1s) && isfinite(s.D2) && isfinite(s.S1s) && isfinite(s.S2s) && isfinite(s.I) &&
-           isfinite(s.x1h) && isfinite(s.x2h) && isfinite(s.x3) && isfinite(s.Q1) && isfinite(s.Q2) &&
+           isfinite(s.x1h) && isfinite(s.x2h) && isfinite(s.e3) && isfinite(s.Q1) && isfinite(s.Q2) &&
            isfinite(s.GIs);
 }
 

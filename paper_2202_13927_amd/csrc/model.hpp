@@ -38,11 +38,14 @@ enum : uint32_t { kStNonFinite = 1u, kStNegQ1 = 2u, kStResample = 4u };
 // Several states are carried pre-multiplied by the coefficient through which they act
 // on the next state, so that each linear update is a single FMA:
 //   D1s = (h/tmaxG) D1,  S1s = (h/(tmaxI VI)) (h/tmaxI) S1,  S2s = (h/(tmaxI VI)) S2,
-//   x1h = h x1, x2h = h x2,  GIs = GI (tau VG)/h.
+//   x1h = h x1,  x2h = h x2,  e3 = h EGP0 (1 - x3),  GIs = GI (tau VG)/h,
+// e3 being exactly the factor through which x3 acts on EGP. (x2 is not folded into
+// 1 - h k12 - h x2 the same way: that sum is ~0.93 while h x2 is ~0.004, and FP32 would
+// keep only four digits of x2.)
 // Unscaled values are recovered only where they are observed (G at the samples, GI for
 // the sensor).
 template <typename R> struct State {
-    R D1s, D2, S1s, S2s, I, x1h, x2h, x3, Q1, Q2, GIs;
+    R D1s, D2, S1s, S2s, I, x1h, x2h, e3, Q1, Q2, GIs;
 };
 
 // Per-patient constants of the EM step; everything that multiplies h is prescaled.
@@ -50,13 +53,12 @@ template <typename R> struct StepConst {
     R a_g, b_g;        // 1 - h/tmaxG, h/tmaxG
     R a_i;             // 1 - h/tmaxI
     R a_e;             // 1 - h ke
-    R a1, hb1;         // 1 - h ka1, h^2 ka1 SIT      (x1h update)
-    R a2, hb2;         // 1 - h ka2, h^2 ka2 SID      (x2h update)
-    R a3, b3;          // 1 - h ka3, h ka3 SIE
+    R a1, hb1;         // 1 - h ka1, h^2 ka1 SIT                     (x1h update)
+    R a2, hb2;         // 1 - h ka2, h^2 ka2 SID                     (x2h update)
+    R a3, b3e, c3;     // 1 - h ka3, h EGP0 h ka3 SIE, h EGP0 h ka3 (e3 update)
     R a_12, hk12;      // 1 - h k12, h k12
     R f01h, f01h_q;    // h F01, h F01/(4.5 VG)      (h F01c = min(h F01, Q1 h F01/(4.5 VG)))
     R fr1, fr0;        // 0.003 h, 0.027 h VG        (h F_R = max(0, Q1 fr1 - fr0))
-    R egp0h;           // h EGP0
     R a_c;             // 1 - h/tau
     R inv_vg;          // 1/VG, for G at the sampling instants
     R gi_scale;        // h/(tau VG): GI = gi_scale GIs
@@ -79,7 +81,7 @@ __device__ __forceinline__ void basal_state(const double *p, double I, double ub
     s.I = R(I);
     s.x1h = R(h * x1);
     s.x2h = R(h * x2);
-    s.x3 = R(x3);
+    s.e3 = R(h * p[kEGP0] * p[kBW] * (1.0 - x3));
     s.Q1 = R(q1);
     s.Q2 = R(q1 * x1 / (p[kK12] + x2));
     s.GIs = R(g_target * tau * vg / h);
@@ -99,15 +101,16 @@ __device__ __forceinline__ void step_constants(const double *p, double h, double
     c.hb1 = R(h * h * p[kKa1] * p[kSIT]);
     c.a2 = R(1.0 - h * p[kKa2]);
     c.hb2 = R(h * h * p[kKa2] * p[kSID]);
+    const double egp0h = h * p[kEGP0] * bw;
     c.a3 = R(1.0 - h * p[kKa3]);
-    c.b3 = R(h * p[kKa3] * p[kSIE]);
+    c.b3e = R(egp0h * h * p[kKa3] * p[kSIE]);
+    c.c3 = R(egp0h * h * p[kKa3]);
     c.a_12 = R(1.0 - h * p[kK12]);
     c.hk12 = R(h * p[kK12]);
     c.f01h = R(h * p[kF01] * bw);
     c.f01h_q = R(h * p[kF01] * bw / (4.5 * vg));
     c.fr1 = R(0.003 * h);
     c.fr0 = R(0.027 * h * vg);
-    c.egp0h = R(h * p[kEGP0] * bw);
     c.a_c = R(1.0 - h / tau);
     c.inv_vg = R(1.0 / vg);
     c.gi_scale = R(h / (tau * vg));
@@ -125,7 +128,7 @@ __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R du
     // terms that do not depend on Q1 first, so the Q1 chain of each step is short
     R side = fmaf_t(c.hk12, s.Q2, dq);                              // h k12 Q2 + noise
     side = fmaf_t(s.D2, c.b_g, side);                               //   + h U_G
-    side = side + vmax(R(0), fmaf_t(-c.egp0h, s.x3, c.egp0h));      //   + h EGP
+    side = side + vmax(R(0), s.e3);                                 //   + h EGP
     const R hf01c = vmin(c.f01h, s.Q1 * c.f01h_q);                   // h F01c
     const R hfr = vmax(R(0), fmaf_t(s.Q1, c.fr1, -c.fr0));           // h F_R
     const R Q1n = ((fmaf_t(-s.x1h, s.Q1, s.Q1) - hf01c) - hfr) + side;
@@ -138,9 +141,9 @@ __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R du
     const R In = fmaf_t(s.I, c.a_e, s.S2s);
     const R x1n = fmaf_t(s.x1h, c.a1, s.I * c.hb1);
     const R x2n = fmaf_t(s.x2h, c.a2, s.I * c.hb2);
-    const R x3n = fmaf_t(s.x3, c.a3, s.I * c.b3);
+    const R e3n = fmaf_t(s.e3, c.a3, fmaf_t(-c.b3e, s.I, c.c3));
     s.D1s = D1n; s.D2 = D2n; s.S1s = S1n; s.S2s = S2n; s.I = In;
-    s.x1h = x1n; s.x2h = x2n; s.x3 = x3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
+    s.x1h = x1n; s.x2h = x2n; s.e3 = e3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
 }
 
 }  // namespace vct

@@ -48,9 +48,10 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 // Uniform on (0, 1): (2m + 1) 2^-24 with m the top 23 bits -- exact in both precisions.
 // FP32: the bit pattern 1 + m 2^-23 minus (1 - 2^-24) is that value, and the
 // subtraction is exact because the result has at most 24 significant bits.
+// The bit pattern 0x3F800000 | (x >> 9) is one funnel shift: ((0x7F << 32) | x) >> 9.
 __device__ __forceinline__ float uniform_f32(uint32_t x)
 {
-    return __uint_as_float((x >> 9) | 0x3F800000u) - 0.99999994039535522f;
+    return __uint_as_float(__builtin_amdgcn_alignbit(0x7Fu, x, 9u)) - 0.99999994039535522f;
 }
 
 __device__ __forceinline__ double uniform_f64(uint32_t x)
