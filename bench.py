@@ -30,6 +30,28 @@ PEAK_FP32_NONPACKED = 78.6e12
 ORACLE_SAMPLE = (10000, 364)  # patients 0..9999 of the same trial, full horizon
 
 
+PROFILE = os.path.join(ROOT, "profiles", "simulate_kernel_paper_scale_1M_x_364d.md")
+
+
+def measured_traffic():
+    """HBM bytes per simulate launch from the committed counter summary (FETCH_SIZE +
+    WRITE_SIZE, scaled by a 1 GiB copy), or None once the kernel sources have changed
+    since those counters were taken."""
+    import glob
+    import hashlib
+    try:
+        txt = open(PROFILE).read()
+    except OSError:
+        return None
+    fields = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith(("traffic_bytes", "kernel_source")))
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_13927_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -145,6 +167,7 @@ def main() -> int:
     value = pdays * args.steps / dt
     kern_s = sum(sim_ms) / len(sim_ms) / 1e3
     achieved = FLOP_PER_PATIENT_DAY * pdays / kern_s
+    traffic = measured_traffic() if (n, days) == (1_000_000, 364) else None
     out = {
         "metric": "patient-days simulated/s (1 GPU)",
         "value": value,
@@ -162,7 +185,9 @@ def main() -> int:
                                "FP32 state / FP64 metrics, 3 meals + 20% snack", "patients": n, "days": days,
                    "parallelism": "one patient per lane, 1 GPU"},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "frac": achieved / PEAK_FP32, "traffic": traffic,
+                     "traffic_unit": "bytes per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "algorithmic_bytes": 208 * n,
                      "kernel": "simulate_kernel<float, PID, noisy>", "kernel_ms": kern_s * 1e3,
                      "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
                      "flop_per_patient_day": FLOP_PER_PATIENT_DAY},
