@@ -29,6 +29,22 @@ class OrcConfig(C.Structure):
         ("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("sigma_q1", C.c_double),
         ("cgm_var", C.c_double), ("noise_seed", C.c_uint64), ("integrator", C.c_int32), ("rk4_sub", C.c_int32),
         ("x0_offset", C.c_double * NX), ("guard_rel", C.c_double),
+        ("mpc_horizon", C.c_int32), ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double),
+        ("mpc_riccati_iters", C.c_int32), ("mpc_power_iters", C.c_int32),
+    ]
+
+
+NMAX = 48
+
+
+class OrcMpc(C.Structure):
+    _fields_ = [
+        ("N", C.c_int32), ("A", C.c_double * (NX * NX)), ("B", C.c_double * NX), ("E", C.c_double * NX),
+        ("K", C.c_double * NX), ("h", C.c_double * NMAX), ("F", C.c_double * (NMAX * NX)), ("w", C.c_double * NMAX),
+        ("Gx", C.c_double * (NMAX * NX)), ("gd", C.c_double * NMAX), ("g1", C.c_double * NMAX),
+        ("lam", C.c_double), ("rho_p", C.c_double), ("step", C.c_double), ("xss", C.c_double * NX),
+        ("ub", C.c_double), ("umax", C.c_double), ("gstar", C.c_double), ("P", C.c_double * (NX * NX)),
+        ("P_change", C.c_double),
     ]
 
 
@@ -80,6 +96,11 @@ def lib() -> C.CDLL:
         L.orc_reduce.argtypes = [C.c_int64, C.c_int64, _P(C.c_int32), _P(C.c_int32), _P(C.c_double),
                                  _P(C.c_double), _P(C.c_int32), _P(C.c_uint32), _P(OrcSummary)]
         L.orc_meals.argtypes = [_P(OrcConfig), C.c_uint32, C.c_int32, _P(C.c_double)]
+        L.orc_jacobian.argtypes = [_P(OrcConfig), _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_double),
+                                   _P(C.c_double)]
+        L.orc_mpc_setup.argtypes = [_P(OrcConfig), _P(C.c_double), _P(OrcMpc)]
+        L.orc_mpc_setup.restype = C.c_int
+        L.orc_mpc_pg.argtypes = [_P(OrcMpc), _P(C.c_double), _P(C.c_double), C.c_int]
         L.orc_pid_run.argtypes = [_P(OrcConfig), C.c_double, C.c_int32, _P(C.c_double), _P(C.c_double),
                                   _P(C.c_double)]
         _lib = L
@@ -120,6 +141,11 @@ def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=N
         for i, v in enumerate(x0_offset):
             c.x0_offset[i] = float(v)
     c.guard_rel = float(guard_rel)
+    c.mpc_horizon = int(trial.get("mpc_horizon", 24))
+    c.mpc_iters = int(trial.get("mpc_iters", 50))
+    c.mpc_rho = float(trial.get("mpc_rho", 1.0))
+    c.mpc_riccati_iters = int(trial.get("mpc_riccati_iters", 500))
+    c.mpc_power_iters = int(trial.get("mpc_power_iters", 100))
     return c
 
 
@@ -192,6 +218,40 @@ def pid_run(trial: dict, u_b: float, y) -> tuple[np.ndarray, np.ndarray]:
     lib().orc_pid_run(C.byref(cfg), float(u_b), len(ya), _ptr(ya, C.c_double), _ptr(u, C.c_double),
                       _ptr(integ, C.c_double))
     return u, integ
+
+
+def jacobian(trial: dict, p, x):
+    cfg = config(trial)
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64)
+    J, Bc, Ec = np.zeros(NX * NX), np.zeros(NX), np.zeros(NX)
+    lib().orc_jacobian(C.byref(cfg), _ptr(pa, C.c_double), _ptr(xa, C.c_double), _ptr(J, C.c_double),
+                       _ptr(Bc, C.c_double), _ptr(Ec, C.c_double))
+    return J.reshape(NX, NX), Bc, Ec
+
+
+def mpc_setup(trial: dict, prm) -> dict:
+    """Per-patient MPC matrices from a sampled parameter row (length NPOUT)."""
+    cfg = config(trial)
+    pa = np.ascontiguousarray(prm, dtype=np.float64)
+    m = OrcMpc()
+    if not lib().orc_mpc_setup(C.byref(cfg), _ptr(pa, C.c_double), C.byref(m)):
+        raise ValueError("no basal state")
+    N = m.N
+    return {
+        "m": m, "N": N, "A": np.array(m.A).reshape(NX, NX), "B": np.array(m.B), "E": np.array(m.E),
+        "K": np.array(m.K), "h": np.array(m.h[:N]), "F": np.array(m.F).reshape(NMAX, NX)[:N],
+        "w": np.array(m.w[:N]), "Gx": np.array(m.Gx).reshape(NMAX, NX)[:N], "gd": np.array(m.gd[:N]),
+        "g1": np.array(m.g1[:N]), "lam": m.lam, "rho_p": m.rho_p, "step": m.step, "xss": np.array(m.xss),
+        "ub": m.ub, "umax": m.umax, "P": np.array(m.P).reshape(NX, NX), "P_change": m.P_change,
+    }
+
+
+def mpc_pg(setup: dict, g, dU0, iters: int) -> np.ndarray:
+    ga = np.ascontiguousarray(g, dtype=np.float64)
+    du = np.ascontiguousarray(dU0, dtype=np.float64).copy()
+    lib().orc_mpc_pg(C.byref(setup["m"]), _ptr(ga, C.c_double), _ptr(du, C.c_double), int(iters))
+    return du
 
 
 # ------------------------------------------------------------------ simulate

@@ -432,6 +432,283 @@ void orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *y, d
     }
 }
 
+/* ------------------------------------------------------------------- MPC ---- */
+/* Linear MPC in the kappa/lambda form of Sec. III-B: the control state is the Kalman
+ * estimate of the state deviation from the basal steady state and the planned input
+ * sequence; the control law solves a box-constrained quadratic program over N samples.
+ *  - model: the drift linearised at the basal state (x_ss, u_b, D = 0), discretised the
+ *    way the plant is integrated: M = I + hJ, A = M^E, B = h (I + M + ... + M^(E-1)) B_c,
+ *    E likewise, with E = em_per_ctrl Euler steps per sample;
+ *  - estimator: stationary Kalman filter for the sensor state GI, gain from a fixed
+ *    number of Riccati iterations with Q = 1e-6 I + sigma^2 h E e_Q1 e_Q1^T and
+ *    R = max(R_cgm, 1e-4);
+ *  - objective over the predicted true glucose G_(k+1..k+N):
+ *      sum_j (G_j - ybar)^2 + rho sum_i ((u_i - u_b)/u_b)^2,  0 <= u_i <= u_max,
+ *    the announced intake of the current interval known, later ones taken as zero;
+ *  - solver: mpc_iters projected-gradient steps of length 1/(lambda_max(G^T G) + rho/u_b^2),
+ *    warm-started from the previous plan shifted by one sample. */
+static void matmul(const double *X, const double *Y, double *Z)
+{
+    double T[ORC_NX * ORC_NX];
+    for (int r = 0; r < ORC_NX; ++r)
+        for (int c = 0; c < ORC_NX; ++c) {
+            double acc = 0.0;
+            for (int q = 0; q < ORC_NX; ++q)
+                acc += X[r * ORC_NX + q] * Y[q * ORC_NX + c];
+            T[r * ORC_NX + c] = acc;
+        }
+    memcpy(Z, T, sizeof T);
+}
+
+void orc_jacobian(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_NX], double J[ORC_NX * ORC_NX],
+                  double Bc[ORC_NX], double Ec[ORC_NX])
+{
+    double bw = p[P_BW];
+    double egp0 = p[P_EGP0] * bw, f01 = p[P_F01] * bw;
+    double vi = p[P_VI] * bw, vg = p[P_VG] * bw;
+    double tg = p[P_TMAXG], ti = p[P_TMAXI];
+    memset(J, 0, sizeof(double) * ORC_NX * ORC_NX);
+    memset(Bc, 0, sizeof(double) * ORC_NX);
+    memset(Ec, 0, sizeof(double) * ORC_NX);
+#define JJ(r, c) J[(r) * ORC_NX + (c)]
+    JJ(X_D1, X_D1) = -1.0 / tg;
+    JJ(X_D2, X_D1) = 1.0 / tg;
+    JJ(X_D2, X_D2) = -1.0 / tg;
+    JJ(X_S1, X_S1) = -1.0 / ti;
+    JJ(X_S2, X_S1) = 1.0 / ti;
+    JJ(X_S2, X_S2) = -1.0 / ti;
+    JJ(X_I, X_S2) = 1.0 / (ti * vi);
+    JJ(X_I, X_I) = -p[P_KE];
+    JJ(X_X1, X_I) = p[P_KA1] * p[P_SIT];
+    JJ(X_X1, X_X1) = -p[P_KA1];
+    JJ(X_X2, X_I) = p[P_KA2] * p[P_SID];
+    JJ(X_X2, X_X2) = -p[P_KA2];
+    JJ(X_X3, X_I) = p[P_KA3] * p[P_SIE];
+    JJ(X_X3, X_X3) = -p[P_KA3];
+    double G = x[X_Q1] / vg;
+    double df01c = G < 4.5 ? f01 / (4.5 * vg) : 0.0;
+    double dfr = G > 9.0 ? 0.003 : 0.0;
+    JJ(X_Q1, X_D2) = 1.0 / tg;
+    JJ(X_Q1, X_X1) = -x[X_Q1];
+    JJ(X_Q1, X_X3) = x[X_X3] < 1.0 ? -egp0 : 0.0;
+    JJ(X_Q1, X_Q1) = -x[X_X1] - df01c - dfr;
+    JJ(X_Q1, X_Q2) = p[P_K12];
+    JJ(X_Q2, X_X1) = x[X_Q1];
+    JJ(X_Q2, X_X2) = -x[X_Q2];
+    JJ(X_Q2, X_Q1) = x[X_X1];
+    JJ(X_Q2, X_Q2) = -(p[P_K12] + x[X_X2]);
+    JJ(X_GI, X_Q1) = 1.0 / (cfg->tau_cgm * vg);
+    JJ(X_GI, X_GI) = -1.0 / cfg->tau_cgm;
+#undef JJ
+    Bc[X_S1] = 1.0;
+    Ec[X_D1] = cfg->ag;
+}
+
+int orc_mpc_setup(const orc_config *cfg, const double prm[ORC_NPOUT], orc_mpc *m)
+{
+    memset(m, 0, sizeof *m);
+    double istar, ub;
+    if (!orc_basal(cfg, prm, &istar, &ub, m->xss))
+        return 0;
+    const int N = cfg->mpc_horizon;
+    const int E = cfg->em_per_ctrl;
+    const double h = (double)cfg->ts_min / (double)E;
+    const double vg = prm[P_VG] * prm[P_BW];
+    m->N = N;
+    m->ub = ub;
+    m->umax = cfg->umax_rel * ub;
+    m->gstar = cfg->g_target;
+
+    double J[ORC_NX * ORC_NX], Bc[ORC_NX], Ec[ORC_NX], Mx[ORC_NX * ORC_NX], S[ORC_NX * ORC_NX], Pw[ORC_NX * ORC_NX];
+    orc_jacobian(cfg, prm, m->xss, J, Bc, Ec);
+    for (int i = 0; i < ORC_NX * ORC_NX; ++i)
+        Mx[i] = h * J[i];
+    for (int i = 0; i < ORC_NX; ++i)
+        Mx[i * ORC_NX + i] += 1.0;
+    /* A = M^E, S = I + M + ... + M^(E-1) */
+    memset(Pw, 0, sizeof Pw);
+    memset(S, 0, sizeof S);
+    for (int i = 0; i < ORC_NX; ++i)
+        Pw[i * ORC_NX + i] = 1.0;
+    for (int e = 0; e < E; ++e) {
+        for (int i = 0; i < ORC_NX * ORC_NX; ++i)
+            S[i] += Pw[i];
+        matmul(Pw, Mx, Pw);
+    }
+    memcpy(m->A, Pw, sizeof Pw);
+    for (int r = 0; r < ORC_NX; ++r) {
+        double b = 0.0, d = 0.0;
+        for (int c = 0; c < ORC_NX; ++c) {
+            b += S[r * ORC_NX + c] * Bc[c];
+            d += S[r * ORC_NX + c] * Ec[c];
+        }
+        m->B[r] = h * b;
+        m->E[r] = h * d;
+    }
+
+    /* Kalman: prior covariance P <- A (P - P c^T c P / (c P c^T + R)) A^T + Q, c = e_GI */
+    double Q[ORC_NX * ORC_NX], P[ORC_NX * ORC_NX], T[ORC_NX * ORC_NX], At[ORC_NX * ORC_NX];
+    memset(Q, 0, sizeof Q);
+    for (int i = 0; i < ORC_NX; ++i)
+        Q[i * ORC_NX + i] = 1e-6;
+    Q[X_Q1 * ORC_NX + X_Q1] += cfg->sigma_q1 * cfg->sigma_q1 * h * E;
+    const double R = cfg->cgm_var > 1e-4 ? cfg->cgm_var : 1e-4;
+    for (int r = 0; r < ORC_NX; ++r)
+        for (int c = 0; c < ORC_NX; ++c)
+            At[r * ORC_NX + c] = m->A[c * ORC_NX + r];
+    memcpy(P, Q, sizeof P);
+    for (int it = 0; it < cfg->mpc_riccati_iters; ++it) {
+        const double s = P[X_GI * ORC_NX + X_GI] + R;
+        for (int r = 0; r < ORC_NX; ++r)
+            for (int c = 0; c < ORC_NX; ++c)
+                T[r * ORC_NX + c] = P[r * ORC_NX + c] - P[r * ORC_NX + X_GI] * P[X_GI * ORC_NX + c] / s;
+        matmul(m->A, T, T);
+        matmul(T, At, T);
+        double change = 0.0;
+        for (int i = 0; i < ORC_NX * ORC_NX; ++i) {
+            double v = T[i] + Q[i];
+            change = fmax(change, fabs(v - P[i]));
+            P[i] = v;
+        }
+        m->P_change = change;
+    }
+    memcpy(m->P, P, sizeof P);
+    const double s = P[X_GI * ORC_NX + X_GI] + R;
+    for (int i = 0; i < ORC_NX; ++i)
+        m->K[i] = P[i * ORC_NX + X_GI] / s;
+
+    /* prediction of G = Q1/VG over N samples */
+    double row[ORC_NX], nrow[ORC_NX];
+    for (int i = 0; i < ORC_NX; ++i)
+        row[i] = i == X_Q1 ? 1.0 / vg : 0.0;          /* c_G A^0 */
+    for (int j = 0; j < N; ++j) {
+        double hb = 0.0, we = 0.0;
+        for (int i = 0; i < ORC_NX; ++i) {
+            hb += row[i] * m->B[i];
+            we += row[i] * m->E[i];
+        }
+        m->h[j] = hb;                                  /* h_(j+1) = c_G A^j B */
+        m->w[j] = we;                                  /* c_G A^j E */
+        for (int c = 0; c < ORC_NX; ++c) {
+            double acc = 0.0;
+            for (int q = 0; q < ORC_NX; ++q)
+                acc += row[q] * m->A[q * ORC_NX + c];
+            nrow[c] = acc;
+        }
+        memcpy(row, nrow, sizeof row);
+        for (int c = 0; c < ORC_NX; ++c)
+            m->F[j * ORC_NX + c] = row[c];             /* c_G A^(j+1) */
+    }
+    /* Gamma[j][i] = h[j - i] (i <= j); Gamma^T F, Gamma^T w, Gamma^T 1 */
+    for (int i = 0; i < N; ++i) {
+        double gd = 0.0, g1 = 0.0;
+        for (int c = 0; c < ORC_NX; ++c)
+            m->Gx[i * ORC_NX + c] = 0.0;
+        for (int j = i; j < N; ++j) {
+            double gji = m->h[j - i];
+            for (int c = 0; c < ORC_NX; ++c)
+                m->Gx[i * ORC_NX + c] += gji * m->F[j * ORC_NX + c];
+            gd += gji * m->w[j];
+            g1 += gji;
+        }
+        m->gd[i] = gd;
+        m->g1[i] = g1;
+    }
+    /* lambda_max(Gamma^T Gamma) by power iteration from the all-ones vector */
+    double v[ORC_NMAX], t[ORC_NMAX], lam = 0.0;
+    for (int i = 0; i < N; ++i)
+        v[i] = 1.0 / sqrt((double)N);
+    for (int it = 0; it < cfg->mpc_power_iters; ++it) {
+        for (int j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i <= j; ++i)
+                acc += m->h[j - i] * v[i];
+            t[j] = acc;
+        }
+        double nrm = 0.0;
+        for (int i = 0; i < N; ++i) {
+            double acc = 0.0;
+            for (int j = i; j < N; ++j)
+                acc += m->h[j - i] * t[j];
+            v[i] = acc;
+            nrm += acc * acc;
+        }
+        nrm = sqrt(nrm);
+        lam = nrm;
+        if (nrm > 0.0)
+            for (int i = 0; i < N; ++i)
+                v[i] /= nrm;
+    }
+    m->lambda = lam;
+    m->rho_p = cfg->mpc_rho / (ub * ub);
+    m->step = 1.0 / (lam + m->rho_p);
+    return 1;
+}
+
+void orc_mpc_pg(const orc_mpc *m, const double g[], double dU[], int iters)
+{
+    const int N = m->N;
+    const double lo = -m->ub, hi = m->umax - m->ub;
+    double r[ORC_NMAX];
+    for (int it = 0; it < iters; ++it) {
+        for (int j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int i = 0; i <= j; ++i)
+                acc += m->h[j - i] * dU[i];
+            r[j] = acc;                                /* Gamma dU */
+        }
+        double nu[ORC_NMAX];
+        for (int i = 0; i < N; ++i) {
+            double acc = 0.0;
+            for (int j = i; j < N; ++j)
+                acc += m->h[j - i] * r[j];             /* Gamma^T Gamma dU */
+            double grad = acc + m->rho_p * dU[i] + g[i];
+            double x = dU[i] - m->step * grad;
+            nu[i] = x < lo ? lo : (x > hi ? hi : x);
+        }
+        memcpy(dU, nu, sizeof(double) * N);
+    }
+}
+
+typedef struct {
+    orc_mpc m;
+    double xh[ORC_NX];     /* estimate of x - x_ss (prior before the measurement update) */
+    double dU[ORC_NMAX];   /* planned u - u_b */
+} mpc_state;
+
+static double mpc_step(const orc_config *cfg, mpc_state *st, double y, double dhat)
+{
+    orc_mpc *m = &st->m;
+    const int N = m->N;
+    /* measurement update with the sensor deviation y - GI_ss */
+    double innov = (y - m->xss[X_GI]) - st->xh[X_GI];
+    for (int i = 0; i < ORC_NX; ++i)
+        st->xh[i] += m->K[i] * innov;
+    /* linear term of the QP: Gamma^T (F xh + w dhat + (G* - ybar)) */
+    double g[ORC_NMAX];
+    for (int i = 0; i < N; ++i) {
+        double acc = m->gd[i] * dhat + m->g1[i] * (m->gstar - cfg->setpoint);
+        for (int c = 0; c < ORC_NX; ++c)
+            acc += m->Gx[i * ORC_NX + c] * st->xh[c];
+        g[i] = acc;
+    }
+    /* warm start: previous plan shifted by one sample */
+    for (int i = 0; i + 1 < N; ++i)
+        st->dU[i] = st->dU[i + 1];
+    orc_mpc_pg(m, g, st->dU, cfg->mpc_iters);
+    const double du = st->dU[0];
+    /* time update with the applied input and the announced intake */
+    double nx[ORC_NX];
+    for (int r = 0; r < ORC_NX; ++r) {
+        double acc = m->B[r] * du + m->E[r] * dhat;
+        for (int c = 0; c < ORC_NX; ++c)
+            acc += m->A[r * ORC_NX + c] * st->xh[c];
+        nx[r] = acc;
+    }
+    memcpy(st->xh, nx, sizeof nx);
+    return m->ub + du;
+}
+
 /* ------------------------------------------------------------ main loop ---- */
 static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient, const orc_outputs *out)
 {
@@ -468,6 +745,14 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
     const double vg = p[P_VG] * p[P_BW];
     pid_t_ pid = {0.0, 0.0, 0};
     int is_traj = j < out->n_traj;
+    mpc_state *mpc = NULL;
+    if (cfg->ctrl_kind == ORC_CTRL_MPC) {
+        mpc = (mpc_state *)calloc(1, sizeof *mpc);
+        if (!orc_mpc_setup(cfg, prm, &mpc->m)) {
+            free(mpc);
+            mpc = NULL;
+        }
+    }
 
     for (int32_t day = 0; day < cfg->n_days; ++day) {
         meal_t meals[ORC_MAX_SLOTS];
@@ -492,16 +777,18 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
             }
             double y = x[X_GI] + sqrt_r * z[M];
 
-            double u;
-            if (cfg->ctrl_kind == ORC_CTRL_PID)
-                u = pid_step(cfg, &pid, y, ub, &a.ctrl_margin);
-            else
-                u = cfg->u_rel * ub;
-
-            double d = 0.0;
+            double d = 0.0;   /* held intake of this interval, also the announcement */
             for (int m = 0; m < nm; ++m)
                 if (meals[m].kd == kd)
                     d += meals[m].rate;
+
+            double u;
+            if (cfg->ctrl_kind == ORC_CTRL_PID)
+                u = pid_step(cfg, &pid, y, ub, &a.ctrl_margin);
+            else if (cfg->ctrl_kind == ORC_CTRL_MPC)
+                u = mpc ? mpc_step(cfg, mpc, y, d) : NAN;
+            else
+                u = cfg->u_rel * ub;
 
             if (is_traj) {
                 if (out->traj_g) out->traj_g[j * K + k] = G;
@@ -529,6 +816,7 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
             if (!isfinite(x[i]))
                 a.status |= ORC_ST_NONFINITE;
     }
+    free(mpc);
 
     for (int b = 0; b < 5; ++b) out->bins[j * 5 + b] = a.bins[b];
     for (int e = 0; e < 3; ++e) out->events[j * 3 + e] = a.events[e];
@@ -568,6 +856,10 @@ int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_thre
         if (cfg->minute_of_day[m] - cfg->jitter < 0 || cfg->minute_of_day[m] + cfg->jitter >= 1440)
             return -1;
     if (cfg->integrator == ORC_INT_RK4 && (cfg->sigma_q1 != 0.0 || cfg->cgm_var != 0.0 || cfg->rk4_sub < 1))
+        return -1;
+    if (cfg->ctrl_kind == ORC_CTRL_MPC &&
+        (cfg->mpc_horizon < 1 || cfg->mpc_horizon > ORC_NMAX || cfg->mpc_iters < 0 || cfg->mpc_riccati_iters < 0 ||
+         cfg->mpc_power_iters < 1 || !(cfg->mpc_rho > 0.0)))
         return -1;
     if (n_threads < 1)
         n_threads = 1;

@@ -82,7 +82,30 @@ typedef struct {
     int32_t  rk4_sub;
     double   x0_offset[ORC_NX]; /* added to the basal steady state (tests only) */
     double   guard_rel;         /* band used for the near-decision diagnostics */
+    /* linear MPC */
+    int32_t  mpc_horizon;       /* N (prediction = control horizon), <= ORC_NMAX */
+    int32_t  mpc_iters;         /* projected-gradient iterations per sample */
+    double   mpc_rho;           /* weight of ((u - u_b)/u_b)^2 */
+    int32_t  mpc_riccati_iters; /* fixed Riccati iterations for the stationary Kalman gain */
+    int32_t  mpc_power_iters;   /* power iterations for lambda_max(Gamma^T Gamma) */
 } orc_config;
+
+#define ORC_NMAX 48
+
+/* Per-patient linear MPC (Sec. III-B form, control state = Kalman estimate + input plan). */
+typedef struct {
+    int32_t N;
+    double A[ORC_NX * ORC_NX], B[ORC_NX], E[ORC_NX];   /* sample-to-sample linear model */
+    double K[ORC_NX];                                   /* stationary Kalman gain (sensor GI) */
+    double h[ORC_NMAX];                                 /* Markov parameters c_G A^(m-1) B, m = 1..N */
+    double F[ORC_NMAX * ORC_NX];                        /* rows c_G A^(j+1), j = 0..N-1 */
+    double w[ORC_NMAX];                                 /* c_G A^j E: response to the announced intake */
+    double Gx[ORC_NMAX * ORC_NX], gd[ORC_NMAX], g1[ORC_NMAX];   /* Gamma^T F, Gamma^T w, Gamma^T 1 */
+    double lambda, rho_p, step;                         /* lambda_max(Gamma^T Gamma), rho/u_b^2, 1/(lambda+rho_p) */
+    double xss[ORC_NX], ub, umax, gstar;
+    double P[ORC_NX * ORC_NX];                          /* prior covariance at the last Riccati iteration */
+    double P_change;                                    /* max |P_n - P_(n-1)| of the last iteration */
+} orc_mpc;
 
 typedef struct {
     int32_t  *bins;        /* [count][5] samples per glucose range          */
@@ -118,6 +141,14 @@ void     orc_rhs(const orc_config *cfg, const double p[ORC_NP], const double x[O
    in the day, carbs g, jitter min); a PID run over a scripted measurement sequence. */
 void     orc_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out);
 void     orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *y, double *u, double *integ);
+
+/* Linear MPC. Jacobian of the drift at (x, u, D = 0); B_c = df/du, E_c = df/dD. */
+void     orc_jacobian(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_NX], double J[ORC_NX * ORC_NX],
+                      double Bc[ORC_NX], double Ec[ORC_NX]);
+/* Setup from a sampled parameter row ([ORC_NPOUT]); returns 0 if the basal state does not exist. */
+int      orc_mpc_setup(const orc_config *cfg, const double prm[ORC_NPOUT], orc_mpc *m);
+/* Projected-gradient iterations on the box QP from the start dU (overwritten). */
+void     orc_mpc_pg(const orc_mpc *m, const double g[], double dU[], int iters);
 
 /* Closed-loop Monte Carlo for patients [first, first+count) on n_threads threads. */
 int      orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out);

@@ -59,6 +59,10 @@ def base_trial() -> dict:
         "kd": 30.0,
         "umax_rel": 3.0,
         "u_rel": 1.0,
+        # linear MPC: horizon 24 samples, 50 projected-gradient iterations, input weight
+        "mpc_horizon": 24,
+        "mpc_iters": 50,
+        "mpc_rho": 1.0,
         # (3) model + simulation settings
         "n_days": 7,
         "em_per_ctrl": 5,
@@ -98,6 +102,21 @@ def c3_paper_scale() -> dict:
     """1,000,000 patients x 364 days, plus a 21:00 snack with probability 0.2, N(20, 5) g."""
     return with_(base_trial(), n_patients=1_000_000, n_days=364, pop_seed=2, noise_seed=2, precision=FP32,
                  n_slots=4, prob=[1.0, 1.0, 1.0, 0.2])
+
+
+def c5_mpc(seed: int = 5) -> dict:
+    """Learned-controller trial, exact-MPC arm: 1,000,000 patients x 364 days, FP32, linear MPC
+    (24-sample horizon, 50 projected-gradient steps), u_max = 3 u_b. The population keeps
+    only parameter sets with a basal rate >= 0.4 U/h (the paper's acceptance rule), which
+    removes patients whose basal need is near zero."""
+    return with_(base_trial(), n_patients=1_000_000, n_days=364, pop_seed=seed, noise_seed=seed, precision=FP32,
+                 pop_flags=1, ctrl_kind=CTRL_MPC)
+
+
+def mlp_training_population(seed: int = 100) -> dict:
+    """Separate population whose MPC closed loop produces the training pairs:
+    5,000 patients x 7 days = 10.08 M (features, action) pairs."""
+    return with_(c5_mpc(seed), n_patients=5_000, n_days=7)
 
 
 GAIN_MULTIPLIERS = (0.5, 0.75, 1.0, 1.5)
