@@ -94,16 +94,26 @@ typedef struct {
     int32_t jitter_min;                     /* 0..120                              */
 } vct_protocol;
 
-/* (5) controller -- Sec. III-B. PID on the sensor value y_k, gains relative to the
- * patient's basal rate u_b:
+/* (5) controller -- Sec. III-B (x^c_{k+1} = kappa(x^c_k, y_k, ...), u_k = lambda(...)).
+ * PID on the sensor value y_k, gains relative to the patient's basal rate u_b:
  *   u_k = clamp(u_b + kp u_b e + ki u_b I_k + kd u_b (y_k - y_{k-1})/Ts, 0, umax_rel u_b),
- *   e = y_k - setpoint, I_{k+1} = I_k + e Ts only while the unclamped value is in range. */
+ *   e = y_k - setpoint, I_{k+1} = I_k + e Ts only while the unclamped value is in range.
+ * Linear MPC (control state: Kalman estimate of x - x_ss and the planned inputs): each
+ * sample corrects the estimate with y_k, minimises
+ *   sum_{j=1..N} (G_{k+j} - setpoint)^2 + mpc_rho sum_{i=0..N-1} ((u_i - u_b)/u_b)^2,
+ *   0 <= u_i <= umax_rel u_b, with the intake of the current interval announced,
+ * by mpc_iters projected-gradient steps warm-started from the shifted previous plan,
+ * applies u_0 and predicts. The per-patient matrices come from vct_mpc_setup. */
 typedef struct {
     int32_t kind;          /* VCT_CTRL_*                                           */
     double  setpoint;      /* mmol/L                                               */
     double  kp, ki, kd;    /* u_b/(mmol/L), u_b/(mmol/L min), u_b min/(mmol/L)     */
     double  umax_rel;      /* > 0                                                  */
     double  u_rel;         /* open-loop mode: u = u_rel u_b                        */
+    int32_t mpc_horizon;   /* N; this build supports 24                             */
+    int32_t mpc_iters;     /* projected-gradient iterations per sample, 0..1000     */
+    double  mpc_rho;       /* > 0                                                   */
+    const void *mpc_dev;   /* VCT_CTRL_MPC: buffer filled by vct_mpc_setup          */
 } vct_controller;
 
 /* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl
@@ -194,6 +204,18 @@ vct_status  vct_create_population(const vct_population_desc *desc, void *params_
 /* Closed-loop Monte Carlo of every patient of the population (Sec. III). */
 vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol, const vct_controller *ctrl,
                          const vct_sim *sim, void *stream);
+/* Linear MPC setup for every patient of the population (FP64 computation): the drift
+ * linearised at the basal state and discretised like the plant (A = (I + hJ)^E, B, E
+ * over the E Euler steps of a sample), the stationary Kalman gain for the sensor state
+ * (500 Riccati iterations, Q = 1e-6 I + sigma^2 h E on Q1, R = max(cgm_var, 1e-4)), the
+ * 24-sample prediction condensed to Gamma^T F, Gamma^T w, Gamma^T 1, the Markov
+ * parameters and the step 1/(lambda_max(Gamma^T Gamma) + rho/u_b^2) (100 power
+ * iterations). mpc_dev: caller buffer of vct_mpc_bytes(n, precision) bytes, SoA rows of
+ * the working precision; sim->precision must equal the precision later simulated, and
+ * ctrl->umax_rel / mpc_rho are baked in. */
+size_t      vct_mpc_bytes(int64_t n_patients, int32_t precision);
+vct_status  vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, const vct_sim *sim, void *mpc_dev,
+                          void *stream);
 /* Reduce the per-patient metrics of n patients with K samples each into *host_out. */
 vct_status  vct_read_metrics(const void *metrics_dev, int64_t n_patients, int64_t n_samples,
                              vct_summary *host_out, void *stream);

@@ -11,6 +11,7 @@
 
 #include "../../include/vct.h"
 #include "internal.hpp"
+#include "mpc.hpp"
 
 struct vct_population {
     int64_t n;
@@ -167,10 +168,18 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     const int64_t K = (int64_t)sim->n_days * (1440 / sim->ts_min);
     if (K >= ((int64_t)1 << 31))
         return fail(VCT_EINVAL, "horizon too long");
-    if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID) {
-        if (ctrl->kind == VCT_CTRL_MPC || ctrl->kind == VCT_CTRL_MLP)
+    if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_MPC) {
+        if (ctrl->kind == VCT_CTRL_MLP)
             return fail(VCT_ENOTSUP, "controller kind %d not in this entry point", ctrl->kind);
         return fail(VCT_EINVAL, "controller kind %d", ctrl->kind);
+    }
+    if (ctrl->kind == VCT_CTRL_MPC) {
+        if (!ctrl->mpc_dev)
+            return fail(VCT_EINVAL, "MPC controller needs mpc_dev (from vct_mpc_setup)");
+        if (ctrl->mpc_horizon != vct::kMpcN)
+            return fail(VCT_ENOTSUP, "MPC horizon %d (this build: %d)", ctrl->mpc_horizon, vct::kMpcN);
+        if (ctrl->mpc_iters < 0 || ctrl->mpc_iters > 1000)
+            return fail(VCT_EINVAL, "mpc_iters %d out of [0, 1000]", ctrl->mpc_iters);
     }
     if (!(std::isfinite(ctrl->setpoint) && std::isfinite(ctrl->kp) && std::isfinite(ctrl->ki) &&
           std::isfinite(ctrl->kd) && finite_pos(ctrl->umax_rel) && std::isfinite(ctrl->u_rel) && ctrl->u_rel >= 0))
@@ -206,6 +215,8 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.kd = ctrl->kd;
     a.umax_rel = ctrl->umax_rel;
     a.u_rel = ctrl->u_rel;
+    a.mpc = ctrl->kind == VCT_CTRL_MPC ? ctrl->mpc_dev : nullptr;
+    a.mpc_iters = ctrl->mpc_iters;
     a.ts_min = sim->ts_min;
     a.em_per_ctrl = sim->em_per_ctrl;
     a.h = (double)sim->ts_min / (double)sim->em_per_ctrl;
@@ -240,6 +251,49 @@ vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const
     hipError_t e = vct::launch_simulate(a, sim->precision, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "vct_simulate: launch");
+    return VCT_OK;
+}
+
+size_t vct_mpc_bytes(int64_t n, int32_t precision)
+{
+    if (n <= 0 || (precision != VCT_FP64 && precision != VCT_FP32))
+        return 0;
+    return (size_t)n * vct::kMRows * (precision == VCT_FP32 ? sizeof(float) : sizeof(double));
+}
+
+vct_status vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, const vct_sim *sim, void *mpc_dev,
+                         void *stream)
+{
+    g_err.clear();
+    if (!pop || !ctrl || !sim || !mpc_dev)
+        return fail(VCT_EINVAL, "vct_mpc_setup: null argument");
+    if (ctrl->mpc_horizon != vct::kMpcN)
+        return fail(VCT_ENOTSUP, "vct_mpc_setup: horizon %d (this build: %d)", ctrl->mpc_horizon, vct::kMpcN);
+    if (!(finite_pos(ctrl->mpc_rho) && finite_pos(ctrl->umax_rel)))
+        return fail(VCT_EINVAL, "vct_mpc_setup: mpc_rho and umax_rel must be finite and > 0");
+    if (sim->precision != VCT_FP64 && sim->precision != VCT_FP32)
+        return fail(VCT_EINVAL, "vct_mpc_setup: precision %d", sim->precision);
+    if (sim->ts_min < 1 || 1440 % sim->ts_min != 0 || sim->em_per_ctrl < 1 || sim->em_per_ctrl > 64)
+        return fail(VCT_EINVAL, "vct_mpc_setup: ts_min / em_per_ctrl invalid");
+    if (!(std::isfinite(sim->sigma_q1) && sim->sigma_q1 >= 0.0 && std::isfinite(sim->cgm_var) && sim->cgm_var >= 0.0))
+        return fail(VCT_EINVAL, "vct_mpc_setup: sigma_q1 and cgm_var must be finite and >= 0");
+    vct::MpcSetupArgs a{};
+    a.params = pop->params;
+    a.n = pop->n;
+    a.h = (double)sim->ts_min / (double)sim->em_per_ctrl;
+    a.ag = pop->ag;
+    a.tau = pop->tau;
+    a.g_target = pop->g_target;
+    a.em_per_ctrl = sim->em_per_ctrl;
+    a.sigma_q1 = sim->sigma_q1;
+    a.cgm_var = sim->cgm_var;
+    a.rho = ctrl->mpc_rho;
+    a.umax_rel = ctrl->umax_rel;
+    a.riccati_iters = 500;
+    a.power_iters = 100;
+    hipError_t e = vct::launch_mpc_setup(a, sim->precision, mpc_dev, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_mpc_setup: launch");
     return VCT_OK;
 }
 

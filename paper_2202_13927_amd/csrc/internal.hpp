@@ -35,6 +35,8 @@ struct SimArgs {
     // controller
     int32_t ctrl;
     double setpoint, kp, ki, kd, umax_rel, u_rel;
+    const void *mpc;      // per-patient MPC data (SoA [kMRows][n], working precision) or null
+    int32_t mpc_iters;
     // integration
     int32_t ts_min, em_per_ctrl;
     double h, sig_sqh, sqrt_r;
@@ -64,10 +66,21 @@ struct BatchLaunch {
     bool noisy;
 };
 
+struct MpcSetupArgs {
+    const double *params;  // population buffer
+    int64_t n;
+    double h, ag, tau, g_target;
+    int32_t em_per_ctrl;
+    double sigma_q1, cgm_var;
+    double rho, umax_rel;
+    int32_t riccati_iters, power_iters;
+};
+
 // Launchers (kernels.hip). They only enqueue work; they return the launch error.
 hipError_t launch_population(const PopArgs &a, hipStream_t s);
 hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
+hipError_t launch_mpc_setup(const MpcSetupArgs &a, int precision, void *out, hipStream_t s);
 int batch_blocks_per_cu(int precision, int ctrl, bool noisy, int block);
 
 struct ReduceOut {

@@ -6,6 +6,7 @@
 // record once. Noise is drawn in the loop from Philox counters, never stored.
 #include "internal.hpp"
 #include "model.hpp"
+#include "mpc.hpp"
 #include "rng.hpp"
 
 namespace vct {
@@ -86,7 +87,7 @@ hipError_t launch_population(const PopArgs &a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- simulation ----
-enum { kCtrlOpen = 0, kCtrlPid = 1 };
+enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2 };
 
 // Meals of one (patient, day): Philox block (day, patient, MEAL, slot) gives
 // carbs = max(0, mean + sd z) (cosine normal of u0, u1), integer jitter
@@ -160,7 +161,7 @@ template <typename R> struct CtrlConst {
 template <typename R, int CTRL, bool TRAJ>
 __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t kk, int32_t k, const R *z,
                                             State<R> &s, const StepConst<R> &c, const CtrlConst<R> &cc,
-                                            DayMeals<R> &ml, Lane<R> &L)
+                                            DayMeals<R> &ml, Lane<R> &L, MpcLane<R> &mp)
 {
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
@@ -184,6 +185,15 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
 
     const R y = fmaf_t(s.GIs, c.gi_scale, z[5]);   // y_k = g(x(t_k)) + v_k
 
+    R dr = R(0);   // held meal input of this interval (also the MPC's announcement)
+    if (kk == ml.k0) {
+        dr = ml.r0;
+        ml.k0 = ml.k1; ml.r0 = ml.r1;
+        ml.k1 = ml.k2; ml.r1 = ml.r2;
+        ml.k2 = ml.k3; ml.r2 = ml.r3;
+        ml.k3 = -1;
+    }
+
     R u;
     if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
         if (k == 0)
@@ -194,17 +204,10 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
         if (u_unc >= R(0) && u_unc <= cc.umax)
             L.integ += e * cc.ts;
         L.y_prev = y;
+    } else if (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
+        u = mpc_step<R>((const R *)a.mpc, a.n, j, mp, y, dr, R(a.g_target - a.setpoint), a.mpc_iters);
     } else {
         u = cc.u_open;
-    }
-
-    R dr = R(0);   // held meal input of this interval
-    if (kk == ml.k0) {
-        dr = ml.r0;
-        ml.k0 = ml.k1; ml.r0 = ml.r1;
-        ml.k1 = ml.k2; ml.r1 = ml.r2;
-        ml.k2 = ml.k3; ml.r2 = ml.r3;
-        ml.k3 = -1;
     }
     if (TRAJ && j < a.n_traj) {
         a.traj[(0 * (int64_t)a.n_traj + j) * a.K + k] = (double)G;
@@ -245,6 +248,10 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
     }
     StepConst<R> c;
     step_constants<R>(p, a.h, a.tau, a.ag, c);
+
+    MpcLane<R> mp;
+    if (CTRL == kCtrlMpc)
+        mpc_load<R>((const R *)a.mpc, a.n, j, mp);
 
     CtrlConst<R> cc;   // gains relative to u_b
     cc.kp = R(a.kp * ub_d);
@@ -290,8 +297,8 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
                 for (int q = 0; q < 12; ++q)
                     z[q] = R(0);
             }
-            sample_step<R, CTRL, TRAJ>(a, j, kk, k, z, s, c, cc, ml, L);
-            sample_step<R, CTRL, TRAJ>(a, j, kk + 1, k + 1, z + 6, s, c, cc, ml, L);
+            sample_step<R, CTRL, TRAJ>(a, j, kk, k, z, s, c, cc, ml, L, mp);
+            sample_step<R, CTRL, TRAJ>(a, j, kk + 1, k + 1, z + 6, s, c, cc, ml, L, mp);
         }
         if (!all_finite(s))
             L.status |= kStNonFinite;
@@ -440,14 +447,20 @@ static hipError_t launch_sim_t(const SimArgs &a, bool noisy, hipStream_t s)
     return hipGetLastError();
 }
 
+template <typename R>
+static hipError_t launch_sim_r(const SimArgs &a, bool noisy, hipStream_t s)
+{
+    switch (a.ctrl) {
+    case kCtrlPid: return launch_sim_t<R, kCtrlPid>(a, noisy, s);
+    case kCtrlMpc: return launch_sim_t<R, kCtrlMpc>(a, noisy, s);
+    default: return launch_sim_t<R, kCtrlOpen>(a, noisy, s);
+    }
+}
+
 hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s)
 {
     const bool noisy = a.sig_sqh != 0.0 || a.sqrt_r != 0.0;
-    if (precision == 1)
-        return a.ctrl == kCtrlPid ? launch_sim_t<float, kCtrlPid>(a, noisy, s)
-                                  : launch_sim_t<float, kCtrlOpen>(a, noisy, s);
-    return a.ctrl == kCtrlPid ? launch_sim_t<double, kCtrlPid>(a, noisy, s)
-                              : launch_sim_t<double, kCtrlOpen>(a, noisy, s);
+    return precision == 1 ? launch_sim_r<float>(a, noisy, s) : launch_sim_r<double>(a, noisy, s);
 }
 
 }  // namespace vct

@@ -21,15 +21,23 @@ class TrialBuffers:
         self.traj_patients = int(traj_patients)
         tb = vct.vct_traj_bytes(self.traj_patients, int(trial["n_days"]), int(trial["ts_min"]))
         self.traj = torch.empty(tb // 8, dtype=torch.float64, device=device) if tb else None
+        self.mpc = None
+        if int(trial["ctrl_kind"]) == vct.VCT_CTRL_MPC:
+            self.mpc = torch.empty(vct.vct_mpc_bytes(n, int(trial["precision"])), dtype=torch.uint8, device=device)
 
 
 def create_population(trial: dict, bufs: TrialBuffers, stream=None):
     return vct.vct_create_population(vct.population_desc(trial), bufs.params, stream)
 
 
+def mpc_setup(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
+    sim = vct.sim_settings(trial, bufs.metrics)
+    vct.vct_mpc_setup(pop, vct.controller(trial), sim, bufs.mpc, stream)
+
+
 def simulate(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
     sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj)
-    vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial), sim, stream)
+    vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial, bufs.mpc), sim, stream)
 
 
 def read_metrics(bufs: TrialBuffers, stream=None) -> dict:
@@ -41,6 +49,8 @@ def run(trial: dict, device="cuda", traj_patients: int = 0, stream=None, bufs: T
     bufs = bufs or TrialBuffers(trial, device, traj_patients)
     pop = create_population(trial, bufs, stream)
     try:
+        if bufs.mpc is not None:
+            mpc_setup(trial, pop, bufs, stream)
         simulate(trial, pop, bufs, stream)
         summary = read_metrics(bufs, stream)
     finally:
@@ -60,6 +70,24 @@ def to_host(bufs: TrialBuffers) -> dict:
     if bufs.traj is not None:
         t = bufs.traj.view(3, bufs.traj_patients, bufs.K).cpu().numpy()
         out["traj_g"], out["traj_y"], out["traj_u"] = t[0], t[1], t[2]
+    return out
+
+
+MPC_ROWS = 11 * 11 + 3 * 11 + 24 * 11 + 3 * 24 + 5   # layout of csrc/mpc.hpp
+
+
+def mpc_to_host(bufs: TrialBuffers, precision: int) -> dict:
+    """Per-patient MPC data (numpy), rows named as in the oracle."""
+    import numpy as np
+    torch.cuda.synchronize()
+    dt = torch.float32 if precision == vct.VCT_FP32 else torch.float64
+    M = bufs.mpc.view(dt).view(MPC_ROWS, bufs.n).cpu().numpy().astype(np.float64)
+    o = 0
+    out = {}
+    for name, rows in (("A", 121), ("B", 11), ("E", 11), ("K", 11), ("Gx", 264), ("gd", 24), ("g1", 24), ("h", 24),
+                       ("step", 1), ("rho_p", 1), ("gi", 1), ("ub", 1), ("umax", 1)):
+        out[name] = M[o:o + rows].T
+        o += rows
     return out
 
 

@@ -40,7 +40,8 @@ class vct_protocol(C.Structure):
 
 class vct_controller(C.Structure):
     _fields_ = [("kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
-                ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double)]
+                ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double), ("mpc_horizon", C.c_int32),
+                ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double), ("mpc_dev", C.c_void_p)]
 
 
 class vct_sim(C.Structure):
@@ -89,7 +90,8 @@ class VctError(RuntimeError):
 # every symbol include/vct.h declares
 EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_metrics_bytes", "vct_traj_bytes",
            "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population",
-           "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy")
+           "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy", "vct_mpc_bytes",
+           "vct_mpc_setup")
 
 _lib = None
 
@@ -128,6 +130,10 @@ def lib() -> C.CDLL:
         L.vct_batch_info.restype = C.c_int
         L.vct_batch_destroy.argtypes = [C.c_void_p]
         L.vct_batch_destroy.restype = None
+        L.vct_mpc_bytes.argtypes = [C.c_int64, C.c_int32]
+        L.vct_mpc_bytes.restype = C.c_size_t
+        L.vct_mpc_setup.argtypes = [C.c_void_p, C.POINTER(vct_controller), C.POINTER(vct_sim), C.c_void_p, C.c_void_p]
+        L.vct_mpc_setup.restype = C.c_int
         _lib = L
     return _lib
 
@@ -198,6 +204,14 @@ def vct_destroy_population(pop) -> None:
         lib().vct_destroy_population(pop)
 
 
+def vct_mpc_bytes(n: int, precision: int) -> int:
+    return lib().vct_mpc_bytes(n, precision)
+
+
+def vct_mpc_setup(pop, ctrl: vct_controller, sim: vct_sim, mpc_dev, stream=None) -> None:
+    _check("vct_mpc_setup", lib().vct_mpc_setup(pop, C.byref(ctrl), C.byref(sim), _ptr(mpc_dev), _stream(stream)))
+
+
 def vct_batch_create(arms, protocol: vct_protocol, ctrl: vct_controller, sim: vct_sim, block: int = 0,
                      stream=None) -> C.c_void_p:
     arr = (vct_arm * len(arms))(*arms)
@@ -247,11 +261,13 @@ def protocol(trial: dict) -> vct_protocol:
     return p
 
 
-def controller(trial: dict) -> vct_controller:
+def controller(trial: dict, mpc_dev=None) -> vct_controller:
     c = vct_controller()
     c.kind = int(trial["ctrl_kind"])
-    for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel"):
+    for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel", "mpc_rho"):
         setattr(c, k, float(trial[k]))
+    c.mpc_horizon, c.mpc_iters = int(trial["mpc_horizon"]), int(trial["mpc_iters"])
+    c.mpc_dev = _ptr(mpc_dev)
     return c
 
 
