@@ -30,8 +30,18 @@ class OrcConfig(C.Structure):
         ("cgm_var", C.c_double), ("noise_seed", C.c_uint64), ("integrator", C.c_int32), ("rk4_sub", C.c_int32),
         ("x0_offset", C.c_double * NX), ("guard_rel", C.c_double),
         ("mpc_horizon", C.c_int32), ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double),
-        ("mpc_riccati_iters", C.c_int32), ("mpc_power_iters", C.c_int32),
+        ("mpc_riccati_iters", C.c_int32), ("mpc_power_iters", C.c_int32), ("mlp", C.c_void_p),
     ]
+
+
+MLP_IN, MLP_H = 12, 64
+MLP_FIELDS = (("W1", (MLP_H, MLP_IN)), ("b1", (MLP_H,)), ("W2", (MLP_H, MLP_H)), ("b2", (MLP_H,)),
+              ("W3", (MLP_H, MLP_H)), ("b3", (MLP_H,)), ("w4", (MLP_H,)), ("b4", ()), ("mean", (MLP_IN,)),
+              ("istd", (MLP_IN,)), ("lo", (MLP_IN,)), ("hi", (MLP_IN,)))
+
+
+class OrcMlp(C.Structure):
+    _fields_ = [(name, C.c_double * int(np.prod(shape)) if shape else C.c_double) for name, shape in MLP_FIELDS]
 
 
 NMAX = 48
@@ -57,7 +67,7 @@ class OrcOutputs(C.Structure):
         ("argmin_k", _P(C.c_int32)), ("sum_u", _P(C.c_double)), ("status", _P(C.c_uint32)),
         ("n_near", _P(C.c_int32)), ("ctrl_margin", _P(C.c_double)), ("params", _P(C.c_double)),
         ("n_traj", C.c_int32), ("traj_g", _P(C.c_double)), ("traj_y", _P(C.c_double)), ("traj_u", _P(C.c_double)),
-        ("traj_x", _P(C.c_double)),
+        ("traj_x", _P(C.c_double)), ("record", _P(C.c_double)), ("fallback", _P(C.c_int32)),
     ]
 
 
@@ -103,6 +113,16 @@ def lib() -> C.CDLL:
         L.orc_mpc_pg.argtypes = [_P(OrcMpc), _P(C.c_double), _P(C.c_double), C.c_int]
         L.orc_pid_run.argtypes = [_P(OrcConfig), C.c_double, C.c_int32, _P(C.c_double), _P(C.c_double),
                                   _P(C.c_double)]
+        L.orc_bf16.argtypes = [C.c_double]
+        L.orc_bf16.restype = C.c_double
+        L.orc_mlp_forward.argtypes = [_P(OrcMlp), _P(C.c_double), C.c_int64, _P(C.c_double)]
+        L.orc_mlp_loss_grad.argtypes = [_P(OrcMlp), _P(C.c_double), _P(C.c_int64), C.c_int64, _P(OrcMlp)]
+        L.orc_mlp_loss_grad.restype = C.c_double
+        L.orc_mlp_init.argtypes = [C.c_uint64, _P(OrcMlp)]
+        L.orc_mlp_batch_rows.argtypes = [C.c_uint64, C.c_int32, C.c_int64, C.c_int64, _P(C.c_int64)]
+        L.orc_mlp_stats.argtypes = [_P(C.c_double), C.c_int64, C.c_double, _P(OrcMlp)]
+        L.orc_adam.argtypes = [C.c_int64, _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_double),
+                               C.c_double, C.c_int64]
         _lib = L
     return _lib
 
@@ -254,10 +274,82 @@ def mpc_pg(setup: dict, g, dU0, iters: int) -> np.ndarray:
     return du
 
 
+# --------------------------------------------------------- learned controller
+def bf16(x) -> np.ndarray:
+    """Nearest BF16 value of each element (ties to even)."""
+    a = np.asarray(x, dtype=np.float64)
+    f = lib().orc_bf16
+    return np.vectorize(f, otypes=[np.float64])(a) if a.size else a.copy()
+
+
+def mlp_struct(net: dict) -> OrcMlp:
+    m = OrcMlp()
+    for name, shape in MLP_FIELDS:
+        v = np.asarray(net[name], dtype=np.float64)
+        assert v.shape == shape, (name, v.shape, shape)
+        if shape:
+            getattr(m, name)[:] = [float(t) for t in v.ravel()]
+        else:
+            setattr(m, name, float(v))
+    return m
+
+
+def mlp_dict(m: OrcMlp) -> dict:
+    out = {}
+    for name, shape in MLP_FIELDS:
+        out[name] = np.array(getattr(m, name)).reshape(shape) if shape else float(getattr(m, name))
+    return out
+
+
+def mlp_forward(net: dict, x) -> np.ndarray:
+    xa = np.ascontiguousarray(x, dtype=np.float64).reshape(-1, MLP_IN)
+    out = np.zeros(xa.shape[0])
+    m = mlp_struct(net)
+    lib().orc_mlp_forward(C.byref(m), _ptr(xa, C.c_double), xa.shape[0], _ptr(out, C.c_double))
+    return out
+
+
+def mlp_loss_grad(net: dict, rows, idx) -> tuple[float, dict]:
+    ra = np.ascontiguousarray(rows, dtype=np.float64).reshape(-1, MLP_IN + 1)
+    ia = np.ascontiguousarray(idx, dtype=np.int64)
+    m, g = mlp_struct(net), OrcMlp()
+    loss = lib().orc_mlp_loss_grad(C.byref(m), _ptr(ra, C.c_double), _ptr(ia, C.c_int64), len(ia), C.byref(g))
+    return loss, mlp_dict(g)
+
+
+def mlp_init(seed: int) -> dict:
+    m = OrcMlp()
+    lib().orc_mlp_init(int(seed), C.byref(m))
+    return mlp_dict(m)
+
+
+def mlp_batch_rows(seed: int, step: int, B: int, n_rows: int) -> np.ndarray:
+    idx = np.zeros(int(B), np.int64)
+    lib().orc_mlp_batch_rows(int(seed), int(step), int(B), int(n_rows), _ptr(idx, C.c_int64))
+    return idx
+
+
+def mlp_stats(rows, box_q: float) -> dict:
+    ra = np.ascontiguousarray(rows, dtype=np.float64).reshape(-1, MLP_IN + 1)
+    m = OrcMlp()
+    lib().orc_mlp_stats(_ptr(ra, C.c_double), ra.shape[0], float(box_q), C.byref(m))
+    d = mlp_dict(m)
+    return {k: d[k] for k in ("mean", "istd", "lo", "hi")}
+
+
+def adam(w, m, v, g, lr: float, t: int):
+    """One Adam step on copies; returns (w, m, v)."""
+    w, m, v = (np.ascontiguousarray(a, dtype=np.float64).copy() for a in (w, m, v))
+    ga = np.ascontiguousarray(g, dtype=np.float64)
+    lib().orc_adam(w.size, _ptr(w, C.c_double), _ptr(m, C.c_double), _ptr(v, C.c_double), _ptr(ga, C.c_double),
+                   float(lr), int(t))
+    return w, m, v
+
+
 # ------------------------------------------------------------------ simulate
 def simulate(trial: dict, first: int = 0, count: int | None = None, threads: int | None = None,
              n_traj: int = 0, record_x: bool = False, integrator: int = INT_EM, rk4_sub: int = 64,
-             x0_offset=None, guard_rel: float = 1e-4) -> dict:
+             x0_offset=None, guard_rel: float = 1e-4, mlp: dict | None = None, record: bool = False) -> dict:
     """Run patients [first, first+count) of the trial; returns per-patient arrays."""
     n = int(trial["n_patients"]) - first if count is None else int(count)
     K = int(trial["n_days"]) * (1440 // int(trial["ts_min"]))
@@ -285,7 +377,14 @@ def simulate(trial: dict, first: int = 0, count: int | None = None, threads: int
     o.traj_y = _ptr(r.get("traj_y"), C.c_double)
     o.traj_u = _ptr(r.get("traj_u"), C.c_double)
     o.traj_x = _ptr(r.get("traj_x"), C.c_double)
+    if record:
+        r["record"] = np.zeros((K, n, MLP_IN + 1))
+    r["fallback"] = np.zeros(n, np.int32)
+    o.record = _ptr(r.get("record"), C.c_double)
+    o.fallback = _ptr(r["fallback"], C.c_int32)
     cfg = config(trial, integrator=integrator, rk4_sub=rk4_sub, x0_offset=x0_offset, guard_rel=guard_rel)
+    net = mlp_struct(mlp) if mlp is not None else None
+    cfg.mlp = C.cast(C.pointer(net), C.c_void_p) if net is not None else None
     if threads is None:
         threads = os.cpu_count() or 1
     rc = lib().orc_simulate(C.byref(cfg), first, n, int(threads), C.byref(o))

@@ -676,14 +676,27 @@ typedef struct {
     double dU[ORC_NMAX];   /* planned u - u_b */
 } mpc_state;
 
-static double mpc_step(const orc_config *cfg, mpc_state *st, double y, double dhat)
+/* The controller sample in three parts: measurement update with the sensor value; the plan
+ * (QP linear term, warm start from the shifted previous plan, projected gradient); the
+ * time update with the applied input deviation and the announced intake. */
+static void mpc_measure(mpc_state *st, double y)
 {
-    orc_mpc *m = &st->m;
-    const int N = m->N;
-    /* measurement update with the sensor deviation y - GI_ss */
+    const orc_mpc *m = &st->m;
     double innov = (y - m->xss[X_GI]) - st->xh[X_GI];
     for (int i = 0; i < ORC_NX; ++i)
         st->xh[i] += m->K[i] * innov;
+}
+
+static void mpc_shift(mpc_state *st)
+{
+    for (int i = 0; i + 1 < st->m.N; ++i)
+        st->dU[i] = st->dU[i + 1];
+}
+
+static double mpc_plan(const orc_config *cfg, mpc_state *st, double dhat)
+{
+    const orc_mpc *m = &st->m;
+    const int N = m->N;
     /* linear term of the QP: Gamma^T (F xh + w dhat + (G* - ybar)) */
     double g[ORC_NMAX];
     for (int i = 0; i < N; ++i) {
@@ -692,12 +705,14 @@ static double mpc_step(const orc_config *cfg, mpc_state *st, double y, double dh
             acc += m->Gx[i * ORC_NX + c] * st->xh[c];
         g[i] = acc;
     }
-    /* warm start: previous plan shifted by one sample */
-    for (int i = 0; i + 1 < N; ++i)
-        st->dU[i] = st->dU[i + 1];
+    mpc_shift(st);
     orc_mpc_pg(m, g, st->dU, cfg->mpc_iters);
-    const double du = st->dU[0];
-    /* time update with the applied input and the announced intake */
+    return st->dU[0];
+}
+
+static void mpc_predict(mpc_state *st, double du, double dhat)
+{
+    const orc_mpc *m = &st->m;
     double nx[ORC_NX];
     for (int r = 0; r < ORC_NX; ++r) {
         double acc = m->B[r] * du + m->E[r] * dhat;
@@ -706,11 +721,253 @@ static double mpc_step(const orc_config *cfg, mpc_state *st, double y, double dh
         nx[r] = acc;
     }
     memcpy(st->xh, nx, sizeof nx);
-    return m->ub + du;
+}
+
+static double mpc_step(const orc_config *cfg, mpc_state *st, double y, double dhat)
+{
+    mpc_measure(st, y);
+    const double du = mpc_plan(cfg, st, dhat);
+    mpc_predict(st, du, dhat);
+    return st->m.ub + du;
+}
+
+/* ------------------------------------------------------- learned controller ---- */
+double orc_bf16(double x)
+{
+    if (x == 0.0 || !isfinite(x))
+        return x;
+    int e;
+    frexp(x, &e);                          /* |x| in [2^(e-1), 2^e) */
+    const double ulp = ldexp(1.0, e - 8);  /* 8 significant bits */
+    return nearbyint(x / ulp) * ulp;       /* x/ulp is exact; ties to even */
+}
+
+static double mlp_eval(const orc_mlp *n, const double x[ORC_MLP_IN], double z[ORC_MLP_IN], double h1[ORC_MLP_H],
+                       double h2[ORC_MLP_H], double h3[ORC_MLP_H])
+{
+    for (int f = 0; f < ORC_MLP_IN; ++f)
+        z[f] = orc_bf16((x[f] - n->mean[f]) * n->istd[f]);
+    for (int u = 0; u < ORC_MLP_H; ++u) {
+        double a = n->b1[u];
+        for (int f = 0; f < ORC_MLP_IN; ++f)
+            a += n->W1[u * ORC_MLP_IN + f] * z[f];
+        h1[u] = a > 0.0 ? a : 0.0;
+    }
+    for (int u = 0; u < ORC_MLP_H; ++u) {
+        double a = n->b2[u];
+        for (int v = 0; v < ORC_MLP_H; ++v)
+            a += n->W2[u * ORC_MLP_H + v] * h1[v];
+        h2[u] = a > 0.0 ? a : 0.0;
+    }
+    for (int u = 0; u < ORC_MLP_H; ++u) {
+        double a = n->b3[u];
+        for (int v = 0; v < ORC_MLP_H; ++v)
+            a += n->W3[u * ORC_MLP_H + v] * h2[v];
+        h3[u] = a > 0.0 ? a : 0.0;
+    }
+    double o = n->b4;
+    for (int u = 0; u < ORC_MLP_H; ++u)
+        o += n->w4[u] * h3[u];
+    return o;
+}
+
+void orc_mlp_forward(const orc_mlp *net, const double *x, int64_t n, double *out)
+{
+    double z[ORC_MLP_IN], h1[ORC_MLP_H], h2[ORC_MLP_H], h3[ORC_MLP_H];
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = mlp_eval(net, x + i * ORC_MLP_IN, z, h1, h2, h3);
+}
+
+/* Backpropagation of L = (1/B) sum (o - t)^2 through the chain of mlp_eval; the derivative
+ * of ReLU is taken as 1 where the unit is positive and 0 elsewhere. */
+double orc_mlp_loss_grad(const orc_mlp *net, const double *rows, const int64_t *idx, int64_t B, orc_mlp *g)
+{
+    memset(g, 0, sizeof *g);
+    double loss = 0.0;
+    for (int64_t i = 0; i < B; ++i) {
+        const double *r = rows + idx[i] * (ORC_MLP_IN + 1);
+        double z[ORC_MLP_IN], h1[ORC_MLP_H], h2[ORC_MLP_H], h3[ORC_MLP_H];
+        const double o = mlp_eval(net, r, z, h1, h2, h3);
+        const double e = o - r[ORC_MLP_IN];
+        loss += e * e / (double)B;
+        const double dout = 2.0 * e / (double)B;
+        double d3[ORC_MLP_H], d2[ORC_MLP_H], d1[ORC_MLP_H];
+        g->b4 += dout;
+        for (int u = 0; u < ORC_MLP_H; ++u) {
+            g->w4[u] += dout * h3[u];
+            d3[u] = h3[u] > 0.0 ? dout * net->w4[u] : 0.0;
+        }
+        for (int v = 0; v < ORC_MLP_H; ++v) {
+            double a = 0.0;
+            for (int u = 0; u < ORC_MLP_H; ++u)
+                a += d3[u] * net->W3[u * ORC_MLP_H + v];
+            d2[v] = h2[v] > 0.0 ? a : 0.0;
+        }
+        for (int u = 0; u < ORC_MLP_H; ++u) {
+            g->b3[u] += d3[u];
+            for (int v = 0; v < ORC_MLP_H; ++v)
+                g->W3[u * ORC_MLP_H + v] += d3[u] * h2[v];
+        }
+        for (int v = 0; v < ORC_MLP_H; ++v) {
+            double a = 0.0;
+            for (int u = 0; u < ORC_MLP_H; ++u)
+                a += d2[u] * net->W2[u * ORC_MLP_H + v];
+            d1[v] = h1[v] > 0.0 ? a : 0.0;
+        }
+        for (int u = 0; u < ORC_MLP_H; ++u) {
+            g->b2[u] += d2[u];
+            for (int v = 0; v < ORC_MLP_H; ++v)
+                g->W2[u * ORC_MLP_H + v] += d2[u] * h1[v];
+        }
+        for (int u = 0; u < ORC_MLP_H; ++u) {
+            g->b1[u] += d1[u];
+            for (int f = 0; f < ORC_MLP_IN; ++f)
+                g->W1[u * ORC_MLP_IN + f] += d1[u] * z[f];
+        }
+    }
+    return loss;
+}
+
+#define TAG_MLP_BATCH 5u
+#define TAG_MLP_INIT 6u
+
+void orc_mlp_init(uint64_t seed, orc_mlp *net)
+{
+    memset(net, 0, sizeof *net);
+    uint32_t key[2];
+    make_key(seed, 0u, key);
+    const int P_W1 = 0, P_W2 = 64 * 16, P_W3 = P_W2 + 64 * 64, P_W4 = P_W3 + 64 * 64, P_B = P_W4 + 16 * 64;
+    for (int p = 0; p < P_B; ++p) {
+        uint32_t ctr[4] = {(uint32_t)(p / 4), 0u, TAG_MLP_INIT, 0u};
+        double z4[4];
+        orc_normals4(ctr, key, z4);
+        const double z = z4[p % 4];
+        if (p < P_W2) {
+            const int u = (p - P_W1) / 16, f = (p - P_W1) % 16;
+            if (f < ORC_MLP_IN)
+                net->W1[u * ORC_MLP_IN + f] = z * sqrt(2.0 / ORC_MLP_IN);
+        } else if (p < P_W3) {
+            net->W2[p - P_W2] = z * sqrt(2.0 / ORC_MLP_H);
+        } else if (p < P_W4) {
+            net->W3[p - P_W3] = z * sqrt(2.0 / ORC_MLP_H);
+        } else if (p - P_W4 < ORC_MLP_H) {
+            net->w4[p - P_W4] = z * sqrt(1.0 / ORC_MLP_H);
+        }
+    }
+    net->b4 = 1.0;
+}
+
+void orc_mlp_batch_rows(uint64_t seed, int32_t step, int64_t B, int64_t n_rows, int64_t *idx)
+{
+    uint32_t key[2];
+    make_key(seed, 0u, key);
+    for (int64_t i = 0; i < B; ++i) {
+        uint32_t ctr[4] = {(uint32_t)step, (uint32_t)i, TAG_MLP_BATCH, 0u}, x[4];
+        orc_philox4x32_10(ctr, key, x);
+        idx[i] = (int64_t)(((uint64_t)x[0] * (uint64_t)n_rows) >> 32);
+    }
+}
+
+static int cmp_f64(const void *a, const void *b)
+{
+    const double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+void orc_mlp_stats(const double *rows, int64_t n, double box_q, orc_mlp *net)
+{
+    double *col = (double *)malloc(sizeof(double) * (size_t)n);
+    for (int f = 0; f < ORC_MLP_IN; ++f) {
+        double s = 0.0, q = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            const double x = rows[i * (ORC_MLP_IN + 1) + f];
+            col[i] = x;
+            s += x;
+            q += x * x;
+        }
+        const double mu = s / (double)n;
+        double var = q / (double)n - mu * mu;
+        if (var < 0.0)
+            var = 0.0;
+        double sd = sqrt(var);
+        if (sd < 1e-6)
+            sd = 1e-6;
+        net->mean[f] = mu;
+        net->istd[f] = 1.0 / sd;
+        qsort(col, (size_t)n, sizeof(double), cmp_f64);
+        if (box_q <= 0.0) {
+            net->lo[f] = col[0];
+            net->hi[f] = col[n - 1];
+        } else {   /* nearest rank: the smallest value with at least ceil(q n) values <= it */
+            const int64_t r_lo = (int64_t)ceil(box_q * (double)n), r_hi = (int64_t)ceil((1.0 - box_q) * (double)n);
+            net->lo[f] = col[(r_lo < 1 ? 1 : r_lo) - 1];
+            net->hi[f] = col[(r_hi < 1 ? 1 : r_hi) - 1];
+        }
+    }
+    free(col);
+}
+
+void orc_adam(int64_t n, double *w, double *m, double *v, const double *g, double lr, int64_t t)
+{
+    const double b1 = 0.9, b2 = 0.999, eps = 1e-8;
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (int64_t i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] -= lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
+/* Inputs of the learned controller at a sample: the sensor history y_k..y_k-5, the insulin
+ * on board relative to basal (S1 + S2)/(2 u_b tmaxI), the glucose on board from the
+ * announced meals D1 + D2 + A_G dhat Ts (the insulin and absorption subsystems are
+ * deterministic, so a controller-side replica driven by the doses and announcements has
+ * the plant's values), and BW, u_b, SIT, SID. */
+static void mlp_inputs(const orc_config *cfg, const double *p, double ub, const double x[ORC_NX],
+                       const double yh[6], double dhat, double f[ORC_MLP_IN])
+{
+    for (int i = 0; i < 6; ++i)
+        f[i] = yh[i];
+    f[6] = (x[X_S1] + x[X_S2]) / (2.0 * ub * p[P_TMAXI]);
+    f[7] = x[X_D1] + x[X_D2] + cfg->ag * dhat * (double)cfg->ts_min;
+    f[8] = p[P_BW];
+    f[9] = ub;
+    f[10] = p[P_SIT];
+    f[11] = p[P_SID];
+}
+
+/* The network acts unless an input is outside its box or it would raise insulin above basal
+ * (out > 1) while y_k < 3.9 mmol/L; then the MPC solves its QP. The Kalman filter runs on
+ * every sample; when the network acts the MPC's plan is only shifted. */
+static double mlp_step(const orc_config *cfg, mpc_state *st, const double f[ORC_MLP_IN], double y, double dhat,
+                       int32_t *fallbacks)
+{
+    const orc_mlp *net = cfg->mlp;
+    mpc_measure(st, y);
+    double z[ORC_MLP_IN], h1[ORC_MLP_H], h2[ORC_MLP_H], h3[ORC_MLP_H];
+    const double o = mlp_eval(net, f, z, h1, h2, h3);
+    int ood = 0;
+    for (int q = 0; q < ORC_MLP_IN; ++q)
+        if (!(f[q] >= net->lo[q] && f[q] <= net->hi[q]))
+            ood = 1;
+    double u, du;
+    if (ood || (y < 3.9 && o > 1.0)) {
+        du = mpc_plan(cfg, st, dhat);
+        u = st->m.ub + du;
+        ++*fallbacks;
+    } else {
+        mpc_shift(st);
+        u = st->m.ub * o;
+        u = u < 0.0 ? 0.0 : (u > st->m.umax ? st->m.umax : u);
+        du = u - st->m.ub;
+    }
+    mpc_predict(st, du, dhat);
+    return u;
 }
 
 /* ------------------------------------------------------------ main loop ---- */
-static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient, const orc_outputs *out)
+static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, uint32_t patient,
+                             const orc_outputs *out)
 {
     double prm[ORC_NPOUT];
     sample_patient(cfg, patient, prm);
@@ -746,7 +1003,10 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
     pid_t_ pid = {0.0, 0.0, 0};
     int is_traj = j < out->n_traj;
     mpc_state *mpc = NULL;
-    if (cfg->ctrl_kind == ORC_CTRL_MPC) {
+    int32_t fallbacks = 0;
+    const int use_inputs = cfg->ctrl_kind == ORC_CTRL_MLP || out->record != NULL;
+    double yh[6] = {0};   /* y_k, y_k-1, ..., y_k-5 */
+    if (cfg->ctrl_kind == ORC_CTRL_MPC || cfg->ctrl_kind == ORC_CTRL_MLP) {
         mpc = (mpc_state *)calloc(1, sizeof *mpc);
         if (!orc_mpc_setup(cfg, prm, &mpc->m)) {
             free(mpc);
@@ -782,13 +1042,32 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
                 if (meals[m].kd == kd)
                     d += meals[m].rate;
 
+            double f[ORC_MLP_IN];
+            if (use_inputs) {
+                if (k == 0)
+                    for (int i = 1; i < 6; ++i) yh[i] = y;
+                yh[0] = y;
+                mlp_inputs(cfg, p, ub, x, yh, d, f);
+            }
+
             double u;
             if (cfg->ctrl_kind == ORC_CTRL_PID)
                 u = pid_step(cfg, &pid, y, ub, &a.ctrl_margin);
             else if (cfg->ctrl_kind == ORC_CTRL_MPC)
                 u = mpc ? mpc_step(cfg, mpc, y, d) : NAN;
+            else if (cfg->ctrl_kind == ORC_CTRL_MLP)
+                u = mpc ? mlp_step(cfg, mpc, f, y, d, &fallbacks) : NAN;
             else
                 u = cfg->u_rel * ub;
+
+            if (use_inputs) {
+                for (int i = 5; i > 0; --i) yh[i] = yh[i - 1];
+                if (out->record) {
+                    double *row = out->record + (k * count + j) * (ORC_MLP_IN + 1);
+                    for (int q = 0; q < ORC_MLP_IN; ++q) row[q] = f[q];
+                    row[ORC_MLP_IN] = u / ub;
+                }
+            }
 
             if (is_traj) {
                 if (out->traj_g) out->traj_g[j * K + k] = G;
@@ -825,6 +1104,7 @@ static void simulate_patient(const orc_config *cfg, int64_t j, uint32_t patient,
     out->argmin_k[j] = a.argmin_k;
     out->sum_u[j] = a.sum_u;
     out->status[j] = a.status;
+    if (out->fallback) out->fallback[j] = fallbacks;
     if (out->n_near) out->n_near[j] = a.n_near;
     if (out->ctrl_margin) out->ctrl_margin[j] = a.ctrl_margin;
     if (out->params)
@@ -842,7 +1122,7 @@ static void *worker(void *arg)
 {
     job_t *jb = (job_t *)arg;
     for (int64_t j = jb->tid; j < jb->count; j += jb->nthreads)
-        simulate_patient(jb->cfg, j, (uint32_t)(jb->first + j), jb->out);
+        simulate_patient(jb->cfg, j, jb->count, (uint32_t)(jb->first + j), jb->out);
     return NULL;
 }
 
@@ -857,7 +1137,9 @@ int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_thre
             return -1;
     if (cfg->integrator == ORC_INT_RK4 && (cfg->sigma_q1 != 0.0 || cfg->cgm_var != 0.0 || cfg->rk4_sub < 1))
         return -1;
-    if (cfg->ctrl_kind == ORC_CTRL_MPC &&
+    if (cfg->ctrl_kind == ORC_CTRL_MLP && !cfg->mlp)
+        return -1;
+    if ((cfg->ctrl_kind == ORC_CTRL_MPC || cfg->ctrl_kind == ORC_CTRL_MLP) &&
         (cfg->mpc_horizon < 1 || cfg->mpc_horizon > ORC_NMAX || cfg->mpc_iters < 0 || cfg->mpc_riccati_iters < 0 ||
          cfg->mpc_power_iters < 1 || !(cfg->mpc_rho > 0.0)))
         return -1;

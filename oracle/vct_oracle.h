@@ -88,7 +88,23 @@ typedef struct {
     double   mpc_rho;           /* weight of ((u - u_b)/u_b)^2 */
     int32_t  mpc_riccati_iters; /* fixed Riccati iterations for the stationary Kalman gain */
     int32_t  mpc_power_iters;   /* power iterations for lambda_max(Gamma^T Gamma) */
+    /* learned controller (ORC_CTRL_MLP): the network, its input normalisation and box */
+    const struct orc_mlp_s *mlp;
 } orc_config;
+
+/* Learned controller: 12 inputs -> 64 -> 64 -> 64 -> 1, ReLU hidden layers. The inputs are
+ * z-scored with (mean, istd) and rounded to BF16 (the network's input format); everything
+ * after that is exact FP64 arithmetic on the stored weights. */
+#define ORC_MLP_IN 12
+#define ORC_MLP_H 64
+typedef struct orc_mlp_s {
+    double W1[ORC_MLP_H * ORC_MLP_IN], b1[ORC_MLP_H];    /* W1[u][f] at u*12 + f */
+    double W2[ORC_MLP_H * ORC_MLP_H], b2[ORC_MLP_H];     /* W2[u][v] at u*64 + v */
+    double W3[ORC_MLP_H * ORC_MLP_H], b3[ORC_MLP_H];
+    double w4[ORC_MLP_H], b4;
+    double mean[ORC_MLP_IN], istd[ORC_MLP_IN];           /* input z-score */
+    double lo[ORC_MLP_IN], hi[ORC_MLP_IN];               /* box outside which the MPC acts */
+} orc_mlp;
 
 #define ORC_NMAX 48
 
@@ -121,6 +137,8 @@ typedef struct {
     int32_t   n_traj;      /* trajectories for the first n_traj patients      */
     double   *traj_g, *traj_y, *traj_u;   /* [n_traj][K] (any may be NULL)   */
     double   *traj_x;      /* [n_traj][K][ORC_NX] state at each sample or NULL */
+    double   *record;      /* [K][count][13] controller inputs + u/u_b (MPC, MLP) or NULL */
+    int32_t  *fallback;    /* [count] samples on which the MPC acted for the MLP, or NULL */
 } orc_outputs;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -149,6 +167,26 @@ void     orc_jacobian(const orc_config *cfg, const double p[ORC_NP], const doubl
 int      orc_mpc_setup(const orc_config *cfg, const double prm[ORC_NPOUT], orc_mpc *m);
 /* Projected-gradient iterations on the box QP from the start dU (overwritten). */
 void     orc_mpc_pg(const orc_mpc *m, const double g[], double dU[], int iters);
+
+/* Learned controller. Round to the nearest BF16 value (8 significant bits, ties to even). */
+double   orc_bf16(double x);
+/* Network outputs for n raw input rows x[n][12]. */
+void     orc_mlp_forward(const orc_mlp *net, const double *x, int64_t n, double *out);
+/* Mean squared error (1/B) sum_i (out(x_idx[i]) - t_idx[i])^2 over rows[.][13] (inputs, then
+ * target) and its gradient with respect to W1..b4 (written into grad; grad's normalisation
+ * fields are zeroed). Returns the loss. */
+double   orc_mlp_loss_grad(const orc_mlp *net, const double *rows, const int64_t *idx, int64_t B, orc_mlp *grad);
+/* He-normal initial weights (std sqrt(2/fan_in), output layer sqrt(1/64)), zero biases but
+ * b4 = 1. Parameters are numbered in the padded order W1[64][16], W2[64][64], W3[64][64],
+ * W4[16][64], b1, b2, b3, b4[16]; number p takes normal p%4 of the block (p/4, 0, 6, 0). */
+void     orc_mlp_init(uint64_t seed, orc_mlp *net);
+/* Minibatch rows drawn with replacement: floor(x n_rows / 2^32), x = word 0 of (step, i, 5, 0). */
+void     orc_mlp_batch_rows(uint64_t seed, int32_t step, int64_t B, int64_t n_rows, int64_t *idx);
+/* Input mean, 1/std (population std, floor 1e-6) and box: box_q = 0 -> [min, max], else the
+ * nearest-rank box_q and 1 - box_q quantiles. */
+void     orc_mlp_stats(const double *rows, int64_t n, double box_q, orc_mlp *net);
+/* Adam step t (1-based) with beta 0.9 / 0.999, eps 1e-8 on n parameters. */
+void     orc_adam(int64_t n, double *w, double *m, double *v, const double *g, double lr, int64_t t);
 
 /* Closed-loop Monte Carlo for patients [first, first+count) on n_threads threads. */
 int      orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out);

@@ -149,3 +149,81 @@ def days_patients(trial: dict) -> int:
 
 def samples_per_day(trial: dict) -> int:
     return 1440 // int(trial["ts_min"])
+
+
+def c5_mlp(seed: int = 5) -> dict:
+    """Learned-controller arm of the same trial (same population, meals and noise)."""
+    return with_(c5_mpc(seed), ctrl_kind=CTRL_MLP)
+
+
+# --------------------------------------------------------- learned-controller inputs
+# Order of the 12 inputs: y_k .. y_k-5 (mmol/L), insulin on board relative to basal,
+# glucose on board from announced meals (mmol), BW (kg), u_b (mU/min), SIT, SID.
+POLICY_INPUTS = ("y0", "y1", "y2", "y3", "y4", "y5", "iob", "gob", "BW", "ub", "SIT", "SID")
+
+
+def synthetic_policy_rows(seed: int, n: int):
+    """n rows [12 inputs, target] drawn from numpy's seeded generator, with the ranges of
+    a closed loop (glucose 2-25 mmol/L, meals on ~20 % of rows, lognormal patients); the
+    target is a smooth function of the inputs in [0, 3]."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    y0 = np.clip(7.0 + 2.0 * rng.standard_normal(n), 2.0, 25.0)
+    slope = 0.15 * rng.standard_normal(n)
+    ys = [np.clip(y0 - slope * i, 2.0, 25.0) for i in range(6)]
+    iob = np.exp(0.3 * rng.standard_normal(n))
+    gob = np.where(rng.random(n) < 0.2, rng.uniform(0.0, 300.0, n), 0.0)
+    bw = 70.0 * np.exp(0.2 * rng.standard_normal(n))
+    ub = 15.0 * np.exp(0.2 * rng.standard_normal(n))
+    sit = 51.2e-4 * np.exp(0.2 * rng.standard_normal(n))
+    sid = 8.2e-4 * np.exp(0.2 * rng.standard_normal(n))
+    target = np.clip(1.0 + 0.5 * (y0 - 6.0) + 2.0 * slope - 0.5 * (iob - 1.0) + gob / 200.0, 0.0, 3.0)
+    return np.stack(ys + [iob, gob, bw, ub, sit, sid, target], axis=1)
+
+
+def synthetic_policy_net(seed: int, gain: float = 1.0, spread: float = 0.05) -> dict:
+    """A controller network for closed-loop tests: units 0 and 1 of every hidden layer carry
+    relu(z0 - a) and relu(a - z0) for the normalised sensor value z0, so the output is
+    1 + gain (z0 - a) (a proportional law around 6 mmol/L) plus a small random network on the
+    other 62 units (weights from numpy's seeded generator, output weights ~ spread). The
+    normalisation is fixed (sensor values around 7 +- 2 mmol/L) and the box covers glucose
+    2.5-16 mmol/L and patients within a factor 1.8 of nominal."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    H = 64
+    W1 = 0.4 * rng.standard_normal((H, 12))
+    W2 = 0.17 * rng.standard_normal((H, H))
+    W3 = 0.17 * rng.standard_normal((H, H))
+    b1 = 0.1 * rng.standard_normal(H)
+    b2 = 0.1 * rng.standard_normal(H)
+    b3 = 0.1 * rng.standard_normal(H)
+    w4 = spread * rng.standard_normal(H)
+    mean = np.array([7.0] * 6 + [1.0, 30.0, 70.0, 15.0, 51.2e-4, 8.2e-4])
+    istd = 1.0 / np.array([2.0] * 6 + [0.5, 60.0, 14.0, 4.0, 1.0e-3, 1.6e-4])
+    a = (6.0 - 7.0) / 2.0
+    for W, b in ((W2, b2), (W3, b3)):
+        W[0:2, :] = 0.0
+        W[:, 0:2] = 0.0
+        W[0, 0] = W[1, 1] = 1.0
+        b[0:2] = 0.0
+    W1[0:2, :] = 0.0
+    W1[0, 0], b1[0] = 1.0, -a
+    W1[1, 0], b1[1] = -1.0, a
+    w4[0], w4[1] = gain, -gain
+    lo = np.array([2.5] * 6 + [0.0, 0.0, 70.0 / 1.8, 0.0, 51.2e-4 / 1.8, 8.2e-4 / 1.8])
+    hi = np.array([16.0] * 6 + [20.0, 1e4, 70.0 * 1.8, 1e3, 51.2e-4 * 1.8, 8.2e-4 * 1.8])
+    # stored precision: FP32 normalisation and biases
+    f32 = lambda v: np.asarray(v, np.float32).astype(np.float64)
+    return {"W1": W1, "b1": f32(b1), "W2": W2, "b2": f32(b2), "W3": W3, "b3": f32(b3), "w4": w4, "b4": 1.0,
+            "mean": f32(mean), "istd": f32(istd), "lo": f32(lo), "hi": f32(hi)}
+
+
+def constant_policy_net(value: float, always_fallback: bool = False) -> dict:
+    """A network whose output is `value` for every input (zero weights, b4 = value); its box
+    admits every finite input, or none (lo > hi) with always_fallback."""
+    import numpy as np
+    z = lambda *s: np.zeros(s)
+    inf = 3.0e38
+    lo, hi = (np.full(12, 1.0), np.full(12, -1.0)) if always_fallback else (np.full(12, -inf), np.full(12, inf))
+    return {"W1": z(64, 12), "b1": z(64), "W2": z(64, 64), "b2": z(64), "W3": z(64, 64), "b3": z(64),
+            "w4": z(64), "b4": float(value), "mean": z(12), "istd": np.ones(12), "lo": lo, "hi": hi}
