@@ -103,7 +103,16 @@ typedef struct {
  *   sum_{j=1..N} (G_{k+j} - setpoint)^2 + mpc_rho sum_{i=0..N-1} ((u_i - u_b)/u_b)^2,
  *   0 <= u_i <= umax_rel u_b, with the intake of the current interval announced,
  * by mpc_iters projected-gradient steps warm-started from the shifted previous plan,
- * applies u_0 and predicts. The per-patient matrices come from vct_mpc_setup. */
+ * applies u_0 and predicts. The per-patient matrices come from vct_mpc_setup.
+ * Learned controller (VCT_CTRL_MLP; needs mpc_dev and mlp_dev): a 12 -> 64 -> 64 -> 64 -> 1
+ * ReLU network trained to imitate the MPC gives u_k = clamp(u_b out, 0, umax_rel u_b) from
+ *   y_k .. y_k-5 (y_0 repeated before the first sample), (S1 + S2)/(2 u_b tmaxI),
+ *   D1 + D2 + A_G dhat_k Ts (glucose on board from the announced meals, mmol),
+ *   BW, u_b, SIT, SID,
+ * where S1, S2, D1, D2 are the insulin and meal-absorption states driven by the delivered
+ * doses and the announced meals. The Kalman filter of the MPC runs on every sample; the
+ * MPC solves its QP and acts instead of the network (a "fallback") when any input lies
+ * outside the box stored with the network, or when y_k < 3.9 mmol/L and out > 1. */
 typedef struct {
     int32_t kind;          /* VCT_CTRL_*                                           */
     double  setpoint;      /* mmol/L                                               */
@@ -113,7 +122,8 @@ typedef struct {
     int32_t mpc_horizon;   /* N; this build supports 24                             */
     int32_t mpc_iters;     /* projected-gradient iterations per sample, 0..1000     */
     double  mpc_rho;       /* > 0                                                   */
-    const void *mpc_dev;   /* VCT_CTRL_MPC: buffer filled by vct_mpc_setup          */
+    const void *mpc_dev;   /* VCT_CTRL_MPC, VCT_CTRL_MLP: buffer filled by vct_mpc_setup */
+    const void *mlp_dev;   /* VCT_CTRL_MLP: network blob (vct_mlp_blob_bytes), read-only */
 } vct_controller;
 
 /* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl
@@ -132,7 +142,11 @@ typedef struct {
  *   int32  argmin_k[n] first sample index of min_g
  *   uint32 status[n]  bit0 non-finite state, bit1 negative Q1, bit2 resampling exhausted
  * traj_dev (optional, NULL = off): double [3][traj_patients][K] = G, y, u of the
- *   first traj_patients patients at every sample, K = n_days * 1440 / ts_min. */
+ *   first traj_patients patients at every sample, K = n_days * 1440 / ts_min.
+ * record_dev (optional, VCT_CTRL_MPC / VCT_CTRL_MLP only): float [K][n][13], row (k, j) =
+ *   the 12 learned-controller inputs of patient j at sample k, then u_k / u_b (the
+ *   behaviour-cloning data set when the MPC acts); K * n * 52 bytes.
+ * fallback_dev (optional, VCT_CTRL_MLP only): int32 [n] samples on which the MPC acted. */
 typedef struct {
     int32_t  n_days;          /* >= 1                                               */
     int32_t  em_per_ctrl;     /* 5 (the supported EM substep count)                 */
@@ -144,6 +158,8 @@ typedef struct {
     void    *metrics_dev;
     int32_t  traj_patients;   /* 0..64                                              */
     void    *traj_dev;
+    float   *record_dev;
+    int32_t *fallback_dev;
 } vct_sim;
 
 /* Population summary (Sec. III-C indicators, Sec. IV-A ranges). Quantiles are nearest
@@ -216,6 +232,53 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
 size_t      vct_mpc_bytes(int64_t n_patients, int32_t precision);
 vct_status  vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, const vct_sim *sim, void *mpc_dev,
                           void *stream);
+/* Learned controller: data set, normalisation, training and inference (BF16 MFMA, FP32
+ * accumulation, FP32 master weights).
+ *
+ * Network blob (vct_mlp_blob_bytes() = 21568 bytes, caller-owned device memory, 16-byte
+ * aligned; the training buffer is 256-byte aligned; misalignment is VCT_EINVAL):
+ *   bf16  W1[64][16]   @0      input layer; columns 12..15 are zero
+ *   bf16  W2[64][64]   @2048
+ *   bf16  W3[64][64]   @10240
+ *   bf16  W4[16][64]   @18432  row 0 is the output layer, rows 1..15 are zero
+ *   f32   b1[64] @20480, b2[64] @20736, b3[64] @20992, b4[16] @21248 (b4[1..15] = 0)
+ *   f32   mean[16] @21312, istd[16] @21376: input z-score (x - mean) istd, then BF16
+ *   f32   lo[16] @21440, hi[16] @21504: the input box outside which the MPC acts
+ * Training buffer (vct_mlp_train_bytes(batch), caller-owned device memory), FP32 with
+ * P = VCT_MLP_PARAMS entries in the order W1, W2, W3, W4, b1, b2, b3, b4 (padded shapes as
+ * in the blob), byte offsets: master[P] @0, adam_m[P] @4P, adam_v[P] @8P, grad[P] @12P,
+ * loss @16P, then library scratch. A buffer serves every batch size up to the one it was sized for.
+ * Data rows: float [n_rows][13] = 12 inputs then the target u/u_b (record_dev layout). */
+#define VCT_MLP_IN 12
+#define VCT_MLP_PARAMS 10448
+#define VCT_MLP_BLOB_BYTES 21568
+size_t      vct_mlp_blob_bytes(void);
+size_t      vct_mlp_train_bytes(int32_t batch);
+/* He-normal weights (std sqrt(2/fan_in); output row sqrt(1/64)), zero biases except
+ * b4[0] = 1, zero Adam moments; weight p (padded order) is normal p%4 of the Philox block
+ * (p/4, 0, 6, 0) with key (seed low word, seed high word). Writes master and the blob's
+ * weights and biases. */
+vct_status  vct_mlp_init(uint64_t seed, void *train_dev, void *blob_dev, void *stream);
+/* Per-input mean and 1/std (population std, floor 1e-6) over the rows, and the box:
+ * box_q = 0 -> [min, max] of the data; 0 < box_q < 0.5 -> the nearest-rank box_q and
+ * 1 - box_q quantiles, widened outward to a 4096-bin grid between min and max.
+ * train_dev must hold vct_mlp_train_bytes(64) bytes or more (scratch). */
+vct_status  vct_mlp_normalize(const float *rows_dev, int64_t n_rows, double box_q, void *train_dev,
+                              void *blob_dev, void *stream);
+/* One step on the mean squared error (1/B) sum (out - target)^2 of a minibatch of B =
+ * batch rows (multiple of 64, <= the size train_dev was built for): rows idx_dev[0..B)
+ * if idx_dev is non-NULL (each in [0, n_rows); an index outside makes the loss and the
+ * gradient NaN), else row floor(x n_rows / 2^32) for the first word x of the Philox
+ * block (step, i, 5, 0), i = 0..B-1. Writes grad and loss; with apply != 0 also takes
+ * the Adam step t = step + 1 (beta 0.9 / 0.999, eps 1e-8, learning rate lr) on master
+ * and refreshes the blob's weights. Gradients are summed over the batch in a fixed
+ * order (deterministic). */
+vct_status  vct_mlp_train_step(const float *rows_dev, int64_t n_rows, const int32_t *idx_dev, uint64_t seed,
+                               int32_t step, int32_t batch, double lr, int32_t apply, void *train_dev,
+                               void *blob_dev, void *stream);
+/* Network output for n input rows x_dev [n][12] (raw inputs) -> out_dev [n]. */
+vct_status  vct_mlp_forward(const float *x_dev, int64_t n, const void *blob_dev, float *out_dev, void *stream);
+
 /* Reduce the per-patient metrics of n patients with K samples each into *host_out. */
 vct_status  vct_read_metrics(const void *metrics_dev, int64_t n_patients, int64_t n_samples,
                              vct_summary *host_out, void *stream);

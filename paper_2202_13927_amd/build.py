@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libvct.so")
-SOURCES = ["abi.hip", "kernels.hip", "reduce.hip", "mpc_setup.hip"]
+SOURCES = ["abi.hip", "kernels.hip", "reduce.hip", "mpc_setup.hip", "mlp.hip"]
 ARCH = os.environ.get("VCT_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -11,6 +11,7 @@
 
 #include "../../include/vct.h"
 #include "internal.hpp"
+#include "mlp.hpp"
 #include "mpc.hpp"
 
 struct vct_population {
@@ -168,14 +169,17 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     const int64_t K = (int64_t)sim->n_days * (1440 / sim->ts_min);
     if (K >= ((int64_t)1 << 31))
         return fail(VCT_EINVAL, "horizon too long");
-    if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_MPC) {
-        if (ctrl->kind == VCT_CTRL_MLP)
-            return fail(VCT_ENOTSUP, "controller kind %d not in this entry point", ctrl->kind);
+    if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_MPC &&
+        ctrl->kind != VCT_CTRL_MLP)
         return fail(VCT_EINVAL, "controller kind %d", ctrl->kind);
-    }
-    if (ctrl->kind == VCT_CTRL_MPC) {
+    const bool uses_mpc = ctrl->kind == VCT_CTRL_MPC || ctrl->kind == VCT_CTRL_MLP;
+    if (sim->record_dev && !uses_mpc)
+        return fail(VCT_EINVAL, "record_dev needs the MPC or the learned controller");
+    if (ctrl->kind == VCT_CTRL_MLP && (!ctrl->mlp_dev || (uintptr_t)ctrl->mlp_dev % 16 != 0))
+        return fail(VCT_EINVAL, "learned controller needs mlp_dev (a 16-byte aligned network blob)");
+    if (uses_mpc) {
         if (!ctrl->mpc_dev)
-            return fail(VCT_EINVAL, "MPC controller needs mpc_dev (from vct_mpc_setup)");
+            return fail(VCT_EINVAL, "MPC and learned controllers need mpc_dev (from vct_mpc_setup)");
         if (ctrl->mpc_horizon != vct::kMpcN)
             return fail(VCT_ENOTSUP, "MPC horizon %d (this build: %d)", ctrl->mpc_horizon, vct::kMpcN);
         if (ctrl->mpc_iters < 0 || ctrl->mpc_iters > 1000)
@@ -215,8 +219,11 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.kd = ctrl->kd;
     a.umax_rel = ctrl->umax_rel;
     a.u_rel = ctrl->u_rel;
-    a.mpc = ctrl->kind == VCT_CTRL_MPC ? ctrl->mpc_dev : nullptr;
+    a.mpc = uses_mpc ? ctrl->mpc_dev : nullptr;
     a.mpc_iters = ctrl->mpc_iters;
+    a.mlp = ctrl->kind == VCT_CTRL_MLP ? (const unsigned char *)ctrl->mlp_dev : nullptr;
+    a.record = sim->record_dev;
+    a.fallback = ctrl->kind == VCT_CTRL_MLP ? sim->fallback_dev : nullptr;
     a.ts_min = sim->ts_min;
     a.em_per_ctrl = sim->em_per_ctrl;
     a.h = (double)sim->ts_min / (double)sim->em_per_ctrl;
@@ -294,6 +301,125 @@ vct_status vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, 
     hipError_t e = vct::launch_mpc_setup(a, sim->precision, mpc_dev, (hipStream_t)stream);
     if (e != hipSuccess)
         return hip_fail(e, "vct_mpc_setup: launch");
+    return VCT_OK;
+}
+
+// ------------------------------------------------------------ learned controller ----
+namespace {
+
+const size_t kParamBytes = (size_t)vct::kMlpParams * sizeof(float);
+const size_t kLossOff = 4 * kParamBytes;             // loss slot (256 bytes)
+const size_t kLossPartOff = kLossOff + 256;           // 1024 partial losses
+const size_t kScratchOff = kLossPartOff + 1024 * sizeof(float);
+const int32_t kMaxBatch = 65536;
+
+size_t mlp_scratch_bytes(int32_t batch)
+{
+    return std::max((size_t)(batch / 64) * kParamBytes, vct::mlp_stats_scratch_bytes());
+}
+
+vct::MlpTrain train_views(void *train_dev, void *blob_dev)
+{
+    char *b = (char *)train_dev;
+    vct::MlpTrain t;
+    t.master = (float *)b;
+    t.m = (float *)(b + kParamBytes);
+    t.v = (float *)(b + 2 * kParamBytes);
+    t.grad = (float *)(b + 3 * kParamBytes);
+    t.loss = (float *)(b + kLossOff);
+    t.loss_partial = (float *)(b + kLossPartOff);
+    t.partial = (float *)(b + kScratchOff);
+    t.blob = (unsigned char *)blob_dev;
+    return t;
+}
+
+}  // namespace
+
+size_t vct_mlp_blob_bytes(void) { return (size_t)vct::kMlpBlobBytes; }
+
+size_t vct_mlp_train_bytes(int32_t batch)
+{
+    if (batch < 64 || batch > kMaxBatch || batch % 64 != 0)
+        return 0;
+    return kScratchOff + mlp_scratch_bytes(batch);
+}
+
+vct_status vct_mlp_init(uint64_t seed, void *train_dev, void *blob_dev, void *stream)
+{
+    g_err.clear();
+    if (!train_dev || !blob_dev)
+        return fail(VCT_EINVAL, "vct_mlp_init: null buffer");
+    if ((uintptr_t)train_dev % 256 != 0 || (uintptr_t)blob_dev % 16 != 0)
+        return fail(VCT_EINVAL, "vct_mlp_init: train_dev must be 256-byte and blob_dev 16-byte aligned");
+    uint32_t k0, k1;
+    split_key(seed, 0u, k0, k1);
+    hipError_t e = vct::launch_mlp_init(train_views(train_dev, blob_dev), k0, k1, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_mlp_init: launch");
+    return VCT_OK;
+}
+
+vct_status vct_mlp_normalize(const float *rows_dev, int64_t n_rows, double box_q, void *train_dev, void *blob_dev,
+                             void *stream)
+{
+    g_err.clear();
+    if (!rows_dev || !train_dev || !blob_dev)
+        return fail(VCT_EINVAL, "vct_mlp_normalize: null buffer");
+    if ((uintptr_t)train_dev % 256 != 0 || (uintptr_t)blob_dev % 16 != 0 || (uintptr_t)rows_dev % 4 != 0)
+        return fail(VCT_EINVAL, "vct_mlp_normalize: misaligned buffer");
+    if (n_rows < 1 || n_rows >= ((int64_t)1 << 40))
+        return fail(VCT_EINVAL, "vct_mlp_normalize: n_rows %lld", (long long)n_rows);
+    if (!(box_q >= 0.0 && box_q < 0.5))
+        return fail(VCT_EINVAL, "vct_mlp_normalize: box_q must be in [0, 0.5)");
+    const vct::MlpTrain t = train_views(train_dev, blob_dev);
+    hipError_t e = vct::launch_mlp_stats(rows_dev, n_rows, box_q, (unsigned char *)blob_dev, t.partial,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_mlp_normalize: launch");
+    return VCT_OK;
+}
+
+vct_status vct_mlp_train_step(const float *rows_dev, int64_t n_rows, const int32_t *idx_dev, uint64_t seed,
+                              int32_t step, int32_t batch, double lr, int32_t apply, void *train_dev,
+                              void *blob_dev, void *stream)
+{
+    g_err.clear();
+    if (!rows_dev || !train_dev || !blob_dev)
+        return fail(VCT_EINVAL, "vct_mlp_train_step: null buffer");
+    if ((uintptr_t)train_dev % 256 != 0 || (uintptr_t)blob_dev % 16 != 0 || (uintptr_t)rows_dev % 4 != 0 ||
+        (uintptr_t)idx_dev % 4 != 0)
+        return fail(VCT_EINVAL, "vct_mlp_train_step: misaligned buffer");
+    if (n_rows < 1 || n_rows > ((int64_t)1 << 32))
+        return fail(VCT_EINVAL, "vct_mlp_train_step: n_rows %lld out of [1, 2^32]", (long long)n_rows);
+    if (batch < 64 || batch > kMaxBatch || batch % 64 != 0)
+        return fail(VCT_EINVAL, "vct_mlp_train_step: batch %d (a multiple of 64 in [64, %d])", batch, kMaxBatch);
+    if (step < 0)
+        return fail(VCT_EINVAL, "vct_mlp_train_step: step %d < 0", step);
+    if (!(std::isfinite(lr) && lr >= 0.0))
+        return fail(VCT_EINVAL, "vct_mlp_train_step: lr must be finite and >= 0");
+    uint32_t k0, k1;
+    split_key(seed, 0u, k0, k1);
+    const double t = (double)step + 1.0;
+    const float bc1 = (float)(1.0 - std::pow(0.9, t)), bc2 = (float)(1.0 - std::pow(0.999, t));
+    hipError_t e = vct::launch_mlp_step(train_views(train_dev, blob_dev), rows_dev, n_rows, idx_dev, k0, k1, step,
+                                        batch, (float)lr, bc1, bc2, apply != 0, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_mlp_train_step: launch");
+    return VCT_OK;
+}
+
+vct_status vct_mlp_forward(const float *x_dev, int64_t n, const void *blob_dev, float *out_dev, void *stream)
+{
+    g_err.clear();
+    if (!x_dev || !blob_dev || !out_dev)
+        return fail(VCT_EINVAL, "vct_mlp_forward: null buffer");
+    if ((uintptr_t)blob_dev % 16 != 0 || (uintptr_t)x_dev % 4 != 0 || (uintptr_t)out_dev % 4 != 0)
+        return fail(VCT_EINVAL, "vct_mlp_forward: misaligned buffer");
+    if (n < 1 || n >= ((int64_t)1 << 37))
+        return fail(VCT_EINVAL, "vct_mlp_forward: n %lld", (long long)n);
+    hipError_t e = vct::launch_mlp_forward(x_dev, n, (const unsigned char *)blob_dev, out_dev, (hipStream_t)stream);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_mlp_forward: launch");
     return VCT_OK;
 }
 
@@ -442,6 +568,12 @@ vct_status vct_batch_create(const vct_arm *arms, int32_t n_arms, const vct_proto
         return fail(VCT_EINVAL, "vct_batch_create: need 1..65536 arms and an output handle");
     if (block != 0 && block != 64 && block != 128 && block != 256 && block != 512)
         return fail(VCT_EINVAL, "vct_batch_create: block %d (0 = autotune, or 64/128/256/512)", block);
+    if (!ctrl || !sim || !pr)
+        return fail(VCT_EINVAL, "vct_batch_create: null argument");
+    if (ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_OPEN)
+        return fail(VCT_ENOTSUP, "vct_batch_create: batched arms run the PID or open-loop controller");
+    if (sim->record_dev || sim->fallback_dev)
+        return fail(VCT_EINVAL, "vct_batch_create: record_dev / fallback_dev are per-population outputs");
     std::vector<vct::SimArgs> hargs(n_arms);
     for (int32_t q = 0; q < n_arms; ++q) {
         if (!arms[q].pop)

@@ -37,6 +37,9 @@ struct SimArgs {
     double setpoint, kp, ki, kd, umax_rel, u_rel;
     const void *mpc;      // per-patient MPC data (SoA [kMRows][n], working precision) or null
     int32_t mpc_iters;
+    const unsigned char *mlp;   // learned-controller blob (VCT_CTRL_MLP) or null
+    float *record;        // [K][n][13] learned-controller inputs + u/u_b, or null
+    int32_t *fallback;    // [n] samples on which the MLP handed over to the MPC, or null
     // integration
     int32_t ts_min, em_per_ctrl;
     double h, sig_sqh, sqrt_r;
@@ -76,11 +79,24 @@ struct MpcSetupArgs {
     int32_t riccati_iters, power_iters;
 };
 
+struct MlpTrain {            // views into the caller's training buffer + the inference blob
+    float *master, *m, *v, *grad, *loss, *loss_partial, *partial;
+    unsigned char *blob;
+};
+
 // Launchers (kernels.hip). They only enqueue work; they return the launch error.
 hipError_t launch_population(const PopArgs &a, hipStream_t s);
 hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
 hipError_t launch_mpc_setup(const MpcSetupArgs &a, int precision, void *out, hipStream_t s);
+hipError_t launch_mlp_init(const MlpTrain &t, uint32_t k0, uint32_t k1, hipStream_t s);
+size_t mlp_stats_scratch_bytes();
+hipError_t launch_mlp_stats(const float *data, int64_t n, double box_q, unsigned char *blob, void *scratch,
+                            hipStream_t s);
+hipError_t launch_mlp_step(const MlpTrain &t, const float *data, int64_t n_rows, const int32_t *idx, uint32_t k0,
+                           uint32_t k1, int32_t step, int32_t batch, float lr, float bc1, float bc2, int apply,
+                           hipStream_t s);
+hipError_t launch_mlp_forward(const float *x, int64_t n, const unsigned char *blob, float *out, hipStream_t s);
 int batch_blocks_per_cu(int precision, int ctrl, bool noisy, int block);
 
 struct ReduceOut {

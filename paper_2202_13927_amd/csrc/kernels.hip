@@ -5,6 +5,7 @@
 // reads its 19 FP64 parameters once (coalesced SoA) and writes its 64-byte metric
 // record once. Noise is drawn in the loop from Philox counters, never stored.
 #include "internal.hpp"
+#include "mlp.hpp"
 #include "model.hpp"
 #include "mpc.hpp"
 #include "rng.hpp"
@@ -87,7 +88,8 @@ hipError_t launch_population(const PopArgs &a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- simulation ----
-enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2 };
+enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2, kCtrlMlp = 3 };
+enum { kOutTraj = 1, kOutRecord = 2 };   // optional per-sample outputs (template bits)
 
 // Meals of one (patient, day): Philox block (day, patient, MEAL, slot) gives
 // carbs = max(0, mean + sd z) (cosine normal of u0, u1), integer jitter
@@ -155,13 +157,87 @@ template <typename R> struct CtrlConst {
     double ts_d;
 };
 
+// Inputs of the learned controller (and of the recorded behaviour-cloning rows), per lane:
+//   f0..f5  y_k, y_k-1, ..., y_k-5 (sensor history; y_0 repeated before the first sample),
+//   f6      insulin on board (S1 + S2) / (2 u_b tmaxI), 1 at the basal state,
+//   f7      glucose on board from the announced meals: D1 + D2 + A_G dhat_k T_s (mmol),
+//   f8..f11 BW, u_b, SIT, SID.
+// S1, S2, D1, D2 are the states of a controller-side replica of the insulin and meal
+// absorption subsystems driven by the delivered doses and the announced meals; both
+// subsystems are deterministic and the announcements exact, so the replica equals the
+// plant's states and is read from them (undoing the state scaling).
+template <typename R> struct PolicyLane {
+    R yh[5];             // y_k-1 .. y_k-5
+    R iob_s1, iob_s2;    // f6 = S1s iob_s1 + S2s iob_s2
+    R cob_d1, cob_dr;    // f7 = D1s cob_d1 + D2 + dhat cob_dr
+    R st[4];
+    int32_t fallbacks;   // samples on which the MPC acted instead of the network
+};
+
+// Per-wave LDS views of the learned controller (simulate_policy_kernel only).
+struct PolicyShared {
+    MlpNet net;          // BF16 weights + FP32 biases, staged once per workgroup
+    uint16_t *hs;        // [64][64] BF16 activations; the inputs use the first [64][16]
+    float *o;            // [64] network outputs
+    const float *mean, *istd, *lo, *hi;
+    int lane;
+};
+
+// Orders this wave's LDS writes before its later LDS reads (LDS operations of one wave
+// complete in order; the fences keep the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename R>
+__device__ __forceinline__ void policy_features(const PolicyLane<R> &P, const State<R> &s, R y, R dr, R f[kMlpIn])
+{
+    f[0] = y;
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+        f[1 + q] = P.yh[q];
+    f[6] = fmaf_t(s.S1s, P.iob_s1, s.S2s * P.iob_s2);
+    f[7] = fmaf_t(s.D1s, P.cob_d1, fmaf_t(dr, P.cob_dr, s.D2));
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        f[8 + q] = P.st[q];
+}
+
+// Network output o_k for the 64 lanes of the wave (all lanes must be active): normalise,
+// round to BF16, stage row `lane` of the input tile, run the MFMA chain.
+template <typename R>
+__device__ __forceinline__ float policy_forward(const PolicyShared &ps, const R f[kMlpIn])
+{
+    uint32_t w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        uint32_t v = 0u;
+        if (2 * q < kMlpIn)
+            v = f2bf(((float)f[2 * q] - ps.mean[2 * q]) * ps.istd[2 * q]);
+        if (2 * q + 1 < kMlpIn)
+            v |= (uint32_t)f2bf(((float)f[2 * q + 1] - ps.mean[2 * q + 1]) * ps.istd[2 * q + 1]) << 16;
+        w[q] = v;
+    }
+    uint4 *dst = (uint4 *)(ps.hs + ps.lane * kMlpInP);
+    dst[0] = uint4{w[0], w[1], w[2], w[3]};
+    dst[1] = uint4{w[4], w[5], w[6], w[7]};
+    wave_lds_sync();
+    mlp_forward(ps.net, ps.hs, ps.hs, ps.hs, ps.hs, ps.o, ps.lane, wave_lds_sync);
+    return ps.o[ps.lane];
+}
+
 // One sampling instant t_k: indicators on the true glucose, sensor value, controller,
 // held inputs, then the EM steps of [t_k, t_k+1). z[0..4] are the EM noise increments
-// (sqrt(h) sigma xi), z[5] the sensor noise (sqrt(R) v).
-template <typename R, int CTRL, bool TRAJ>
-__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t kk, int32_t k, const R *z,
-                                            State<R> &s, const StepConst<R> &c, const CtrlConst<R> &cc,
-                                            DayMeals<R> &ml, Lane<R> &L, MpcLane<R> &mp)
+// (sqrt(h) sigma xi), z[5] the sensor noise (sqrt(R) v). `live` is false for the padding
+// lanes of the learned controller's last wave, which compute but write nothing.
+template <typename R, int CTRL, int OUT>
+__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool live, int32_t kk, int32_t k,
+                                            const R *z, State<R> &s, const StepConst<R> &c,
+                                            const CtrlConst<R> &cc, DayMeals<R> &ml, Lane<R> &L, MpcLane<R> &mp,
+                                            PolicyLane<R> &pl, const PolicyShared &ps)
 {
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
@@ -194,6 +270,17 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
         ml.k3 = -1;
     }
 
+    constexpr bool kFeat = CTRL == kCtrlMlp || (OUT & kOutRecord);
+    R f[kMlpIn];
+    if (kFeat) {
+        if (k == 0) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q)
+                pl.yh[q] = y;
+        }
+        policy_features<R>(pl, s, y, dr, f);
+    }
+
     R u;
     if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
         if (k == 0)
@@ -206,10 +293,46 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
         L.y_prev = y;
     } else if (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
         u = mpc_step<R>((const R *)a.mpc, a.n, j, mp, y, dr, R(a.g_target - a.setpoint), a.mpc_iters);
+    } else if (CTRL == kCtrlMlp) {
+        // control state (CGM history, Kalman estimate, input plan): the network acts unless
+        // an input leaves the box it was trained on or it would raise insulin above basal
+        // while the sensor reads below 3.9 mmol/L; then the MPC solves its QP. The Kalman
+        // filter runs on every sample so the MPC is ready to take over.
+        const R *M = (const R *)a.mpc;
+        mpc_measure<R>(M, a.n, j, mp, y);
+        bool ood = false;
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q)
+            ood |= !(f[q] >= R(ps.lo[q]) && f[q] <= R(ps.hi[q]));
+        const float o = policy_forward<R>(ps, f);
+        R du;
+        if (ood || (y < R(3.9) && o > 1.f)) {
+            du = mpc_plan<R>(M, a.n, j, mp, dr, R(a.g_target - a.setpoint), a.mpc_iters);
+            u = cc.ub + du;
+            ++pl.fallbacks;
+        } else {
+            mpc_shift<R>(mp);
+            u = vmin(vmax(cc.ub * R(o), R(0)), cc.umax);
+            du = u - cc.ub;
+        }
+        mpc_predict<R>(M, a.n, j, mp, du, dr);
     } else {
         u = cc.u_open;
     }
-    if (TRAJ && j < a.n_traj) {
+    if (kFeat) {
+#pragma unroll
+        for (int q = 4; q > 0; --q)
+            pl.yh[q] = pl.yh[q - 1];
+        pl.yh[0] = y;
+    }
+    if ((OUT & kOutRecord) && live) {   // row (k, j): the 12 inputs, then u_k / u_b
+        float *row = a.record + ((int64_t)k * a.n + j) * (kMlpIn + 1);
+#pragma unroll
+        for (int q = 0; q < kMlpIn; ++q)
+            row[q] = (float)f[q];
+        row[kMlpIn] = (float)(u / cc.ub);
+    }
+    if ((OUT & kOutTraj) && live && j < a.n_traj) {
         a.traj[(0 * (int64_t)a.n_traj + j) * a.K + k] = (double)G;
         a.traj[(1 * (int64_t)a.n_traj + j) * a.K + k] = (double)y;
         a.traj[(2 * (int64_t)a.n_traj + j) * a.K + k] = (double)u;
@@ -223,8 +346,8 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, int32_t
 }
 
 // The whole horizon of patient j of the population described by a (one lane).
-template <typename R, int CTRL, bool NOISY, bool TRAJ>
-__device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
+template <typename R, int CTRL, bool NOISY, int OUT>
+__device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool live, const PolicyShared &ps)
 {
     const uint32_t pid = (uint32_t)(a.patient_base + j);
 
@@ -250,8 +373,22 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
     step_constants<R>(p, a.h, a.tau, a.ag, c);
 
     MpcLane<R> mp;
-    if (CTRL == kCtrlMpc)
+    if (CTRL == kCtrlMpc || CTRL == kCtrlMlp)
         mpc_load<R>((const R *)a.mpc, a.n, j, mp);
+    PolicyLane<R> pl;
+    if (CTRL == kCtrlMlp || (OUT & kOutRecord)) {
+        const double ti = p[kTmaxI], vi = p[kVI] * p[kBW];
+        const double c_ui = a.h / (ti * vi), b_i = a.h / ti;
+        pl.iob_s1 = R(1.0 / (c_ui * b_i * 2.0 * ub_d * ti));
+        pl.iob_s2 = R(1.0 / (c_ui * 2.0 * ub_d * ti));
+        pl.cob_d1 = R(p[kTmaxG] / a.h);
+        pl.cob_dr = R(a.ag * (double)a.ts_min);
+        pl.st[0] = R(p[kBW]);
+        pl.st[1] = R(ub_d);
+        pl.st[2] = R(p[kSIT]);
+        pl.st[3] = R(p[kSID]);
+        pl.fallbacks = 0;
+    }
 
     CtrlConst<R> cc;   // gains relative to u_b
     cc.kp = R(a.kp * ub_d);
@@ -297,13 +434,17 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
                 for (int q = 0; q < 12; ++q)
                     z[q] = R(0);
             }
-            sample_step<R, CTRL, TRAJ>(a, j, kk, k, z, s, c, cc, ml, L, mp);
-            sample_step<R, CTRL, TRAJ>(a, j, kk + 1, k + 1, z + 6, s, c, cc, ml, L, mp);
+            sample_step<R, CTRL, OUT>(a, j, live, kk, k, z, s, c, cc, ml, L, mp, pl, ps);
+            sample_step<R, CTRL, OUT>(a, j, live, kk + 1, k + 1, z + 6, s, c, cc, ml, L, mp, pl, ps);
         }
         if (!all_finite(s))
             L.status |= kStNonFinite;
     }
 
+    if (!live)
+        return;
+    if (CTRL == kCtrlMlp && a.fallback)
+        a.fallback[j] = pl.fallbacks;
     const int64_t st = a.out_stride;
     const int32_t K = (int32_t)a.K;
     a.sum_g[j] = L.sum_g;
@@ -321,12 +462,42 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j)
     a.status[j] = L.status;
 }
 
-template <typename R, int CTRL, bool NOISY, bool TRAJ>
+template <typename R, int CTRL, bool NOISY, int OUT>
 __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j < a.n)
-        run_patient<R, CTRL, NOISY, TRAJ>(a, j);
+        run_patient<R, CTRL, NOISY, OUT>(a, j, true, PolicyShared{});
+}
+
+// The learned controller: the same per-patient loop, with the network evaluated by each
+// wave for its 64 patients on every sample. The weights and biases are staged into LDS
+// once per workgroup; each wave owns an activation tile. Every lane of a wave takes part
+// in the MFMA chain, so the padding lanes of the last wave replay patient n - 1 and
+// write nothing.
+constexpr int kPolicyBlock = 256;
+constexpr int kPolicyWaveBytes = kMlpH * kMlpH * 2 + 64 * 4;
+
+template <typename R, bool NOISY, int OUT>
+__global__ __launch_bounds__(kPolicyBlock) void simulate_policy_kernel(const SimArgs a)
+{
+    __shared__ __align__(16) unsigned char lds[kMlpNetBytes + (kPolicyBlock / 64) * kPolicyWaveBytes];
+    for (int i = threadIdx.x; i < kMlpNetBytes / 16; i += kPolicyBlock)
+        ((uint4 *)lds)[i] = ((const uint4 *)a.mlp)[i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6;
+    unsigned char *wl = lds + kMlpNetBytes + wave * kPolicyWaveBytes;
+    PolicyShared ps;
+    ps.net = mlp_net(lds);
+    ps.hs = (uint16_t *)wl;
+    ps.o = (float *)(wl + kMlpH * kMlpH * 2);
+    ps.mean = (const float *)(a.mlp + kOffMean);
+    ps.istd = (const float *)(a.mlp + kOffIstd);
+    ps.lo = (const float *)(a.mlp + kOffLo);
+    ps.hi = (const float *)(a.mlp + kOffHi);
+    ps.lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * kPolicyBlock + threadIdx.x;
+    run_patient<R, kCtrlMlp, NOISY, OUT>(a, j < a.n ? j : a.n - 1, j < a.n, ps);
 }
 
 // ------------------------------------------------------------ batched arms ----
@@ -354,7 +525,7 @@ __global__ __launch_bounds__(BLOCK) void batch_kernel(const SimArgs *__restrict_
         const SimArgs &a = arms[w.arm];
         const int64_t j = (int64_t)w.first + threadIdx.x;
         if (j < a.n)
-            run_patient<R, CTRL, NOISY, false>(a, j);
+            run_patient<R, CTRL, NOISY, 0>(a, j, true, PolicyShared{});
     }
 }
 
@@ -428,22 +599,45 @@ int batch_blocks_per_cu(int precision, int ctrl, bool noisy, int block)
     return noisy ? resident_b<double, kCtrlOpen, true>(block) : resident_b<double, kCtrlOpen, false>(block);
 }
 
+template <typename R, int CTRL, bool NOISY, int OUT>
+static void launch_sim_o(const SimArgs &a, hipStream_t s)
+{
+    if (CTRL == kCtrlMlp) {
+        const unsigned blocks = (unsigned)((a.n + kPolicyBlock - 1) / kPolicyBlock);
+        hipLaunchKernelGGL((simulate_policy_kernel<R, NOISY, OUT>), dim3(blocks), dim3(kPolicyBlock), 0, s, a);
+    } else {
+        const unsigned blocks = (unsigned)((a.n + 255) / 256);
+        hipLaunchKernelGGL((simulate_kernel<R, CTRL, NOISY, OUT>), dim3(blocks), dim3(256), 0, s, a);
+    }
+}
+
+template <typename R, int CTRL, bool NOISY>
+static void launch_sim_n(const SimArgs &a, hipStream_t s)
+{
+    const bool traj = a.traj != nullptr && a.n_traj > 0;
+    const bool rec = a.record != nullptr;
+    if (CTRL == kCtrlMpc || CTRL == kCtrlMlp) {
+        if (rec) {
+            if (traj)
+                launch_sim_o<R, CTRL, NOISY, kOutTraj | kOutRecord>(a, s);
+            else
+                launch_sim_o<R, CTRL, NOISY, kOutRecord>(a, s);
+            return;
+        }
+    }
+    if (traj)
+        launch_sim_o<R, CTRL, NOISY, kOutTraj>(a, s);
+    else
+        launch_sim_o<R, CTRL, NOISY, 0>(a, s);
+}
+
 template <typename R, int CTRL>
 static hipError_t launch_sim_t(const SimArgs &a, bool noisy, hipStream_t s)
 {
-    const unsigned blocks = (unsigned)((a.n + 255) / 256);
-    const bool traj = a.traj != nullptr && a.n_traj > 0;
-    if (noisy) {
-        if (traj)
-            hipLaunchKernelGGL((simulate_kernel<R, CTRL, true, true>), dim3(blocks), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((simulate_kernel<R, CTRL, true, false>), dim3(blocks), dim3(256), 0, s, a);
-    } else {
-        if (traj)
-            hipLaunchKernelGGL((simulate_kernel<R, CTRL, false, true>), dim3(blocks), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((simulate_kernel<R, CTRL, false, false>), dim3(blocks), dim3(256), 0, s, a);
-    }
+    if (noisy)
+        launch_sim_n<R, CTRL, true>(a, s);
+    else
+        launch_sim_n<R, CTRL, false>(a, s);
     return hipGetLastError();
 }
 
@@ -453,6 +647,7 @@ static hipError_t launch_sim_r(const SimArgs &a, bool noisy, hipStream_t s)
     switch (a.ctrl) {
     case kCtrlPid: return launch_sim_t<R, kCtrlPid>(a, noisy, s);
     case kCtrlMpc: return launch_sim_t<R, kCtrlMpc>(a, noisy, s);
+    case kCtrlMlp: return launch_sim_t<R, kCtrlMlp>(a, noisy, s);
     default: return launch_sim_t<R, kCtrlOpen>(a, noisy, s);
     }
 }

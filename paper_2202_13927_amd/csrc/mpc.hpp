@@ -63,18 +63,23 @@ __device__ __forceinline__ void mpc_load(const R *__restrict__ M, int64_t n, int
     L.hi = M[(int64_t)kMumax * n + j] - L.ub;
 }
 
-// One controller sample: y is the sensor value, dhat the announced held intake (mmol/min),
-// gofs = G* - set point. Returns u.
+// The controller sample split in three parts, so that a learned policy can act while the
+// estimator keeps running: measurement update; plan (QP by projected gradient); time update.
 template <typename R>
-__device__ __forceinline__ R mpc_step(const R *__restrict__ M, int64_t n, int64_t j, MpcLane<R> &L, R y, R dhat,
-                                      R gofs, int iters)
+__device__ __forceinline__ void mpc_measure(const R *__restrict__ M, int64_t n, int64_t j, MpcLane<R> &L, R y)
 {
-    // measurement update
     const R innov = (y - L.gi_ss) - L.xh[kXGI];
 #pragma unroll
     for (int i = 0; i < kNx; ++i)
         L.xh[i] = fmaf_t(M[(int64_t)(kMK + i) * n + j], innov, L.xh[i]);
-    // QP linear term g = Gamma^T (F xh + w dhat + (G* - ybar) 1)
+}
+
+// Plan: QP linear term g = Gamma^T (F xh + w dhat + (G* - ybar) 1), warm start from the
+// shifted previous plan, `iters` projected-gradient steps. Returns u_0 - u_b.
+template <typename R>
+__device__ __forceinline__ R mpc_plan(const R *__restrict__ M, int64_t n, int64_t j, MpcLane<R> &L, R dhat, R gofs,
+                                      int iters)
+{
     R g[kMpcN];
 #pragma unroll
     for (int i = 0; i < kMpcN; ++i) {
@@ -84,7 +89,6 @@ __device__ __forceinline__ R mpc_step(const R *__restrict__ M, int64_t n, int64_
             acc = fmaf_t(M[(int64_t)(kMGx + i * kNx + c) * n + j], L.xh[c], acc);
         g[i] = acc;
     }
-    // warm start: previous plan shifted by one sample
 #pragma unroll
     for (int i = 0; i + 1 < kMpcN; ++i)
         L.dU[i] = L.dU[i + 1];
@@ -108,8 +112,22 @@ __device__ __forceinline__ R mpc_step(const R *__restrict__ M, int64_t n, int64_
             L.dU[i] = vmin(vmax(fmaf_t(-L.step, acc, L.dU[i]), L.lo), L.hi);
         }
     }
-    const R du = L.dU[0];
-    // time update with the applied input and the announced intake
+    return L.dU[0];
+}
+
+// The plan is not solved this sample (another policy acts): only shift it.
+template <typename R>
+__device__ __forceinline__ void mpc_shift(MpcLane<R> &L)
+{
+#pragma unroll
+    for (int i = 0; i + 1 < kMpcN; ++i)
+        L.dU[i] = L.dU[i + 1];
+}
+
+// Time update with the applied input deviation du and the announced intake.
+template <typename R>
+__device__ __forceinline__ void mpc_predict(const R *__restrict__ M, int64_t n, int64_t j, MpcLane<R> &L, R du, R dhat)
+{
     R nx[kNx];
 #pragma unroll
     for (int r = 0; r < kNx; ++r) {
@@ -122,6 +140,17 @@ __device__ __forceinline__ R mpc_step(const R *__restrict__ M, int64_t n, int64_
 #pragma unroll
     for (int r = 0; r < kNx; ++r)
         L.xh[r] = nx[r];
+}
+
+// One full MPC sample: y is the sensor value, dhat the announced held intake (mmol/min),
+// gofs = G* - set point. Returns u.
+template <typename R>
+__device__ __forceinline__ R mpc_step(const R *__restrict__ M, int64_t n, int64_t j, MpcLane<R> &L, R y, R dhat,
+                                      R gofs, int iters)
+{
+    mpc_measure<R>(M, n, j, L, y);
+    const R du = mpc_plan<R>(M, n, j, L, dhat, gofs, iters);
+    mpc_predict<R>(M, n, j, L, du, dhat);
     return L.ub + du;
 }
 

@@ -22,8 +22,12 @@ class TrialBuffers:
         tb = vct.vct_traj_bytes(self.traj_patients, int(trial["n_days"]), int(trial["ts_min"]))
         self.traj = torch.empty(tb // 8, dtype=torch.float64, device=device) if tb else None
         self.mpc = None
-        if int(trial["ctrl_kind"]) == vct.VCT_CTRL_MPC:
+        if int(trial["ctrl_kind"]) in (vct.VCT_CTRL_MPC, vct.VCT_CTRL_MLP):
             self.mpc = torch.empty(vct.vct_mpc_bytes(n, int(trial["precision"])), dtype=torch.uint8, device=device)
+        self.record = None     # optional float [K][n][13] (MPC / learned controller)
+        self.fallback = None   # optional int32 [n] (learned controller)
+        if int(trial["ctrl_kind"]) == vct.VCT_CTRL_MLP:
+            self.fallback = torch.zeros(n, dtype=torch.int32, device=device)
 
 
 def create_population(trial: dict, bufs: TrialBuffers, stream=None):
@@ -35,23 +39,25 @@ def mpc_setup(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
     vct.vct_mpc_setup(pop, vct.controller(trial), sim, bufs.mpc, stream)
 
 
-def simulate(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
-    sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj)
-    vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial, bufs.mpc), sim, stream)
+def simulate(trial: dict, pop, bufs: TrialBuffers, stream=None, mlp_blob=None) -> None:
+    sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj, bufs.record, bufs.fallback)
+    vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial, bufs.mpc, mlp_blob), sim, stream)
 
 
 def read_metrics(bufs: TrialBuffers, stream=None) -> dict:
     return vct.vct_read_metrics(bufs.metrics, bufs.n, bufs.K, stream).as_dict()
 
 
-def run(trial: dict, device="cuda", traj_patients: int = 0, stream=None, bufs: TrialBuffers | None = None):
-    """Population -> simulation -> reduction. Returns (summary dict, buffers)."""
+def run(trial: dict, device="cuda", traj_patients: int = 0, stream=None, bufs: TrialBuffers | None = None,
+        mlp_blob=None):
+    """Population -> (MPC setup) -> simulation -> reduction. Returns (summary dict, buffers).
+    The learned controller (ctrl_kind MLP) needs mlp_blob, a trained network blob."""
     bufs = bufs or TrialBuffers(trial, device, traj_patients)
     pop = create_population(trial, bufs, stream)
     try:
         if bufs.mpc is not None:
             mpc_setup(trial, pop, bufs, stream)
-        simulate(trial, pop, bufs, stream)
+        simulate(trial, pop, bufs, stream, mlp_blob)
         summary = read_metrics(bufs, stream)
     finally:
         vct.vct_destroy_population(pop)
@@ -70,6 +76,10 @@ def to_host(bufs: TrialBuffers) -> dict:
     if bufs.traj is not None:
         t = bufs.traj.view(3, bufs.traj_patients, bufs.K).cpu().numpy()
         out["traj_g"], out["traj_y"], out["traj_u"] = t[0], t[1], t[2]
+    if bufs.record is not None:
+        out["record"] = bufs.record.view(bufs.K, bufs.n, 13).cpu().numpy()
+    if bufs.fallback is not None:
+        out["fallback"] = bufs.fallback.cpu().numpy()
     return out
 
 

@@ -19,6 +19,13 @@ VCT_OK, VCT_EINVAL, VCT_ENOMEM, VCT_EHIP, VCT_ESTATE, VCT_ENOTSUP = 0, -1, -2, -
 VCT_CTRL_OPEN, VCT_CTRL_PID, VCT_CTRL_MPC, VCT_CTRL_MLP = 0, 1, 2, 3
 VCT_FP64, VCT_FP32 = 0, 1
 VCT_POP_MIN_BASAL = 1
+VCT_MLP_IN, VCT_MLP_PARAMS, VCT_MLP_BLOB_BYTES = 12, 10448, 21568
+# byte offsets inside a learned-controller blob
+MLP_BLOB = {"W1": 0, "W2": 2048, "W3": 10240, "W4": 18432, "b1": 20480, "b2": 20736, "b3": 20992, "b4": 21248,
+            "mean": 21312, "istd": 21376, "lo": 21440, "hi": 21504}
+# FP32 parameter order (padded shapes) of master / Adam moments / gradient
+MLP_PARAM_SHAPES = (("W1", (64, 16)), ("W2", (64, 64)), ("W3", (64, 64)), ("W4", (16, 64)), ("b1", (64,)),
+                    ("b2", (64,)), ("b3", (64,)), ("b4", (16,)))
 
 # byte offsets of the per-patient metric arrays inside a metrics buffer of n patients
 METRIC_LAYOUT = (("sum_g", "f8", 0, 1), ("min_g", "f8", 8, 1), ("sum_u", "f8", 16, 1),
@@ -41,13 +48,15 @@ class vct_protocol(C.Structure):
 class vct_controller(C.Structure):
     _fields_ = [("kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
                 ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double), ("mpc_horizon", C.c_int32),
-                ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double), ("mpc_dev", C.c_void_p)]
+                ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double), ("mpc_dev", C.c_void_p),
+                ("mlp_dev", C.c_void_p)]
 
 
 class vct_sim(C.Structure):
     _fields_ = [("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("precision", C.c_int32),
                 ("sigma_q1", C.c_double), ("cgm_var", C.c_double), ("noise_seed", C.c_uint64),
-                ("metrics_dev", C.c_void_p), ("traj_patients", C.c_int32), ("traj_dev", C.c_void_p)]
+                ("metrics_dev", C.c_void_p), ("traj_patients", C.c_int32), ("traj_dev", C.c_void_p),
+                ("record_dev", C.c_void_p), ("fallback_dev", C.c_void_p)]
 
 
 class vct_summary(C.Structure):
@@ -91,7 +100,8 @@ class VctError(RuntimeError):
 EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_metrics_bytes", "vct_traj_bytes",
            "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population",
            "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy", "vct_mpc_bytes",
-           "vct_mpc_setup")
+           "vct_mpc_setup", "vct_mlp_blob_bytes", "vct_mlp_train_bytes", "vct_mlp_init", "vct_mlp_normalize",
+           "vct_mlp_train_step", "vct_mlp_forward")
 
 _lib = None
 
@@ -134,6 +144,19 @@ def lib() -> C.CDLL:
         L.vct_mpc_bytes.restype = C.c_size_t
         L.vct_mpc_setup.argtypes = [C.c_void_p, C.POINTER(vct_controller), C.POINTER(vct_sim), C.c_void_p, C.c_void_p]
         L.vct_mpc_setup.restype = C.c_int
+        L.vct_mlp_blob_bytes.argtypes = []
+        L.vct_mlp_blob_bytes.restype = C.c_size_t
+        L.vct_mlp_train_bytes.argtypes = [C.c_int32]
+        L.vct_mlp_train_bytes.restype = C.c_size_t
+        L.vct_mlp_init.argtypes = [C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vct_mlp_init.restype = C.c_int
+        L.vct_mlp_normalize.argtypes = [C.c_void_p, C.c_int64, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vct_mlp_normalize.restype = C.c_int
+        L.vct_mlp_train_step.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32,
+                                         C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vct_mlp_train_step.restype = C.c_int
+        L.vct_mlp_forward.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vct_mlp_forward.restype = C.c_int
         _lib = L
     return _lib
 
@@ -212,6 +235,35 @@ def vct_mpc_setup(pop, ctrl: vct_controller, sim: vct_sim, mpc_dev, stream=None)
     _check("vct_mpc_setup", lib().vct_mpc_setup(pop, C.byref(ctrl), C.byref(sim), _ptr(mpc_dev), _stream(stream)))
 
 
+def vct_mlp_blob_bytes() -> int:
+    return lib().vct_mlp_blob_bytes()
+
+
+def vct_mlp_train_bytes(batch: int) -> int:
+    return lib().vct_mlp_train_bytes(batch)
+
+
+def vct_mlp_init(seed: int, train_dev, blob_dev, stream=None) -> None:
+    _check("vct_mlp_init", lib().vct_mlp_init(int(seed), _ptr(train_dev), _ptr(blob_dev), _stream(stream)))
+
+
+def vct_mlp_normalize(rows_dev, n_rows: int, box_q: float, train_dev, blob_dev, stream=None) -> None:
+    _check("vct_mlp_normalize", lib().vct_mlp_normalize(_ptr(rows_dev), int(n_rows), float(box_q),
+                                                         _ptr(train_dev), _ptr(blob_dev), _stream(stream)))
+
+
+def vct_mlp_train_step(rows_dev, n_rows: int, idx_dev, seed: int, step: int, batch: int, lr: float, apply: bool,
+                       train_dev, blob_dev, stream=None) -> None:
+    _check("vct_mlp_train_step",
+           lib().vct_mlp_train_step(_ptr(rows_dev), int(n_rows), _ptr(idx_dev), int(seed), int(step), int(batch),
+                                    float(lr), int(bool(apply)), _ptr(train_dev), _ptr(blob_dev), _stream(stream)))
+
+
+def vct_mlp_forward(x_dev, n: int, blob_dev, out_dev, stream=None) -> None:
+    _check("vct_mlp_forward", lib().vct_mlp_forward(_ptr(x_dev), int(n), _ptr(blob_dev), _ptr(out_dev),
+                                                     _stream(stream)))
+
+
 def vct_batch_create(arms, protocol: vct_protocol, ctrl: vct_controller, sim: vct_sim, block: int = 0,
                      stream=None) -> C.c_void_p:
     arr = (vct_arm * len(arms))(*arms)
@@ -261,17 +313,19 @@ def protocol(trial: dict) -> vct_protocol:
     return p
 
 
-def controller(trial: dict, mpc_dev=None) -> vct_controller:
+def controller(trial: dict, mpc_dev=None, mlp_dev=None) -> vct_controller:
     c = vct_controller()
     c.kind = int(trial["ctrl_kind"])
     for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel", "mpc_rho"):
         setattr(c, k, float(trial[k]))
     c.mpc_horizon, c.mpc_iters = int(trial["mpc_horizon"]), int(trial["mpc_iters"])
     c.mpc_dev = _ptr(mpc_dev)
+    c.mlp_dev = _ptr(mlp_dev)
     return c
 
 
-def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None) -> vct_sim:
+def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None, record_dev=None,
+                 fallback_dev=None) -> vct_sim:
     s = vct_sim()
     s.n_days, s.em_per_ctrl, s.ts_min = int(trial["n_days"]), int(trial["em_per_ctrl"]), int(trial["ts_min"])
     s.precision = int(trial["precision"])
@@ -280,6 +334,8 @@ def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None
     s.metrics_dev = _ptr(metrics_dev)
     s.traj_patients = int(traj_patients)
     s.traj_dev = _ptr(traj_dev)
+    s.record_dev = _ptr(record_dev)
+    s.fallback_dev = _ptr(fallback_dev)
     return s
 
 

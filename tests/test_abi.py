@@ -67,3 +67,29 @@ def test_read_metrics_rejects():
         vct.vct_read_metrics(1 << 20, 0, 100)
     with pytest.raises(vct.VctError):
         vct.vct_read_metrics(1 << 20, 10, 0)
+
+
+def test_mlp_sizes_and_rejects():
+    assert vct.vct_mlp_blob_bytes() == vct.VCT_MLP_BLOB_BYTES
+    P = vct.VCT_MLP_PARAMS
+    assert vct.vct_mlp_train_bytes(100) == 0 and vct.vct_mlp_train_bytes(0) == 0
+    assert vct.vct_mlp_train_bytes(64) >= 16 * P + 4
+    assert vct.vct_mlp_train_bytes(4096) >= 16 * P + 4096 // 64 * 4 * P
+    fake = 1 << 20
+    bad = [
+        lambda: vct.vct_mlp_init(1, None, fake),
+        lambda: vct.vct_mlp_init(1, fake + 8, fake),                        # misaligned training buffer
+        lambda: vct.vct_mlp_normalize(fake, 0, 0.0, fake, fake),
+        lambda: vct.vct_mlp_normalize(fake, 10, 0.5, fake, fake),
+        lambda: vct.vct_mlp_train_step(fake, 100, None, 1, 0, 100, 1e-3, 1, fake, fake),     # batch not x64
+        lambda: vct.vct_mlp_train_step(fake, 100, None, 1, -1, 64, 1e-3, 1, fake, fake),
+        lambda: vct.vct_mlp_train_step(fake, 100, None, 1, 0, 64, float("nan"), 1, fake, fake),
+        lambda: vct.vct_mlp_train_step(fake, 0, None, 1, 0, 64, 1e-3, 1, fake, fake),
+        lambda: vct.vct_mlp_forward(fake, 0, fake, fake),
+        lambda: vct.vct_mlp_forward(fake, 10, fake + 4, fake),
+    ]
+    for f in bad:
+        with pytest.raises(vct.VctError) as e:
+            f()
+        assert e.value.code == vct.VCT_EINVAL
+
