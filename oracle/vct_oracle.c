@@ -938,9 +938,11 @@ static void mlp_inputs(const orc_config *cfg, const double *p, double ub, const 
 
 /* The network acts unless an input is outside its box or it would raise insulin above basal
  * (out > 1) while y_k < 3.9 mmol/L; then the MPC solves its QP. The Kalman filter runs on
- * every sample; when the network acts the MPC's plan is only shifted. */
+ * every sample; when the network acts the MPC's plan is only shifted. With `label` non-NULL
+ * (data aggregation along the network's closed loop) the QP is solved on every sample and
+ * *label receives the MPC's action, whoever acts. */
 static double mlp_step(const orc_config *cfg, mpc_state *st, const double f[ORC_MLP_IN], double y, double dhat,
-                       int32_t *fallbacks)
+                       int32_t *fallbacks, double *label)
 {
     const orc_mlp *net = cfg->mlp;
     mpc_measure(st, y);
@@ -950,17 +952,24 @@ static double mlp_step(const orc_config *cfg, mpc_state *st, const double f[ORC_
     for (int q = 0; q < ORC_MLP_IN; ++q)
         if (!(f[q] >= net->lo[q] && f[q] <= net->hi[q]))
             ood = 1;
+    const int fb = ood || (y < 3.9 && o > 1.0);
+    double du_mpc = 0.0;
+    if (fb || label)
+        du_mpc = mpc_plan(cfg, st, dhat);
+    else
+        mpc_shift(st);
     double u, du;
-    if (ood || (y < 3.9 && o > 1.0)) {
-        du = mpc_plan(cfg, st, dhat);
+    if (fb) {
+        du = du_mpc;
         u = st->m.ub + du;
         ++*fallbacks;
     } else {
-        mpc_shift(st);
         u = st->m.ub * o;
         u = u < 0.0 ? 0.0 : (u > st->m.umax ? st->m.umax : u);
         du = u - st->m.ub;
     }
+    if (label)
+        *label = st->m.ub + du_mpc;
     mpc_predict(st, du, dhat);
     return u;
 }
@@ -1042,7 +1051,7 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
                 if (meals[m].kd == kd)
                     d += meals[m].rate;
 
-            double f[ORC_MLP_IN];
+            double f[ORC_MLP_IN], label = NAN;
             if (use_inputs) {
                 if (k == 0)
                     for (int i = 1; i < 6; ++i) yh[i] = y;
@@ -1056,16 +1065,16 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
             else if (cfg->ctrl_kind == ORC_CTRL_MPC)
                 u = mpc ? mpc_step(cfg, mpc, y, d) : NAN;
             else if (cfg->ctrl_kind == ORC_CTRL_MLP)
-                u = mpc ? mlp_step(cfg, mpc, f, y, d, &fallbacks) : NAN;
+                u = mpc ? mlp_step(cfg, mpc, f, y, d, &fallbacks, out->record ? &label : NULL) : NAN;
             else
                 u = cfg->u_rel * ub;
 
             if (use_inputs) {
                 for (int i = 5; i > 0; --i) yh[i] = yh[i - 1];
-                if (out->record) {
+                if (out->record) {   /* inputs, then the MPC's action / u_b */
                     double *row = out->record + (k * count + j) * (ORC_MLP_IN + 1);
                     for (int q = 0; q < ORC_MLP_IN; ++q) row[q] = f[q];
-                    row[ORC_MLP_IN] = u / ub;
+                    row[ORC_MLP_IN] = (cfg->ctrl_kind == ORC_CTRL_MLP ? label : u) / ub;
                 }
             }
 

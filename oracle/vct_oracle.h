@@ -137,7 +137,8 @@ typedef struct {
     int32_t   n_traj;      /* trajectories for the first n_traj patients      */
     double   *traj_g, *traj_y, *traj_u;   /* [n_traj][K] (any may be NULL)   */
     double   *traj_x;      /* [n_traj][K][ORC_NX] state at each sample or NULL */
-    double   *record;      /* [K][count][13] controller inputs + u/u_b (MPC, MLP) or NULL */
+    double   *record;      /* [K][count][13] controller inputs, then the MPC's action / u_b
+                              (MPC; MLP: the QP is then solved on every sample) or NULL */
     int32_t  *fallback;    /* [count] samples on which the MPC acted for the MLP, or NULL */
 } orc_outputs;
 

@@ -255,9 +255,22 @@ vct_status vct_simulate(const vct_population *pop, const vct_protocol *pr, const
         g_err = "vct_simulate: " + g_err;
         return st;
     }
-    hipError_t e = vct::launch_simulate(a, sim->precision, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    void *scratch = nullptr;
+    if (ctrl->kind == VCT_CTRL_MLP) {
+        const size_t nb = vct::policy_scratch_bytes(a.n, sim->precision);
+        hipError_t e = hipMallocAsync(&scratch, nb, s);
+        if (e != hipSuccess)
+            return fail(VCT_ENOMEM, "vct_simulate: learned-controller scratch of %zu bytes: %s", nb,
+                        hipGetErrorString(e));
+        vct::policy_scratch_views(a, scratch, sim->precision);
+    }
+    hipError_t e = vct::launch_simulate(a, sim->precision, s);
+    hipError_t e2 = scratch ? hipFreeAsync(scratch, s) : hipSuccess;
     if (e != hipSuccess)
         return hip_fail(e, "vct_simulate: launch");
+    if (e2 != hipSuccess)
+        return hip_fail(e2, "vct_simulate: free");
     return VCT_OK;
 }
 

@@ -40,6 +40,9 @@ struct SimArgs {
     const unsigned char *mlp;   // learned-controller blob (VCT_CTRL_MLP) or null
     float *record;        // [K][n][13] learned-controller inputs + u/u_b, or null
     int32_t *fallback;    // [n] samples on which the MLP handed over to the MPC, or null
+    void *plan;           // learned controller: [kMpcN][n] input plans (working precision)
+    int32_t *kplan;       //   [n] sample index at which each plan was computed
+    const int32_t *order; //   [n] lane -> patient (patients outside the input box last)
     // integration
     int32_t ts_min, em_per_ctrl;
     double h, sig_sqh, sqrt_r;
@@ -98,6 +101,10 @@ hipError_t launch_mlp_step(const MlpTrain &t, const float *data, int64_t n_rows,
                            hipStream_t s);
 hipError_t launch_mlp_forward(const float *x, int64_t n, const unsigned char *blob, float *out, hipStream_t s);
 int batch_blocks_per_cu(int precision, int ctrl, bool noisy, int block);
+// Learned controller: scratch of launch_simulate (plans, plan times, lane order, partition
+// counts) and its layout.
+size_t policy_scratch_bytes(int64_t n, int precision);
+void policy_scratch_views(SimArgs &a, void *scratch, int precision);
 
 struct ReduceOut {
     uint64_t bins[5];

@@ -4,6 +4,8 @@
 // constants, the controller state and the metric accumulators stay in VGPRs; a patient
 // reads its 19 FP64 parameters once (coalesced SoA) and writes its 64-byte metric
 // record once. Noise is drawn in the loop from Philox counters, never stored.
+#include <algorithm>
+
 #include "internal.hpp"
 #include "mlp.hpp"
 #include "model.hpp"
@@ -174,7 +176,8 @@ template <typename R> struct PolicyLane {
     int32_t fallbacks;   // samples on which the MPC acted instead of the network
 };
 
-// Per-wave LDS views of the learned controller (simulate_policy_kernel only).
+// LDS views of the learned controller (simulate_policy_kernel only): the staged blob and the
+// wave's activation tile.
 struct PolicyShared {
     MlpNet net;          // BF16 weights + FP32 biases, staged once per workgroup
     uint16_t *hs;        // [64][64] BF16 activations; the inputs use the first [64][16]
@@ -213,20 +216,111 @@ __device__ __forceinline__ float policy_forward(const PolicyShared &ps, const R 
 {
     uint32_t w[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        uint32_t v = 0u;
-        if (2 * q < kMlpIn)
-            v = f2bf(((float)f[2 * q] - ps.mean[2 * q]) * ps.istd[2 * q]);
-        if (2 * q + 1 < kMlpIn)
-            v |= (uint32_t)f2bf(((float)f[2 * q + 1] - ps.mean[2 * q + 1]) * ps.istd[2 * q + 1]) << 16;
-        w[q] = v;
-    }
-    uint4 *dst = (uint4 *)(ps.hs + ps.lane * kMlpInP);
+    for (int q = 0; q < 8; ++q)
+        w[q] = 2 * q < kMlpIn ? pack_bf16(((float)f[2 * q] - ps.mean[2 * q]) * ps.istd[2 * q],
+                                          ((float)f[2 * q + 1] - ps.mean[2 * q + 1]) * ps.istd[2 * q + 1])
+                              : 0u;
+    uint4 *dst = (uint4 *)(ps.hs + ps.lane * PaddedLayout::ldi);
     dst[0] = uint4{w[0], w[1], w[2], w[3]};
     dst[1] = uint4{w[4], w[5], w[6], w[7]};
     wave_lds_sync();
-    mlp_forward(ps.net, ps.hs, ps.hs, ps.hs, ps.hs, ps.o, ps.lane, wave_lds_sync);
+    mlp_forward<PaddedLayout>(ps.net, ps.hs, ps.hs, ps.hs, ps.hs, ps.o, ps.lane, wave_lds_sync);
     return ps.o[ps.lane];
+}
+
+// ------------------------------------------------------ wave-cooperative QP ----
+// The MPC's QP for one patient of the learned controller (its fallback, and the labels when
+// recording), solved by the whole wave: lane i < 24 owns entry i of the plan and the two
+// Toeplitz products of a projected-gradient step become 24 steps of a one-lane shift (DPP
+// wave_shr:1 / wave_shl:1 with zero fill) and an FMA with the uniform Markov parameter
+// h_d. The summation orders are those of mpc_pg, so the result equals the SIMD solver's.
+// The plan lives in global memory, untouched while the network acts: the warm start at
+// sample k is the plan computed at sample k_plan moved on k - k_plan samples (entries past
+// the horizon repeat the last), exactly what shifting it once per sample would give.
+__device__ __forceinline__ float lane_shr1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float lane_shl1(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xF, 0xF, true));
+}
+__device__ __forceinline__ double lane_shr1(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_shl1(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_read(float v, int l)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double lane_read(double v, int l)
+{
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), l),
+                            __builtin_amdgcn_readlane(__double2loint(v), l));
+}
+__device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+// Solve the QP of the patient of lane L (all lanes must be active). Returns u_0 - u_b of
+// that patient, uniform across the wave; stores its plan when it is a live lane.
+template <typename R>
+__device__ __forceinline__ R coop_qp(const SimArgs &a, const R *__restrict__ M, int64_t j, bool live, int32_t k,
+                                     const MpcState<R> &ms, R dhat, int L, int lane)
+{
+    const uint32_t jL = (uint32_t)lane_read((int)j, L);
+    const bool liveL = lane_read((int)live, L) != 0;
+    R xh[kNx];
+#pragma unroll
+    for (int c = 0; c < kNx; ++c)
+        xh[c] = lane_read(ms.xh[c], L);
+    const R dh = lane_read(dhat, L), step = lane_read(ms.step, L), rho = lane_read(ms.rho_p, L);
+    const R lo = lane_read(ms.lo, L), hi = lane_read(ms.hi, L);
+    const bool act = lane < kMpcN;
+    const int i = act ? lane : 0;
+    // linear term g_i (the order of mpc_linear_term)
+    R g = fmaf_t(soa<R>(M, a.n, jL, kMgd + i), dh, soa<R>(M, a.n, jL, kMg1 + i) * R(a.g_target - a.setpoint));
+#pragma unroll
+    for (int c = 0; c < kNx; ++c)
+        g = fmaf_t(soa<R>(M, a.n, jL, kMGx + i * kNx + c), xh[c], g);
+    const R hl = soa<R>(M, a.n, jL, kMh + i);
+    R h[kMpcN];
+#pragma unroll
+    for (int d = 0; d < kMpcN; ++d)
+        h[d] = lane_read(hl, d);
+    auto P = as_global((R *)a.plan);
+    auto KP = as_global(a.kplan);
+    const int32_t sh = min(max(k - KP[jL], 0), kMpcN - 1);
+    R dU = act ? P[(int64_t)min(i + sh, kMpcN - 1) * a.n + jL] : R(0);
+    for (int it = 0; it < a.mpc_iters; ++it) {
+        R s = dU, r = R(0);
+#pragma unroll
+        for (int d = 0; d < kMpcN; ++d) {
+            r = fmaf_t(h[d], s, r);
+            if (d + 1 < kMpcN)
+                s = lane_shr1(s);
+        }
+        r = act ? r : R(0);
+        R acc = fmaf_t(rho, dU, g), t = r;
+#pragma unroll
+        for (int d = 0; d < kMpcN; ++d) {
+            acc = fmaf_t(h[d], t, acc);
+            if (d + 1 < kMpcN)
+                t = lane_shl1(t);
+        }
+        dU = act ? vmin(vmax(fmaf_t(-step, acc, dU), lo), hi) : R(0);
+    }
+    if (liveL && act)
+        P[(int64_t)i * a.n + jL] = dU;
+    if (liveL && lane == 0)
+        KP[jL] = k;
+    return lane_read(dU, 0);
 }
 
 // One sampling instant t_k: indicators on the true glucose, sensor value, controller,
@@ -236,7 +330,8 @@ __device__ __forceinline__ float policy_forward(const PolicyShared &ps, const R 
 template <typename R, int CTRL, int OUT>
 __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool live, int32_t kk, int32_t k,
                                             const R *z, State<R> &s, const StepConst<R> &c,
-                                            const CtrlConst<R> &cc, DayMeals<R> &ml, Lane<R> &L, MpcLane<R> &mp,
+                                            const CtrlConst<R> &cc, DayMeals<R> &ml, Lane<R> &L, MpcState<R> &ms,
+                                            MpcPlan<R> &mplan, const LinStep<R> &lin,
                                             PolicyLane<R> &pl, const PolicyShared &ps)
 {
     // indicators (Sec. IV-A ranges) on G(t_k)
@@ -281,7 +376,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         policy_features<R>(pl, s, y, dr, f);
     }
 
-    R u;
+    R u, label = R(0);
     if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
         if (k == 0)
             L.y_prev = y;
@@ -292,30 +387,42 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
             L.integ += e * cc.ts;
         L.y_prev = y;
     } else if (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
-        u = mpc_step<R>((const R *)a.mpc, a.n, j, mp, y, dr, R(a.g_target - a.setpoint), a.mpc_iters);
+        u = mpc_step<R>((const R *)a.mpc, a.n, j, ms, mplan, c, lin, R(a.h), R(a.h * a.ag), a.em_per_ctrl, y, dr,
+                        R(a.g_target - a.setpoint), a.mpc_iters);
     } else if (CTRL == kCtrlMlp) {
         // control state (CGM history, Kalman estimate, input plan): the network acts unless
         // an input leaves the box it was trained on or it would raise insulin above basal
         // while the sensor reads below 3.9 mmol/L; then the MPC solves its QP. The Kalman
-        // filter runs on every sample so the MPC is ready to take over.
+        // filter runs on every sample so the MPC is ready to take over. With recording on,
+        // the MPC's QP is solved on every sample and its action recorded as the label of
+        // the network's inputs (data aggregation along the network's own closed loop).
         const R *M = (const R *)a.mpc;
-        mpc_measure<R>(M, a.n, j, mp, y);
+        mpc_measure<R>(M, a.n, j, ms, y);
         bool ood = false;
 #pragma unroll
         for (int q = 0; q < kMlpIn; ++q)
             ood |= !(f[q] >= R(ps.lo[q]) && f[q] <= R(ps.hi[q]));
         const float o = policy_forward<R>(ps, f);
+        const bool fb = ood || (y < R(3.9) && o > 1.f);
+        // every live lane that needs the MPC's action gets it from a wave-cooperative solve
+        R du_mpc = R(0);
+        for (uint64_t need = __ballot(live && (fb || (OUT & kOutRecord))); need; need &= need - 1) {
+            const int L = __builtin_ctzll(need);
+            const R d = coop_qp<R>(a, M, j, live, k, ms, dr, L, ps.lane);
+            if (ps.lane == L)
+                du_mpc = d;
+        }
         R du;
-        if (ood || (y < R(3.9) && o > 1.f)) {
-            du = mpc_plan<R>(M, a.n, j, mp, dr, R(a.g_target - a.setpoint), a.mpc_iters);
+        if (fb) {
+            du = du_mpc;
             u = cc.ub + du;
             ++pl.fallbacks;
         } else {
-            mpc_shift<R>(mp);
             u = vmin(vmax(cc.ub * R(o), R(0)), cc.umax);
             du = u - cc.ub;
         }
-        mpc_predict<R>(M, a.n, j, mp, du, dr);
+        label = cc.ub + du_mpc;
+        mpc_predict<R>(ms, c, lin, du, dr, R(a.h), R(a.h * a.ag), a.em_per_ctrl);
     } else {
         u = cc.u_open;
     }
@@ -326,11 +433,11 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         pl.yh[0] = y;
     }
     if ((OUT & kOutRecord) && live) {   // row (k, j): the 12 inputs, then u_k / u_b
-        float *row = a.record + ((int64_t)k * a.n + j) * (kMlpIn + 1);
+        auto row = as_global(a.record) + ((int64_t)k * a.n + j) * (kMlpIn + 1);
 #pragma unroll
         for (int q = 0; q < kMlpIn; ++q)
             row[q] = (float)f[q];
-        row[kMlpIn] = (float)(u / cc.ub);
+        row[kMlpIn] = (float)((CTRL == kCtrlMlp ? label : u) / cc.ub);
     }
     if ((OUT & kOutTraj) && live && j < a.n_traj) {
         a.traj[(0 * (int64_t)a.n_traj + j) * a.K + k] = (double)G;
@@ -372,9 +479,26 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     StepConst<R> c;
     step_constants<R>(p, a.h, a.tau, a.ag, c);
 
-    MpcLane<R> mp;
-    if (CTRL == kCtrlMpc || CTRL == kCtrlMlp)
-        mpc_load<R>((const R *)a.mpc, a.n, j, mp);
+    MpcState<R> ms;
+    MpcPlan<R> mplan;
+    LinStep<R> lin;
+    if (CTRL == kCtrlMpc || CTRL == kCtrlMlp) {
+        mpc_load_state<R>((const R *)a.mpc, a.n, j, ms);
+        lin_step_constants<R>(p, istar, a.h, a.g_target, lin);
+    }
+    if (CTRL == kCtrlMpc) {
+        mpc_load_h<R>((const R *)a.mpc, a.n, j, mplan.h);
+#pragma unroll
+        for (int i = 0; i < kMpcN; ++i)
+            mplan.dU[i] = R(0);
+    }
+    if (CTRL == kCtrlMlp && live) {   // empty plan, computed "before" sample 0
+        R *P = (R *)a.plan;
+#pragma unroll
+        for (int i = 0; i < kMpcN; ++i)
+            P[(int64_t)i * a.n + j] = R(0);
+        a.kplan[j] = -1;
+    }
     PolicyLane<R> pl;
     if (CTRL == kCtrlMlp || (OUT & kOutRecord)) {
         const double ti = p[kTmaxI], vi = p[kVI] * p[kBW];
@@ -434,8 +558,8 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
                 for (int q = 0; q < 12; ++q)
                     z[q] = R(0);
             }
-            sample_step<R, CTRL, OUT>(a, j, live, kk, k, z, s, c, cc, ml, L, mp, pl, ps);
-            sample_step<R, CTRL, OUT>(a, j, live, kk + 1, k + 1, z + 6, s, c, cc, ml, L, mp, pl, ps);
+            sample_step<R, CTRL, OUT>(a, j, live, kk, k, z, s, c, cc, ml, L, ms, mplan, lin, pl, ps);
+            sample_step<R, CTRL, OUT>(a, j, live, kk + 1, k + 1, z + 6, s, c, cc, ml, L, ms, mplan, lin, pl, ps);
         }
         if (!all_finite(s))
             L.status |= kStNonFinite;
@@ -472,32 +596,209 @@ __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
 
 // The learned controller: the same per-patient loop, with the network evaluated by each
 // wave for its 64 patients on every sample. The weights and biases are staged into LDS
-// once per workgroup; each wave owns an activation tile. Every lane of a wave takes part
-// in the MFMA chain, so the padding lanes of the last wave replay patient n - 1 and
-// write nothing.
+// once per workgroup; each wave owns an activation tile. Lanes take patients in the order
+// a.order (patients whose fixed inputs lie outside the box, and so hand every sample to
+// the MPC, gathered in the last waves instead of stalling 64-lane waves of network
+// patients). Every lane of a wave takes part in the MFMA chain, so the padding lanes of
+// the last wave replay a patient and write nothing.
 constexpr int kPolicyBlock = 256;
-constexpr int kPolicyWaveBytes = kMlpH * kMlpH * 2 + 64 * 4;
+// LDS image of the blob with padded row strides (PaddedLayout): W1 [64][24], W2 and W3
+// [64][72], W4 [16][72], then the biases, normalisation and box as in the blob.
+constexpr int kLdsW1 = 0;
+constexpr int kLdsW2 = kLdsW1 + kMlpH * PaddedLayout::ldw1 * 2;
+constexpr int kLdsW3 = kLdsW2 + kMlpH * PaddedLayout::ldw * 2;
+constexpr int kLdsW4 = kLdsW3 + kMlpH * PaddedLayout::ldw * 2;
+constexpr int kLdsTail = kLdsW4 + kMlpOutP * PaddedLayout::ldw * 2;
+constexpr int kLdsNet = kLdsTail + (kMlpBlobBytes - kOffB1);
+constexpr int kPolicyWaveBytes = kMlpH * PaddedLayout::ldh * 2 + 64 * 4;
+
+__device__ __forceinline__ void stage_padded(const unsigned char *blob, unsigned char *lds, int tid, int nthreads)
+{
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const auto src = as_global((const u32x4 *)blob);
+    // 16-byte chunks: W1 128, W2 512, W3 512, W4 128, tail 68
+    for (int c = tid; c < 128 + 512 + 512 + 128 + 68; c += nthreads) {
+        int soff, doff;
+        if (c < 128) {                 // W1: 2 chunks per row
+            soff = kOffW1 + c * 16;
+            doff = kLdsW1 + (c >> 1) * PaddedLayout::ldw1 * 2 + (c & 1) * 16;
+        } else if (c < 640) {          // W2: 8 chunks per row
+            const int q = c - 128;
+            soff = kOffW2 + q * 16;
+            doff = kLdsW2 + (q >> 3) * PaddedLayout::ldw * 2 + (q & 7) * 16;
+        } else if (c < 1152) {         // W3
+            const int q = c - 640;
+            soff = kOffW3 + q * 16;
+            doff = kLdsW3 + (q >> 3) * PaddedLayout::ldw * 2 + (q & 7) * 16;
+        } else if (c < 1280) {         // W4
+            const int q = c - 1152;
+            soff = kOffW4 + q * 16;
+            doff = kLdsW4 + (q >> 3) * PaddedLayout::ldw * 2 + (q & 7) * 16;
+        } else {                       // biases, normalisation, box
+            const int q = c - 1280;
+            soff = kOffB1 + q * 16;
+            doff = kLdsTail + q * 16;
+        }
+        *(u32x4 *)(lds + doff) = src[soff / 16];
+    }
+}
 
 template <typename R, bool NOISY, int OUT>
-__global__ __launch_bounds__(kPolicyBlock) void simulate_policy_kernel(const SimArgs a)
+__global__ __launch_bounds__(kPolicyBlock, 2) void simulate_policy_kernel(const SimArgs a, const int32_t *counts,
+                                                                          int32_t nb, uint32_t *queue)
 {
-    __shared__ __align__(16) unsigned char lds[kMlpNetBytes + (kPolicyBlock / 64) * kPolicyWaveBytes];
-    for (int i = threadIdx.x; i < kMlpNetBytes / 16; i += kPolicyBlock)
-        ((uint4 *)lds)[i] = ((const uint4 *)a.mlp)[i];
+    __shared__ __align__(16) unsigned char lds[kLdsNet + (kPolicyBlock / 64) * kPolicyWaveBytes];
+    stage_padded(a.mlp, lds, threadIdx.x, kPolicyBlock);
     __syncthreads();
     const int wave = threadIdx.x >> 6;
-    unsigned char *wl = lds + kMlpNetBytes + wave * kPolicyWaveBytes;
+    unsigned char *wl = lds + kLdsNet + wave * kPolicyWaveBytes;
     PolicyShared ps;
-    ps.net = mlp_net(lds);
+    ps.net.W1 = (const uint16_t *)(lds + kLdsW1);
+    ps.net.W2 = (const uint16_t *)(lds + kLdsW2);
+    ps.net.W3 = (const uint16_t *)(lds + kLdsW3);
+    ps.net.W4 = (const uint16_t *)(lds + kLdsW4);
+    ps.net.b1 = (const float *)(lds + kLdsTail + (kOffB1 - kOffB1));
+    ps.net.b2 = (const float *)(lds + kLdsTail + (kOffB2 - kOffB1));
+    ps.net.b3 = (const float *)(lds + kLdsTail + (kOffB3 - kOffB1));
+    ps.net.b4 = (const float *)(lds + kLdsTail + (kOffB4 - kOffB1));
     ps.hs = (uint16_t *)wl;
-    ps.o = (float *)(wl + kMlpH * kMlpH * 2);
-    ps.mean = (const float *)(a.mlp + kOffMean);
-    ps.istd = (const float *)(a.mlp + kOffIstd);
-    ps.lo = (const float *)(a.mlp + kOffLo);
-    ps.hi = (const float *)(a.mlp + kOffHi);
+    ps.o = (float *)(wl + kMlpH * PaddedLayout::ldh * 2);
+    ps.mean = (const float *)(lds + kLdsTail + (kOffMean - kOffB1));
+    ps.istd = (const float *)(lds + kLdsTail + (kOffIstd - kOffB1));
+    ps.lo = (const float *)(lds + kLdsTail + (kOffLo - kOffB1));
+    ps.hi = (const float *)(lds + kLdsTail + (kOffHi - kOffB1));
     ps.lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * kPolicyBlock + threadIdx.x;
-    run_patient<R, kCtrlMlp, NOISY, OUT>(a, j < a.n ? j : a.n - 1, j < a.n, ps);
+    // Work items, longest first: each patient outside the box alone on a wave (the MPC acts
+    // on every sample, solved cooperatively), then tiles of 64 patients inside the box.
+    const int32_t n_in = counts[nb];
+    const int32_t n_rest = (int32_t)a.n - n_in;
+    const int32_t n_items = n_rest + (n_in + 63) / 64;
+    for (;;) {
+        int32_t item = 0;
+        if (ps.lane == 0)
+            item = (int32_t)atomicAdd(queue, 1u);
+        item = __builtin_amdgcn_readfirstlane(item);
+        if (item >= n_items)
+            break;
+        int64_t slot;
+        bool live;
+        if (item < n_rest) {
+            slot = (int64_t)n_in + item;
+            live = ps.lane == 0;
+        } else {
+            const int64_t s0 = (int64_t)(item - n_rest) * 64 + ps.lane;
+            live = s0 < n_in;
+            slot = live ? s0 : (int64_t)n_in - 1;
+        }
+        run_patient<R, kCtrlMlp, NOISY, OUT>(a, (int64_t)a.order[slot], live, ps);
+    }
+}
+
+// Lane order of the learned controller: a stable partition of the patients into those whose
+// fixed inputs (BW, u_b, SIT, SID) lie inside the network's box and the rest, in three
+// launches (per-block counts, one-block scan, scatter). Only the placement of patients on
+// lanes depends on it, never a result.
+constexpr int kPartBlock = 1024;
+
+template <typename R>
+__device__ __forceinline__ bool fixed_inputs_in_box(const SimArgs &a, int64_t j)
+{
+    const float *lo = (const float *)(a.mlp + kOffLo), *hi = (const float *)(a.mlp + kOffHi);
+    const R v[4] = {R(a.params[(int64_t)kBW * a.n + j]), R(a.params[(int64_t)kUb * a.n + j]),
+                    R(a.params[(int64_t)kSIT * a.n + j]), R(a.params[(int64_t)kSID * a.n + j])};
+    bool in = true;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+        in = in && v[q] >= R(lo[8 + q]) && v[q] <= R(hi[8 + q]);
+    return in;
+}
+
+template <typename R>
+__global__ __launch_bounds__(kPartBlock) void policy_count_kernel(const SimArgs a, int32_t *counts)
+{
+    const int64_t j = (int64_t)blockIdx.x * kPartBlock + threadIdx.x;
+    const int c = __syncthreads_count(j < a.n && fixed_inputs_in_box<R>(a, j));
+    if (threadIdx.x == 0)
+        counts[blockIdx.x] = c;
+}
+
+// Exclusive scan of counts[0 .. nb) in place; counts[nb] = total.
+__global__ __launch_bounds__(kPartBlock) void policy_scan_kernel(int32_t *counts, int32_t nb)
+{
+    __shared__ int32_t part[kPartBlock];
+    int32_t carry = 0;
+    for (int32_t base = 0; base < nb; base += kPartBlock) {
+        const int32_t i = base + (int32_t)threadIdx.x;
+        const int32_t v = i < nb ? counts[i] : 0;
+        part[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < kPartBlock; off <<= 1) {
+            const int32_t t = (int)threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+            __syncthreads();
+            part[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nb)
+            counts[i] = carry + part[threadIdx.x] - v;
+        carry += part[kPartBlock - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        counts[nb] = carry;
+        counts[nb + 1] = 0;   // work-queue head of the simulation launch that follows
+    }
+}
+
+template <typename R>
+__global__ __launch_bounds__(kPartBlock) void policy_scatter_kernel(const SimArgs a, const int32_t *scan,
+                                                                    int32_t *order)
+{
+    __shared__ int32_t wsum[kPartBlock / 64];
+    const int64_t j = (int64_t)blockIdx.x * kPartBlock + threadIdx.x;
+    const bool valid = j < a.n;
+    const bool in = valid && fixed_inputs_in_box<R>(a, j);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const uint64_t m = __ballot(in);
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+    if (lane == 0)
+        wsum[w] = __popcll(m);
+    __syncthreads();
+    int32_t rank_in = __popcll(m & below);
+    for (int q = 0; q < w; ++q)
+        rank_in += wsum[q];
+    if (valid) {
+        const int32_t in_before = scan[blockIdx.x];
+        const int64_t pos = in ? (int64_t)in_before + rank_in
+                               : (int64_t)scan[gridDim.x] + ((int64_t)blockIdx.x * kPartBlock - in_before) +
+                                     ((int32_t)threadIdx.x - rank_in);
+        order[pos] = (int32_t)j;
+    }
+}
+
+size_t policy_scratch_bytes(int64_t n, int precision)
+{
+    const size_t rb = precision == 1 ? sizeof(float) : sizeof(double);
+    const int64_t nb = (n + kPartBlock - 1) / kPartBlock;
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    // plans, plan times, lane order, per-block counts + total + work-queue head
+    return up((size_t)kMpcN * n * rb) + up((size_t)n * 4) + up((size_t)n * 4) + up((size_t)(nb + 2) * 4);
+}
+
+void policy_scratch_views(SimArgs &a, void *scratch, int precision)
+{
+    const size_t rb = precision == 1 ? sizeof(float) : sizeof(double);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    char *p = (char *)scratch;
+    a.plan = p;
+    p += up((size_t)kMpcN * a.n * rb);
+    a.kplan = (int32_t *)p;
+    p += up((size_t)a.n * 4);
+    a.order = (const int32_t *)p;
+}
+
+static int32_t *policy_counts(const SimArgs &a)
+{
+    return (int32_t *)((char *)a.order + (((size_t)a.n * 4 + 255) & ~(size_t)255));
 }
 
 // ------------------------------------------------------------ batched arms ----
@@ -603,8 +904,23 @@ template <typename R, int CTRL, bool NOISY, int OUT>
 static void launch_sim_o(const SimArgs &a, hipStream_t s)
 {
     if (CTRL == kCtrlMlp) {
-        const unsigned blocks = (unsigned)((a.n + kPolicyBlock - 1) / kPolicyBlock);
-        hipLaunchKernelGGL((simulate_policy_kernel<R, NOISY, OUT>), dim3(blocks), dim3(kPolicyBlock), 0, s, a);
+        const unsigned nb = (unsigned)((a.n + kPartBlock - 1) / kPartBlock);
+        int32_t *counts = policy_counts(a);
+        hipLaunchKernelGGL((policy_count_kernel<R>), dim3(nb), dim3(kPartBlock), 0, s, a, counts);
+        hipLaunchKernelGGL(policy_scan_kernel, dim3(1), dim3(kPartBlock), 0, s, counts, (int32_t)nb);
+        hipLaunchKernelGGL((policy_scatter_kernel<R>), dim3(nb), dim3(kPartBlock), 0, s, a, (const int32_t *)counts,
+                           (int32_t *)a.order);
+        // persistent grid: every resident workgroup, but no more waves than there can be items
+        int dev = 0, cus = 0, per_cu = 0;
+        hipGetDevice(&dev);
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, simulate_policy_kernel<R, NOISY, OUT>, kPolicyBlock,
+                                                         0) != hipSuccess)
+            per_cu = 1;
+        const int64_t need = (a.n + kPolicyBlock / 64 - 1) / (kPolicyBlock / 64);
+        const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * std::max(1, per_cu)));
+        hipLaunchKernelGGL((simulate_policy_kernel<R, NOISY, OUT>), dim3(blocks), dim3(kPolicyBlock), 0, s, a,
+                           (const int32_t *)counts, (int32_t)nb, (uint32_t *)(counts + nb + 1));
     } else {
         const unsigned blocks = (unsigned)((a.n + 255) / 256);
         hipLaunchKernelGGL((simulate_kernel<R, CTRL, NOISY, OUT>), dim3(blocks), dim3(256), 0, s, a);

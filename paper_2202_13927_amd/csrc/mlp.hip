@@ -275,7 +275,7 @@ __global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ 
     __syncthreads();
 
     const MlpNet n = mlp_net(net);
-    mlp_forward(n, xs, h1, h2, h3, o, lane, wave_sync);
+    mlp_forward<DenseLayout>(n, xs, h1, h2, h3, o, lane, wave_sync);
 
     float *g = partial + (int64_t)blockIdx.x * kMlpParams;
     const float r = o[lane] - target;
@@ -371,7 +371,7 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict
     for (int f = 0; f < kMlpInP; ++f)
         xs[lane * kMlpInP + f] = f < kMlpIn ? f2bf((x[row * kMlpIn + f] - mean[f]) * istd[f]) : (uint16_t)0;
     __syncthreads();
-    mlp_forward(mlp_net(net), xs, hs, hs, hs, o, lane, wave_sync);
+    mlp_forward<DenseLayout>(mlp_net(net), xs, hs, hs, hs, o, lane, wave_sync);
     if (gi < n)
         out[gi] = o[lane];
 }

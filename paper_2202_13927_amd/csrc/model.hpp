@@ -20,6 +20,20 @@
 
 namespace vct {
 
+// Pointers read from the argument structs are generic; casting them to the global address
+// space lets the compiler emit global (not flat) loads, which do not share the LDS wait
+// counter and can take a scalar base.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *as_global(const T *p)
+{
+    return (const __attribute__((address_space(1))) T *)p;
+}
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *as_global(T *p)
+{
+    return (__attribute__((address_space(1))) T *)p;
+}
+
 __device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }

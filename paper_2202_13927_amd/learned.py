@@ -34,17 +34,12 @@ def _timed(fn, stream=None):
     return out, e0.elapsed_time(e1) / 1000.0
 
 
-def train_policy(train_trial: dict, epochs: float = 10.0, batch: int = 4096, lr: float = 1e-3, box_q: float = 0.0,
-                 seed: int = 100, log=print) -> tuple[PL.Policy, dict]:
-    """Steps 1-2. Returns the trained policy and a report (data-set size, times, losses)."""
-    rows, mpc_summary = PL.record_dataset(train_trial)
+def _fit(rows: torch.Tensor, epochs: float, batch: int, lr: float, box_q: float, seed: int, log) -> tuple:
     n_rows = rows.shape[0]
     pol = PL.Policy(batch=batch)
     pol.init(seed)
     pol.normalize(rows, box_q)
     steps = int(math.ceil(epochs * n_rows / batch))
-    log(f"[learned] data set {n_rows} rows from {train_trial['n_patients']} x {train_trial['n_days']} d; "
-        f"{steps} steps of {batch}")
     t0 = time.perf_counter()
     pol.step(rows, seed, 0.0, apply=False)
     loss0 = float(pol.loss().item())
@@ -57,11 +52,39 @@ def train_policy(train_trial: dict, epochs: float = 10.0, batch: int = 4096, lr:
         x = rows[a:a + (1 << 22)]
         out = pol.forward(x[:, :12].contiguous())
         se += float(((out - x[:, 12]) ** 2).double().sum().item())
-    rep = {"rows": int(n_rows), "steps": steps, "batch": batch, "epochs": epochs, "train_s": train_s,
-           "loss_first_batch": loss0, "loss_log": losses, "mse_full": se / n_rows,
-           "mpc_train_tir": mpc_summary["mean_tir"], "box_q": box_q}
-    log(f"[learned] trained in {train_s:.2f} s, minibatch loss {loss0:.4f} -> {losses[-1][1]:.4f}, "
-        f"data-set MSE {rep['mse_full']:.4f}")
+    rep = {"rows": int(n_rows), "steps": steps, "train_s": train_s, "loss_first_batch": loss0,
+           "loss_last_batch": losses[-1][1], "mse_full": se / n_rows}
+    log(f"[learned] {n_rows} rows, {steps} steps of {batch} in {train_s:.2f} s: minibatch loss {loss0:.4f} -> "
+        f"{losses[-1][1]:.4f}, data-set MSE {rep['mse_full']:.4f}")
+    return pol, rep
+
+
+def train_policy(train_trial: dict, epochs: float = 10.0, batch: int = 4096, lr: float = 1e-3, box_q: float = 0.0,
+                 seed: int = 100, aggregate_rounds: int = 0, log=print) -> tuple[PL.Policy, dict]:
+    """Steps 1-2, optionally followed by rounds of data aggregation: run the current network
+    (with fallback) on the training population under fresh noise, label every sample with the
+    MPC's action along that closed loop, append the rows and refit on all rows so far.
+    Returns the trained policy and a report (data-set sizes, times, losses)."""
+    rows, mpc_summary = PL.record_dataset(train_trial)
+    log(f"[learned] MPC data set from {train_trial['n_patients']} x {train_trial['n_days']} d, "
+        f"TIR {mpc_summary['mean_tir']:.4f}")
+    pol, fit = _fit(rows, epochs, batch, lr, box_q, seed, log)
+    rounds = [fit]
+    for r in range(1, aggregate_rounds + 1):
+        t = W.with_(train_trial, ctrl_kind=W.CTRL_MLP, noise_seed=int(train_trial["noise_seed"]) + 1000 * r)
+        bufs = T.TrialBuffers(t)
+        new = torch.empty(bufs.K * bufs.n * PL.ROW, dtype=torch.float32, device="cuda")
+        bufs.record = new
+        summ, _ = T.run(t, bufs=bufs, mlp_blob=pol.blob)
+        log(f"[learned] round {r}: network closed loop TIR {summ['mean_tir']:.4f}, fallback "
+            f"{float(bufs.fallback.double().sum().item()) / (bufs.n * bufs.K):.4%}")
+        rows = torch.cat([rows, new.view(-1, PL.ROW)])
+        del bufs, new
+        pol, fit = _fit(rows, epochs, batch, lr, box_q, seed + r, log)
+        fit["loop_tir"] = summ["mean_tir"]
+        rounds.append(fit)
+    rep = {"batch": batch, "epochs": epochs, "box_q": box_q, "mpc_train_tir": mpc_summary["mean_tir"],
+           "rounds": rounds}
     return pol, rep
 
 

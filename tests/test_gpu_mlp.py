@@ -386,3 +386,19 @@ def test_training_reduces_loss_and_is_deterministic(G):
         assert np.mean([l for _, l in log[-2:]]) < 0.1 * l0
         blobs.append(pol.blob.cpu().numpy().copy())
     assert np.array_equal(blobs[0], blobs[1])
+
+
+def test_labels_with_empty_box_equal_mpc_rows(G):
+    """Data aggregation: recording with the learned controller labels each sample with the
+    MPC's action; with an empty box the closed loop is the MPC's, so the rows equal the MPC
+    arm's rows bit for bit."""
+    torch, policy, trial = G
+    t = _mlp_trial(n_patients=100)
+    pol = policy.Policy(batch=64)
+    pol.load(W.constant_policy_net(2.0, always_fallback=True))
+    bufs = trial.TrialBuffers(t)
+    bufs.record = torch.empty(bufs.K * bufs.n * 13, dtype=torch.float32, device="cuda")
+    _say("[gpu] learned controller with labels, empty box")
+    trial.run(t, bufs=bufs, mlp_blob=pol.blob)
+    rows_mpc, _ = policy.record_dataset(W.with_(t, ctrl_kind=W.CTRL_MPC))
+    assert torch.equal(bufs.record.view(-1, 13), rows_mpc)

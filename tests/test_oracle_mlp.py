@@ -223,3 +223,17 @@ def test_recorded_rows(orc):
         assert np.all(rec[:k0, j, 7] == 0.0)
         grams = first[j][0][2]
         assert rec[k0, j, 7] == pytest.approx(0.8 * grams * 1000.0 / 180.16, rel=1e-12)
+
+
+def test_labels_along_own_loop(orc):
+    """Recording with the learned controller labels every sample with the MPC's action; with
+    an empty box the MPC acts everywhere, so the rows equal those of the MPC's own loop."""
+    t = _small(W.c5_mlp(), n_patients=10)
+    a = orc.simulate(t, threads=4, record=True, mlp=W.constant_policy_net(2.0, always_fallback=True))
+    b = orc.simulate(W.with_(t, ctrl_kind=W.CTRL_MPC), threads=4, record=True)
+    assert np.array_equal(a["record"], b["record"])
+    # with a network that acts, the labels still come from the MPC (u/u_b = 2 is never applied
+    # below 3.9, and the labels differ from the applied 2)
+    c = orc.simulate(t, threads=4, record=True, n_traj=10, mlp=W.constant_policy_net(2.0))
+    applied = c["traj_u"].T / c["params"][:, 15]
+    assert np.any(np.abs(c["record"][:, :, 12] - applied) > 1e-3)
