@@ -106,13 +106,18 @@ typedef struct {
  * applies u_0 and predicts. The per-patient matrices come from vct_mpc_setup.
  * Learned controller (VCT_CTRL_MLP; needs mpc_dev and mlp_dev): a 12 -> 64 -> 64 -> 64 -> 1
  * ReLU network trained to imitate the MPC gives u_k = clamp(u_b out, 0, umax_rel u_b) from
- *   y_k .. y_k-5 (y_0 repeated before the first sample), (S1 + S2)/(2 u_b tmaxI),
- *   D1 + D2 + A_G dhat_k Ts (glucose on board from the announced meals, mmol),
- *   BW, u_b, SIT, SID,
- * where S1, S2, D1, D2 are the insulin and meal-absorption states driven by the delivered
- * doses and the announced meals. The Kalman filter of the MPC runs on every sample; the
+ *   y_k .. y_k-5 (y_0 repeated before the first sample);
+ *   insulin on board, as the mean change of G over the MPC's 24-sample prediction that the
+ *   insulin states' deviation from basal (S1, S2, I, x1, x2, x3) still causes (mmol/L);
+ *   the announced meals likewise: meal states D1, D2 and the intake announced now (mmol/L);
+ *   the patient: u_b, the insulin response over the horizon (sum of the MPC's Markov
+ *   parameters), its mean delay (sum m h_m / sum h_m, samples), BW,
+ * with the insulin and meal states those driven by the delivered doses and the announced
+ * meals, and the horizon means of the MPC's prediction rows and intake response (written
+ * by vct_mpc_setup). The Kalman filter of the MPC runs on every sample; the
  * MPC solves its QP and acts instead of the network (a "fallback") when any input lies
- * outside the box stored with the network, or when y_k < 3.9 mmol/L and out > 1. */
+ * outside the box stored with the network, or when y_k < mlp_safe_g and out > mlp_safe_out
+ * (e.g. 3.9 mmol/L and 1: never more than basal insulin while the sensor reads low). */
 typedef struct {
     int32_t kind;          /* VCT_CTRL_*                                           */
     double  setpoint;      /* mmol/L                                               */
@@ -124,6 +129,8 @@ typedef struct {
     double  mpc_rho;       /* > 0                                                   */
     const void *mpc_dev;   /* VCT_CTRL_MPC, VCT_CTRL_MLP: buffer filled by vct_mpc_setup */
     const void *mlp_dev;   /* VCT_CTRL_MLP: network blob (vct_mlp_blob_bytes), read-only */
+    double  mlp_safe_g;    /* VCT_CTRL_MLP: the MPC acts when y_k < mlp_safe_g (mmol/L) ... */
+    double  mlp_safe_out;  /*   ... and the network's output exceeds mlp_safe_out (u / u_b) */
 } vct_controller;
 
 /* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl

@@ -31,6 +31,7 @@ class OrcConfig(C.Structure):
         ("x0_offset", C.c_double * NX), ("guard_rel", C.c_double),
         ("mpc_horizon", C.c_int32), ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double),
         ("mpc_riccati_iters", C.c_int32), ("mpc_power_iters", C.c_int32), ("mlp", C.c_void_p),
+        ("mlp_safe_g", C.c_double), ("mlp_safe_out", C.c_double),
     ]
 
 
@@ -166,6 +167,8 @@ def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=N
     c.mpc_rho = float(trial.get("mpc_rho", 1.0))
     c.mpc_riccati_iters = int(trial.get("mpc_riccati_iters", 500))
     c.mpc_power_iters = int(trial.get("mpc_power_iters", 100))
+    c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.9))
+    c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
     return c
 
 

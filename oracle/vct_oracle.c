@@ -674,6 +674,9 @@ typedef struct {
     orc_mpc m;
     double xh[ORC_NX];     /* estimate of x - x_ss (prior before the measurement update) */
     double dU[ORC_NMAX];   /* planned u - u_b */
+    double Fbar[ORC_NX];   /* mean over the horizon of the prediction rows F_j */
+    double wbar;           /* mean over the horizon of the intake response w_j */
+    double hsum, hdelay;   /* sum of the Markov parameters, and their mean delay (samples) */
 } mpc_state;
 
 /* The controller sample in three parts: measurement update with the sensor value; the plan
@@ -918,26 +921,35 @@ void orc_adam(int64_t n, double *w, double *m, double *v, const double *g, doubl
     }
 }
 
-/* Inputs of the learned controller at a sample: the sensor history y_k..y_k-5, the insulin
- * on board relative to basal (S1 + S2)/(2 u_b tmaxI), the glucose on board from the
- * announced meals D1 + D2 + A_G dhat Ts (the insulin and absorption subsystems are
- * deterministic, so a controller-side replica driven by the doses and announcements has
- * the plant's values), and BW, u_b, SIT, SID. */
-static void mlp_inputs(const orc_config *cfg, const double *p, double ub, const double x[ORC_NX],
-                       const double yh[6], double dhat, double f[ORC_MLP_IN])
+/* Inputs of the learned controller at a sample: the sensor history y_k..y_k-5; the insulin
+ * on board, as the mean change of G over the MPC's prediction horizon that the insulin
+ * states' deviation from basal still causes, sum over S1, S2, I, x1, x2, x3 of
+ * Fbar_s (x_s - x*_s); the announced meals likewise, Fbar_D1 D1 + Fbar_D2 D2 + wbar dhat;
+ * and the patient: u_b, the insulin response over the horizon (sum of the Markov parameters
+ * h_1..h_N), its mean delay (sum m h_m / sum h_m, samples), BW. Fbar and wbar are the horizon
+ * means of the prediction rows and of the intake response. (The insulin and absorption subsystems are deterministic and the
+ * meals announced exactly, so a controller-side replica driven by the doses and the
+ * announcements has the plant's values.) */
+static void mlp_inputs(const mpc_state *st, const double *p, double ub, const double x[ORC_NX], const double yh[6],
+                       double dhat, double f[ORC_MLP_IN])
 {
+    static const int ins[6] = {X_S1, X_S2, X_I, X_X1, X_X2, X_X3};
     for (int i = 0; i < 6; ++i)
         f[i] = yh[i];
-    f[6] = (x[X_S1] + x[X_S2]) / (2.0 * ub * p[P_TMAXI]);
-    f[7] = x[X_D1] + x[X_D2] + cfg->ag * dhat * (double)cfg->ts_min;
-    f[8] = p[P_BW];
-    f[9] = ub;
-    f[10] = p[P_SIT];
-    f[11] = p[P_SID];
+    double a = 0.0;
+    for (int i = 0; i < 6; ++i)
+        a += st->Fbar[ins[i]] * (x[ins[i]] - st->m.xss[ins[i]]);
+    f[6] = a;
+    f[7] = st->Fbar[X_D1] * x[X_D1] + st->Fbar[X_D2] * x[X_D2] + st->wbar * dhat;
+    f[8] = ub;
+    f[9] = st->hsum;
+    f[10] = st->hdelay;
+    f[11] = p[P_BW];
 }
 
-/* The network acts unless an input is outside its box or it would raise insulin above basal
- * (out > 1) while y_k < 3.9 mmol/L; then the MPC solves its QP. The Kalman filter runs on
+/* The network acts unless an input is outside its box or, while the sensor reads low
+ * (y_k < mlp_safe_g), its output exceeds mlp_safe_out (e.g. 3.9 mmol/L and 1: not above basal);
+ * then the MPC solves its QP. The Kalman filter runs on
  * every sample; when the network acts the MPC's plan is only shifted. With `label` non-NULL
  * (data aggregation along the network's closed loop) the QP is solved on every sample and
  * *label receives the MPC's action, whoever acts. */
@@ -952,7 +964,7 @@ static double mlp_step(const orc_config *cfg, mpc_state *st, const double f[ORC_
     for (int q = 0; q < ORC_MLP_IN; ++q)
         if (!(f[q] >= net->lo[q] && f[q] <= net->hi[q]))
             ood = 1;
-    const int fb = ood || (y < 3.9 && o > 1.0);
+    const int fb = ood || (y < cfg->mlp_safe_g && o > cfg->mlp_safe_out);
     double du_mpc = 0.0;
     if (fb || label)
         du_mpc = mpc_plan(cfg, st, dhat);
@@ -1020,6 +1032,25 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
         if (!orc_mpc_setup(cfg, prm, &mpc->m)) {
             free(mpc);
             mpc = NULL;
+        } else {
+            const int N = mpc->m.N;
+            for (int c = 0; c < ORC_NX; ++c) {
+                double acc = 0.0;
+                for (int jj = 0; jj < N; ++jj)
+                    acc += mpc->m.F[jj * ORC_NX + c];
+                mpc->Fbar[c] = acc / N;
+            }
+            double wacc = 0.0;
+            for (int jj = 0; jj < N; ++jj)
+                wacc += mpc->m.w[jj];
+            mpc->wbar = wacc / N;
+            double hs = 0.0, hm = 0.0;
+            for (int m = 0; m < N; ++m) {
+                hs += mpc->m.h[m];
+                hm += (double)(m + 1) * mpc->m.h[m];
+            }
+            mpc->hsum = hs;
+            mpc->hdelay = hm / hs;
         }
     }
 
@@ -1056,7 +1087,10 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
                 if (k == 0)
                     for (int i = 1; i < 6; ++i) yh[i] = y;
                 yh[0] = y;
-                mlp_inputs(cfg, p, ub, x, yh, d, f);
+                if (mpc)
+                    mlp_inputs(mpc, p, ub, x, yh, d, f);
+                else
+                    for (int q = 0; q < ORC_MLP_IN; ++q) f[q] = NAN;
             }
 
             double u;
@@ -1148,6 +1182,8 @@ int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_thre
         return -1;
     if (cfg->ctrl_kind == ORC_CTRL_MLP && !cfg->mlp)
         return -1;
+    if (out->record && cfg->ctrl_kind != ORC_CTRL_MPC && cfg->ctrl_kind != ORC_CTRL_MLP)
+        return -1;   /* the recorded inputs and labels come from the MPC's model */
     if ((cfg->ctrl_kind == ORC_CTRL_MPC || cfg->ctrl_kind == ORC_CTRL_MLP) &&
         (cfg->mpc_horizon < 1 || cfg->mpc_horizon > ORC_NMAX || cfg->mpc_iters < 0 || cfg->mpc_riccati_iters < 0 ||
          cfg->mpc_power_iters < 1 || !(cfg->mpc_rho > 0.0)))

@@ -88,8 +88,10 @@ typedef struct {
     double   mpc_rho;           /* weight of ((u - u_b)/u_b)^2 */
     int32_t  mpc_riccati_iters; /* fixed Riccati iterations for the stationary Kalman gain */
     int32_t  mpc_power_iters;   /* power iterations for lambda_max(Gamma^T Gamma) */
-    /* learned controller (ORC_CTRL_MLP): the network, its input normalisation and box */
+    /* learned controller (ORC_CTRL_MLP): the network, its input normalisation and box, and
+       the safety hand-over: the MPC acts when y_k < mlp_safe_g and out > mlp_safe_out */
     const struct orc_mlp_s *mlp;
+    double   mlp_safe_g, mlp_safe_out;
 } orc_config;
 
 /* Learned controller: 12 inputs -> 64 -> 64 -> 64 -> 1, ReLU hidden layers. The inputs are

@@ -177,6 +177,8 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
         return fail(VCT_EINVAL, "record_dev needs the MPC or the learned controller");
     if (ctrl->kind == VCT_CTRL_MLP && (!ctrl->mlp_dev || (uintptr_t)ctrl->mlp_dev % 16 != 0))
         return fail(VCT_EINVAL, "learned controller needs mlp_dev (a 16-byte aligned network blob)");
+    if (ctrl->kind == VCT_CTRL_MLP && !(std::isfinite(ctrl->mlp_safe_g) && std::isfinite(ctrl->mlp_safe_out)))
+        return fail(VCT_EINVAL, "learned controller: mlp_safe_g and mlp_safe_out must be finite");
     if (uses_mpc) {
         if (!ctrl->mpc_dev)
             return fail(VCT_EINVAL, "MPC and learned controllers need mpc_dev (from vct_mpc_setup)");
@@ -222,6 +224,8 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.mpc = uses_mpc ? ctrl->mpc_dev : nullptr;
     a.mpc_iters = ctrl->mpc_iters;
     a.mlp = ctrl->kind == VCT_CTRL_MLP ? (const unsigned char *)ctrl->mlp_dev : nullptr;
+    a.mlp_safe_g = ctrl->mlp_safe_g;
+    a.mlp_safe_out = ctrl->mlp_safe_out;
     a.record = sim->record_dev;
     a.fallback = ctrl->kind == VCT_CTRL_MLP ? sim->fallback_dev : nullptr;
     a.ts_min = sim->ts_min;

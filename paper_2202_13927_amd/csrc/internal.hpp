@@ -38,6 +38,7 @@ struct SimArgs {
     const void *mpc;      // per-patient MPC data (SoA [kMRows][n], working precision) or null
     int32_t mpc_iters;
     const unsigned char *mlp;   // learned-controller blob (VCT_CTRL_MLP) or null
+    double mlp_safe_g, mlp_safe_out;   // MPC acts when y < mlp_safe_g and out > mlp_safe_out
     float *record;        // [K][n][13] learned-controller inputs + u/u_b, or null
     int32_t *fallback;    // [n] samples on which the MLP handed over to the MPC, or null
     void *plan;           // learned controller: [kMpcN][n] input plans (working precision)

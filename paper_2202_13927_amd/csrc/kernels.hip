@@ -161,20 +161,42 @@ template <typename R> struct CtrlConst {
 
 // Inputs of the learned controller (and of the recorded behaviour-cloning rows), per lane:
 //   f0..f5  y_k, y_k-1, ..., y_k-5 (sensor history; y_0 repeated before the first sample),
-//   f6      insulin on board (S1 + S2) / (2 u_b tmaxI), 1 at the basal state,
-//   f7      glucose on board from the announced meals: D1 + D2 + A_G dhat_k T_s (mmol),
-//   f8..f11 BW, u_b, SIT, SID.
-// S1, S2, D1, D2 are the states of a controller-side replica of the insulin and meal
-// absorption subsystems driven by the delivered doses and the announced meals; both
-// subsystems are deterministic and the announcements exact, so the replica equals the
-// plant's states and is read from them (undoing the state scaling).
+//   f6      insulin on board, as the mean change of G over the MPC's prediction horizon that
+//           the insulin states' deviation from basal (S1, S2, I, x1, x2, x3) still causes:
+//           Fbar_ins . (x_ins - x_ins*), mmol/L,
+//   f7      the announced meals, likewise: Fbar_D1 D1 + Fbar_D2 D2 + wbar dhat_k, mmol/L,
+//   f8..f11 the patient: u_b; the insulin response over the horizon, sum of the MPC's Markov
+//           parameters h_1..h_24 (mmol/L per mU/min held for one sample); its mean delay
+//           sum m h_m / sum h_m (samples); BW.
+// Fbar and wbar are the horizon means of the MPC's prediction rows and intake response. The
+// insulin and meal states are those of a controller-side replica of the insulin and
+// absorption subsystems driven by the delivered doses and the announced meals; both are
+// deterministic and the announcements exact, so the replica equals the plant's states and
+// is read from them (the coefficients below undo the state scaling).
 template <typename R> struct PolicyLane {
-    R yh[5];             // y_k-1 .. y_k-5
-    R iob_s1, iob_s2;    // f6 = S1s iob_s1 + S2s iob_s2
-    R cob_d1, cob_dr;    // f7 = D1s cob_d1 + D2 + dhat cob_dr
+    R yh[5];                 // y_k-1 .. y_k-5
+    R ins[6], ins0;          // f6 = ins . (S1s, S2s, I, x1h, x2h, e3) + ins0
+    R meal_d1, meal_d2, wbar;   // f7 = D1s meal_d1 + D2 meal_d2 + dhat wbar
     R st[4];
-    int32_t fallbacks;   // samples on which the MPC acted instead of the network
+    int32_t fallbacks;       // samples on which the MPC acted instead of the network
 };
+
+// The four patient inputs f8..f11 (see PolicyLane), from the population and MPC buffers.
+template <typename R>
+__device__ __forceinline__ void patient_inputs(const SimArgs &a, int64_t j, R out[4])
+{
+    const auto M = as_global((const R *)a.mpc);
+    double hs = 0.0, hm = 0.0;
+    for (int q = 0; q < kMpcN; ++q) {
+        const double v = (double)M[(int64_t)(kMh + q) * a.n + j];
+        hs += v;
+        hm += (double)(q + 1) * v;
+    }
+    out[0] = R(a.params[(int64_t)kUb * a.n + j]);
+    out[1] = R(hs);
+    out[2] = R(hm / hs);
+    out[3] = R(a.params[(int64_t)kBW * a.n + j]);
+}
 
 // LDS views of the learned controller (simulate_policy_kernel only): the staged blob and the
 // wave's activation tile.
@@ -202,8 +224,14 @@ __device__ __forceinline__ void policy_features(const PolicyLane<R> &P, const St
 #pragma unroll
     for (int q = 0; q < 5; ++q)
         f[1 + q] = P.yh[q];
-    f[6] = fmaf_t(s.S1s, P.iob_s1, s.S2s * P.iob_s2);
-    f[7] = fmaf_t(s.D1s, P.cob_d1, fmaf_t(dr, P.cob_dr, s.D2));
+    R a6 = P.ins0;
+    a6 = fmaf_t(P.ins[0], s.S1s, a6);
+    a6 = fmaf_t(P.ins[1], s.S2s, a6);
+    a6 = fmaf_t(P.ins[2], s.I, a6);
+    a6 = fmaf_t(P.ins[3], s.x1h, a6);
+    a6 = fmaf_t(P.ins[4], s.x2h, a6);
+    f[6] = fmaf_t(P.ins[5], s.e3, a6);
+    f[7] = fmaf_t(s.D1s, P.meal_d1, fmaf_t(s.D2, P.meal_d2, dr * P.wbar));
 #pragma unroll
     for (int q = 0; q < 4; ++q)
         f[8 + q] = P.st[q];
@@ -391,9 +419,9 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
                         R(a.g_target - a.setpoint), a.mpc_iters);
     } else if (CTRL == kCtrlMlp) {
         // control state (CGM history, Kalman estimate, input plan): the network acts unless
-        // an input leaves the box it was trained on or it would raise insulin above basal
-        // while the sensor reads below 3.9 mmol/L; then the MPC solves its QP. The Kalman
-        // filter runs on every sample so the MPC is ready to take over. With recording on,
+        // an input leaves the box it was trained on, or the sensor reads low (y < mlp_safe_g)
+        // while the network asks for more than mlp_safe_out u_b; then the MPC solves its QP.
+        // The Kalman filter runs on every sample so the MPC is ready to take over. With recording on,
         // the MPC's QP is solved on every sample and its action recorded as the label of
         // the network's inputs (data aggregation along the network's own closed loop).
         const R *M = (const R *)a.mpc;
@@ -403,7 +431,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         for (int q = 0; q < kMlpIn; ++q)
             ood |= !(f[q] >= R(ps.lo[q]) && f[q] <= R(ps.hi[q]));
         const float o = policy_forward<R>(ps, f);
-        const bool fb = ood || (y < R(3.9) && o > 1.f);
+        const bool fb = ood || (y < R(a.mlp_safe_g) && o > (float)a.mlp_safe_out);
         // every live lane that needs the MPC's action gets it from a wave-cooperative solve
         R du_mpc = R(0);
         for (uint64_t need = __ballot(live && (fb || (OUT & kOutRecord))); need; need &= need - 1) {
@@ -501,16 +529,28 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     }
     PolicyLane<R> pl;
     if (CTRL == kCtrlMlp || (OUT & kOutRecord)) {
-        const double ti = p[kTmaxI], vi = p[kVI] * p[kBW];
-        const double c_ui = a.h / (ti * vi), b_i = a.h / ti;
-        pl.iob_s1 = R(1.0 / (c_ui * b_i * 2.0 * ub_d * ti));
-        pl.iob_s2 = R(1.0 / (c_ui * 2.0 * ub_d * ti));
-        pl.cob_d1 = R(p[kTmaxG] / a.h);
-        pl.cob_dr = R(a.ag * (double)a.ts_min);
-        pl.st[0] = R(p[kBW]);
-        pl.st[1] = R(ub_d);
-        pl.st[2] = R(p[kSIT]);
-        pl.st[3] = R(p[kSID]);
+        // f6, f7 from the horizon-mean prediction rows (FP64 here, then the working precision)
+        const auto M = as_global((const R *)a.mpc);
+        double fb[kNx];
+#pragma unroll
+        for (int q = 0; q < kNx; ++q)
+            fb[q] = (double)M[(int64_t)(kMFbar + q) * a.n + j];
+        const double ti = p[kTmaxI], vi = p[kVI] * p[kBW], h = a.h, egp0 = p[kEGP0] * p[kBW];
+        const double c_ui = h / (ti * vi), b_i = h / ti;
+        // unscaled states: S1 = S1s/(c_ui b_i), S2 = S2s/c_ui, x1 = x1h/h, x2 = x2h/h,
+        // x3 = 1 - e3/(h EGP0); basal: S1* = S2* = u_b tmaxI, I*, x_j* = S_j I*
+        pl.ins[0] = R(fb[kXS1] / (c_ui * b_i));
+        pl.ins[1] = R(fb[kXS2] / c_ui);
+        pl.ins[2] = R(fb[kXI]);
+        pl.ins[3] = R(fb[kXx1] / h);
+        pl.ins[4] = R(fb[kXx2] / h);
+        pl.ins[5] = R(-fb[kXx3] / (h * egp0));
+        pl.ins0 = R(fb[kXx3] - (fb[kXS1] + fb[kXS2]) * ub_d * ti - fb[kXI] * istar -
+                    (fb[kXx1] * p[kSIT] + fb[kXx2] * p[kSID] + fb[kXx3] * p[kSIE]) * istar);
+        pl.meal_d1 = R(fb[kXD1] * p[kTmaxG] / h);
+        pl.meal_d2 = R(fb[kXD2]);
+        pl.wbar = R((double)M[(int64_t)kMwbar * a.n + j]);
+        patient_inputs<R>(a, j, pl.st);
         pl.fallbacks = 0;
     }
 
@@ -695,7 +735,7 @@ __global__ __launch_bounds__(kPolicyBlock, 2) void simulate_policy_kernel(const 
 }
 
 // Lane order of the learned controller: a stable partition of the patients into those whose
-// fixed inputs (BW, u_b, SIT, SID) lie inside the network's box and the rest, in three
+// fixed inputs f8..f11 lie inside the network's box and the rest, in three
 // launches (per-block counts, one-block scan, scatter). Only the placement of patients on
 // lanes depends on it, never a result.
 constexpr int kPartBlock = 1024;
@@ -704,8 +744,8 @@ template <typename R>
 __device__ __forceinline__ bool fixed_inputs_in_box(const SimArgs &a, int64_t j)
 {
     const float *lo = (const float *)(a.mlp + kOffLo), *hi = (const float *)(a.mlp + kOffHi);
-    const R v[4] = {R(a.params[(int64_t)kBW * a.n + j]), R(a.params[(int64_t)kUb * a.n + j]),
-                    R(a.params[(int64_t)kSIT * a.n + j]), R(a.params[(int64_t)kSID * a.n + j])};
+    R v[4];
+    patient_inputs<R>(a, j, v);
     bool in = true;
 #pragma unroll
     for (int q = 0; q < 4; ++q)

@@ -31,7 +31,9 @@ enum : int {
     kMgi = kMrho + 1,              // GI at the basal state (= G*)
     kMub = kMgi + 1,
     kMumax = kMub + 1,
-    kMRows = kMumax + 1
+    kMFbar = kMumax + 1,           // mean over the horizon of the prediction rows c_G A^(j+1)
+    kMwbar = kMFbar + kNx,         // mean over the horizon of the intake response c_G A^j E
+    kMRows = kMwbar + 1
 };
 
 // Model state order of the linear model (unscaled deviations).

@@ -7,7 +7,7 @@
 // the prediction of G = Q1/VG over 24 samples (Markov parameters h, free response F,
 // intake response w) condensed into Gamma^T F, Gamma^T w, Gamma^T 1; and the projected-
 // gradient step 1/(lambda_max(Gamma^T Gamma) + rho/u_b^2) with lambda from power
-// iteration. The matrices live in per-lane private arrays: this kernel runs once per trial.
+// iteration; and the horizon means of the prediction rows and of the intake response. The matrices live in per-lane private arrays: this kernel runs once per trial.
 #include "internal.hpp"
 #include "mpc.hpp"
 
@@ -221,6 +221,18 @@ __global__ __launch_bounds__(64) void mpc_setup_kernel(const MpcSetupArgs a, R *
     W(kMgi, a.g_target);
     W(kMub, ub);
     W(kMumax, a.umax_rel * ub);
+    // horizon means of the free-response rows and of the intake response: the learned
+    // controller's insulin and meal inputs are the mean glucose changes they predict
+    for (int c = 0; c < NX; ++c) {
+        double acc = 0.0;
+        for (int jj = 0; jj < kMpcN; ++jj)
+            acc += Fm[jj * NX + c];
+        W(kMFbar + c, acc / kMpcN);
+    }
+    double wacc = 0.0;
+    for (int jj = 0; jj < kMpcN; ++jj)
+        wacc += wm[jj];
+    W(kMwbar, wacc / kMpcN);
 }
 
 hipError_t launch_mpc_setup(const MpcSetupArgs &a, int precision, void *out, hipStream_t s)

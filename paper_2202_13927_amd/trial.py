@@ -83,7 +83,7 @@ def to_host(bufs: TrialBuffers) -> dict:
     return out
 
 
-MPC_ROWS = 11 * 11 + 3 * 11 + 24 * 11 + 3 * 24 + 5   # layout of csrc/mpc.hpp
+MPC_ROWS = 11 * 11 + 3 * 11 + 24 * 11 + 3 * 24 + 5 + 11 + 1   # layout of csrc/mpc.hpp
 
 
 def mpc_to_host(bufs: TrialBuffers, precision: int) -> dict:
@@ -95,7 +95,7 @@ def mpc_to_host(bufs: TrialBuffers, precision: int) -> dict:
     o = 0
     out = {}
     for name, rows in (("A", 121), ("B", 11), ("E", 11), ("K", 11), ("Gx", 264), ("gd", 24), ("g1", 24), ("h", 24),
-                       ("step", 1), ("rho_p", 1), ("gi", 1), ("ub", 1), ("umax", 1)):
+                       ("step", 1), ("rho_p", 1), ("gi", 1), ("ub", 1), ("umax", 1), ("Fbar", 11), ("wbar", 1)):
         out[name] = M[o:o + rows].T
         o += rows
     return out

@@ -49,7 +49,7 @@ class vct_controller(C.Structure):
     _fields_ = [("kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
                 ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double), ("mpc_horizon", C.c_int32),
                 ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double), ("mpc_dev", C.c_void_p),
-                ("mlp_dev", C.c_void_p)]
+                ("mlp_dev", C.c_void_p), ("mlp_safe_g", C.c_double), ("mlp_safe_out", C.c_double)]
 
 
 class vct_sim(C.Structure):
@@ -321,6 +321,8 @@ def controller(trial: dict, mpc_dev=None, mlp_dev=None) -> vct_controller:
     c.mpc_horizon, c.mpc_iters = int(trial["mpc_horizon"]), int(trial["mpc_iters"])
     c.mpc_dev = _ptr(mpc_dev)
     c.mlp_dev = _ptr(mlp_dev)
+    c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.9))
+    c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
     return c
 
 

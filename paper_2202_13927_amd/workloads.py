@@ -63,6 +63,10 @@ def base_trial() -> dict:
         "mpc_horizon": 24,
         "mpc_iters": 50,
         "mpc_rho": 1.0,
+        # learned controller: the MPC takes over while the sensor reads below mlp_safe_g
+        # (mmol/L) and the network asks for more than mlp_safe_out u_b
+        "mlp_safe_g": 3.9,
+        "mlp_safe_out": 1.0,
         # (3) model + simulation settings
         "n_days": 7,
         "em_per_ctrl": 5,
@@ -115,8 +119,9 @@ def c5_mpc(seed: int = 5) -> dict:
 
 def mlp_training_population(seed: int = 100) -> dict:
     """Separate population whose MPC closed loop produces the training pairs:
-    5,000 patients x 7 days = 10.08 M (features, action) pairs."""
-    return with_(c5_mpc(seed), n_patients=5_000, n_days=7)
+    17,500 patients x 2 days = 10.08 M (inputs, action) pairs -- as many pairs as 5,000 x 7 days
+    but a wider sample of patients, which the network's patient inputs need."""
+    return with_(c5_mpc(seed), n_patients=17_500, n_days=2)
 
 
 GAIN_MULTIPLIERS = (0.5, 0.75, 1.0, 1.5)
@@ -157,9 +162,11 @@ def c5_mlp(seed: int = 5) -> dict:
 
 
 # --------------------------------------------------------- learned-controller inputs
-# Order of the 12 inputs: y_k .. y_k-5 (mmol/L), insulin on board relative to basal,
-# glucose on board from announced meals (mmol), BW (kg), u_b (mU/min), SIT, SID.
-POLICY_INPUTS = ("y0", "y1", "y2", "y3", "y4", "y5", "iob", "gob", "BW", "ub", "SIT", "SID")
+# Order of the 12 inputs: y_k .. y_k-5 (mmol/L), insulin on board and announced meals as the
+# mean glucose change they still cause over the MPC's horizon (mmol/L), u_b (mU/min), the
+# insulin response over the horizon (sum of the MPC's Markov parameters) and its mean delay
+# (samples), BW (kg).
+POLICY_INPUTS = ("y0", "y1", "y2", "y3", "y4", "y5", "iob", "meal", "ub", "hsum", "hdelay", "BW")
 
 
 def synthetic_policy_rows(seed: int, n: int):
@@ -171,14 +178,14 @@ def synthetic_policy_rows(seed: int, n: int):
     y0 = np.clip(7.0 + 2.0 * rng.standard_normal(n), 2.0, 25.0)
     slope = 0.15 * rng.standard_normal(n)
     ys = [np.clip(y0 - slope * i, 2.0, 25.0) for i in range(6)]
-    iob = np.exp(0.3 * rng.standard_normal(n))
-    gob = np.where(rng.random(n) < 0.2, rng.uniform(0.0, 300.0, n), 0.0)
+    iob = 0.8 * rng.standard_normal(n)
+    gob = np.where(rng.random(n) < 0.2, rng.uniform(0.0, 6.0, n), 0.0)
+    ub = 10.0 * np.exp(0.3 * rng.standard_normal(n))
+    hsum = -0.1 * np.exp(0.4 * rng.standard_normal(n))
+    hdelay = 18.5 + 0.2 * rng.standard_normal(n)
     bw = 70.0 * np.exp(0.2 * rng.standard_normal(n))
-    ub = 15.0 * np.exp(0.2 * rng.standard_normal(n))
-    sit = 51.2e-4 * np.exp(0.2 * rng.standard_normal(n))
-    sid = 8.2e-4 * np.exp(0.2 * rng.standard_normal(n))
-    target = np.clip(1.0 + 0.5 * (y0 - 6.0) + 2.0 * slope - 0.5 * (iob - 1.0) + gob / 200.0, 0.0, 3.0)
-    return np.stack(ys + [iob, gob, bw, ub, sit, sid, target], axis=1)
+    target = np.clip(1.0 + 0.5 * (y0 - 6.0) + 2.0 * slope + 0.5 * iob + 0.3 * gob, 0.0, 3.0)
+    return np.stack(ys + [iob, gob, ub, hsum, hdelay, bw, target], axis=1)
 
 
 def synthetic_policy_net(seed: int, gain: float = 1.0, spread: float = 0.05) -> dict:
@@ -187,7 +194,8 @@ def synthetic_policy_net(seed: int, gain: float = 1.0, spread: float = 0.05) -> 
     1 + gain (z0 - a) (a proportional law around 6 mmol/L) plus a small random network on the
     other 62 units (weights from numpy's seeded generator, output weights ~ spread). The
     normalisation is fixed (sensor values around 7 +- 2 mmol/L) and the box covers glucose
-    2.5-16 mmol/L and patients within a factor 1.8 of nominal."""
+    2.5-16 mmol/L, an insulin response down to -0.25 and body weights within a factor 1.5 of
+    nominal."""
     import numpy as np
     rng = np.random.default_rng(seed)
     H = 64
@@ -198,8 +206,8 @@ def synthetic_policy_net(seed: int, gain: float = 1.0, spread: float = 0.05) -> 
     b2 = 0.1 * rng.standard_normal(H)
     b3 = 0.1 * rng.standard_normal(H)
     w4 = spread * rng.standard_normal(H)
-    mean = np.array([7.0] * 6 + [1.0, 30.0, 70.0, 15.0, 51.2e-4, 8.2e-4])
-    istd = 1.0 / np.array([2.0] * 6 + [0.5, 60.0, 14.0, 4.0, 1.0e-3, 1.6e-4])
+    mean = np.array([7.0] * 6 + [0.0, 0.5, 10.0, -0.1, 18.5, 70.0])
+    istd = 1.0 / np.array([2.0] * 6 + [1.0, 1.5, 3.0, 0.05, 0.2, 14.0])
     a = (6.0 - 7.0) / 2.0
     for W, b in ((W2, b2), (W3, b3)):
         W[0:2, :] = 0.0
@@ -210,8 +218,8 @@ def synthetic_policy_net(seed: int, gain: float = 1.0, spread: float = 0.05) -> 
     W1[0, 0], b1[0] = 1.0, -a
     W1[1, 0], b1[1] = -1.0, a
     w4[0], w4[1] = gain, -gain
-    lo = np.array([2.5] * 6 + [0.0, 0.0, 70.0 / 1.8, 0.0, 51.2e-4 / 1.8, 8.2e-4 / 1.8])
-    hi = np.array([16.0] * 6 + [20.0, 1e4, 70.0 * 1.8, 1e3, 51.2e-4 * 1.8, 8.2e-4 * 1.8])
+    lo = np.array([2.5] * 6 + [-50.0, -1.0, 0.0, -0.25, 10.0, 70.0 / 1.5])
+    hi = np.array([16.0] * 6 + [50.0, 1e3, 1e3, 0.0, 30.0, 70.0 * 1.5])
     # stored precision: FP32 normalisation and biases
     f32 = lambda v: np.asarray(v, np.float32).astype(np.float64)
     return {"W1": W1, "b1": f32(b1), "W2": W2, "b2": f32(b2), "W3": W3, "b3": f32(b3), "w4": w4, "b4": 1.0,

@@ -52,6 +52,8 @@ def test_mpc_setup_matches_oracle(T, orc):
         assert g["step"][j, 0] == pytest.approx(o["step"], rel=1e-9)
         assert g["rho_p"][j, 0] == pytest.approx(o["rho_p"], rel=1e-12)
         assert g["umax"][j, 0] == pytest.approx(o["umax"], rel=1e-12)
+        assert np.allclose(g["Fbar"][j], o["F"].mean(0), rtol=1e-9, atol=1e-15)
+        assert g["wbar"][j, 0] == pytest.approx(o["w"].mean(), rel=1e-9)
 
 
 def test_mpc_fp64_closed_loop(T, orc):

@@ -210,19 +210,24 @@ def test_recorded_rows(orc):
     for i in range(1, 6):
         assert np.array_equal(rec[i:, :, i], y[:-i])
         assert np.array_equal(rec[:i, :, i], np.broadcast_to(y[0], (i, y.shape[1])))
-    assert np.allclose(rec[0, :, 6], 1.0, rtol=1e-12)                    # basal insulin on board
-    assert np.array_equal(rec[:, :, 8], np.broadcast_to(prm[:, 14], rec.shape[:2]))
-    assert np.array_equal(rec[:, :, 9], np.broadcast_to(prm[:, 15], rec.shape[:2]))
-    assert np.array_equal(rec[:, :, 10], np.broadcast_to(prm[:, 6], rec.shape[:2]))
-    assert np.array_equal(rec[:, :, 11], np.broadcast_to(prm[:, 7], rec.shape[:2]))
+    assert np.allclose(rec[0, :, 6], 0.0, rtol=0, atol=1e-12)           # basal: no pending insulin effect
+    assert np.array_equal(rec[:, :, 8], np.broadcast_to(prm[:, 15], rec.shape[:2]))
+    assert np.array_equal(rec[:, :, 11], np.broadcast_to(prm[:, 14], rec.shape[:2]))
+    for j in range(12):   # insulin response over the horizon and its mean delay
+        h = orc.mpc_setup(t, prm[j])["h"]
+        assert np.allclose(rec[:, j, 9], h.sum(), rtol=1e-12)
+        assert np.allclose(rec[:, j, 10], (np.arange(1, 25) * h).sum() / h.sum(), rtol=1e-12)
     assert np.allclose(rec[:, :, 12], u / prm[:, 15], rtol=1e-15)
-    # glucose on board: zero before the day's first meal, then jumps by A_G d Ts at the meal
+    # meal input: zero before the day's first meal; at the meal sample the announced intake
+    # rate times the horizon mean of the intake response (the meal states are still empty)
     first = [orc.meals(t, j, 0) for j in range(12)]
     for j in range(12):
         k0 = int(first[j][0][1])
         assert np.all(rec[:k0, j, 7] == 0.0)
-        grams = first[j][0][2]
-        assert rec[k0, j, 7] == pytest.approx(0.8 * grams * 1000.0 / 180.16, rel=1e-12)
+        rate = first[j][0][2] * (1000.0 / 180.16) / t["ts_min"]
+        wbar = orc.mpc_setup(t, prm[j])["w"].mean()
+        assert rec[k0, j, 7] == pytest.approx(wbar * rate, rel=1e-12)
+        assert rec[k0 + 1, j, 7] > 0.0
 
 
 def test_labels_along_own_loop(orc):
