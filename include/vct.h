@@ -66,6 +66,9 @@ enum { VCT_POP_MIN_BASAL = 1 };   /* also require u_b >= 0.4 U/h (Sec. IV-B) */
  * exists (and, with VCT_POP_MIN_BASAL, its rate is >= 0.4 U/h); up to 32 draws,
  * then the nominal vector with a status bit. Random numbers: Philox4x32-10 with
  * key (seed low word, seed high word ^ arm_id), counter (j/4, patient, 0, attempt).
+ * The handle holds patients [first_patient, first_patient + n_patients) of the population:
+ * every draw of a patient (parameters, meals, noise) is keyed by its global index, so a
+ * population split into slices -- over launches or GPUs -- gives the same per-patient results.
  */
 typedef struct {
     int64_t  n_patients;       /* >= 1, < 2^31                                       */
@@ -77,6 +80,7 @@ typedef struct {
     double   ag;               /* carbohydrate bioavailability, shared, in (0, 1]      */
     double   tau_cgm;          /* sensor time constant, min, shared, > 0               */
     double   g_target;         /* basal steady-state glucose, mmol/L, > 0              */
+    int64_t  first_patient;    /* global index of the first patient, >= 0, first + n <= 2^32 */
 } vct_population_desc;
 
 /* (2) protocol -- Sec. II-B: disturbances with type, size and time. Each day and slot

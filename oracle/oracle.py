@@ -193,8 +193,12 @@ def normals4(ctr, key) -> np.ndarray:
     return np.array(list(o))
 
 
-def sample_population(trial: dict, first: int = 0, count: int | None = None) -> np.ndarray:
-    n = int(trial["n_patients"]) - first if count is None else int(count)
+def sample_population(trial: dict, first: int | None = None, count: int | None = None) -> np.ndarray:
+    if first is None:
+        first = int(trial.get("first_patient", 0))
+        n = int(trial["n_patients"]) if count is None else int(count)
+    else:
+        n = int(trial["n_patients"]) - first if count is None else int(count)
     out = np.zeros((n, NPOUT))
     cfg = config(trial)
     lib().orc_sample_population(C.byref(cfg), first, n, _ptr(out, C.c_double))
@@ -350,11 +354,16 @@ def adam(w, m, v, g, lr: float, t: int):
 
 
 # ------------------------------------------------------------------ simulate
-def simulate(trial: dict, first: int = 0, count: int | None = None, threads: int | None = None,
+def simulate(trial: dict, first: int | None = None, count: int | None = None, threads: int | None = None,
              n_traj: int = 0, record_x: bool = False, integrator: int = INT_EM, rk4_sub: int = 64,
              x0_offset=None, guard_rel: float = 1e-4, mlp: dict | None = None, record: bool = False) -> dict:
-    """Run patients [first, first+count) of the trial; returns per-patient arrays."""
-    n = int(trial["n_patients"]) - first if count is None else int(count)
+    """Run patients [first, first+count) of the trial (default: the trial's own slice);
+    returns per-patient arrays."""
+    if first is None:
+        first = int(trial.get("first_patient", 0))
+        n = int(trial["n_patients"]) if count is None else int(count)
+    else:
+        n = int(trial["n_patients"]) - first if count is None else int(count)
     K = int(trial["n_days"]) * (1440 // int(trial["ts_min"]))
     nt = min(int(n_traj), n)
     r = {

@@ -16,6 +16,7 @@
 
 struct vct_population {
     int64_t n;
+    int64_t first;
     double *params;
     uint32_t arm_id;
     uint32_t flags;
@@ -89,11 +90,14 @@ vct_status vct_create_population(const vct_population_desc *d, void *params_dev,
         return fail(VCT_EINVAL, "vct_create_population: ag in (0,1], tau_cgm > 0, g_target > 0 required");
     if (d->flags & ~(uint32_t)VCT_POP_MIN_BASAL)
         return fail(VCT_EINVAL, "vct_create_population: unknown flags 0x%x", d->flags);
+    if (d->first_patient < 0 || d->first_patient + d->n_patients > ((int64_t)1 << 32))
+        return fail(VCT_EINVAL, "vct_create_population: patients [%lld, %lld) outside [0, 2^32)",
+                    (long long)d->first_patient, (long long)(d->first_patient + d->n_patients));
 
     vct::PopArgs a{};
     a.params = (double *)params_dev;
     a.n = d->n_patients;
-    a.patient_base = 0;
+    a.patient_base = d->first_patient;
     split_key(d->seed, d->arm_id, a.key0, a.key1);
     a.flags = d->flags;
     for (int q = 0; q < VCT_NP; ++q)
@@ -108,6 +112,7 @@ vct_status vct_create_population(const vct_population_desc *d, void *params_dev,
     if (!p)
         return fail(VCT_ENOMEM, "vct_create_population: out of host memory");
     p->n = d->n_patients;
+    p->first = d->first_patient;
     p->params = (double *)params_dev;
     p->arm_id = d->arm_id;
     p->flags = d->flags;
@@ -197,7 +202,7 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a = vct::SimArgs{};
     a.params = pop->params;
     a.n = pop->n;
-    a.patient_base = 0;
+    a.patient_base = pop->first;
     a.n_days = sim->n_days;
     a.kday = 1440 / sim->ts_min;
     split_key(sim->noise_seed, pop->arm_id, a.key0, a.key1);

@@ -36,7 +36,7 @@ METRIC_LAYOUT = (("sum_g", "f8", 0, 1), ("min_g", "f8", 8, 1), ("sum_u", "f8", 1
 class vct_population_desc(C.Structure):
     _fields_ = [("n_patients", C.c_int64), ("seed", C.c_uint64), ("arm_id", C.c_uint32), ("flags", C.c_uint32),
                 ("nominal", C.c_double * VCT_NP), ("cv", C.c_double), ("ag", C.c_double),
-                ("tau_cgm", C.c_double), ("g_target", C.c_double)]
+                ("tau_cgm", C.c_double), ("g_target", C.c_double), ("first_patient", C.c_int64)]
 
 
 class vct_protocol(C.Structure):
@@ -298,6 +298,7 @@ def population_desc(trial: dict) -> vct_population_desc:
     for i, v in enumerate(trial["nominal"]):
         d.nominal[i] = float(v)
     d.cv, d.ag, d.tau_cgm, d.g_target = (float(trial[k]) for k in ("cv", "ag", "tau_cgm", "g_target"))
+    d.first_patient = int(trial.get("first_patient", 0))
     return d
 
 

@@ -36,6 +36,7 @@ def base_trial() -> dict:
     return {
         # (1) population + (4) parameter values
         "n_patients": 1000,
+        "first_patient": 0,    # global index of patient 0 (slices of a larger population)
         "pop_seed": 0,
         "arm_id": 0,
         "pop_flags": 0,

@@ -93,3 +93,11 @@ def test_mlp_sizes_and_rejects():
             f()
         assert e.value.code == vct.VCT_EINVAL
 
+
+
+def test_create_population_rejects_bad_slice():
+    for first, n in ((-1, 10), ((1 << 32) - 5, 10)):
+        d = vct.population_desc(W.with_(W.base_trial(), first_patient=first, n_patients=n))
+        with pytest.raises(vct.VctError) as e:
+            vct.vct_create_population(d, 1 << 20)
+        assert e.value.code == vct.VCT_EINVAL

@@ -404,3 +404,32 @@ def test_labels_with_empty_box_equal_mpc_rows(G):
     trial.run(t, bufs=bufs, mlp_blob=pol.blob)
     rows_mpc, _ = policy.record_dataset(W.with_(t, ctrl_kind=W.CTRL_MPC))
     assert torch.equal(bufs.record.view(-1, 13), rows_mpc)
+
+
+def test_trained_network_gain(G):
+    """End to end, on the GPU only: record the MPC's closed loop on a training population,
+    fit the network, then run a separate population three ways on common random numbers.
+    The trained network keeps the population TIR within 0.5 pp of the exact MPC while its
+    simulation is faster; the same network untrained (the method without learning) is far
+    from the MPC."""
+    torch, policy, trial = G
+    from paper_2202_13927_amd import learned
+    train = W.with_(W.mlp_training_population(), n_patients=4000, n_days=2)
+    _say("[gpu] learned controller end to end: train on 4000 x 2 d")
+    pol, rep = learned.train_policy(train, epochs=8.0, log=_say)
+    ev = W.with_(W.c5_mpc(), n_patients=20000, n_days=7, pop_seed=41, noise_seed=41)
+    res = learned.evaluate(pol, ev, log=_say)
+    untrained = policy.Policy(batch=64)
+    untrained.init(seed=100)
+    untrained.blob[vct_norm_slice()] = pol.blob[vct_norm_slice()]   # same normalisation and box
+    res0 = learned.evaluate(untrained, ev, log=_say)
+    _say("   trained dTIR %.3f pp (speedup %.2f), untrained dTIR %.3f pp" %
+         (res["delta_tir_pp"], res["speedup"], res0["delta_tir_pp"]))
+    assert abs(res["delta_tir_pp"]) <= 0.5
+    assert res["mlp"]["sim_s"] < res["mpc"]["sim_s"]
+    assert abs(res0["delta_tir_pp"]) > 5 * max(abs(res["delta_tir_pp"]), 0.1)
+
+
+def vct_norm_slice():
+    from paper_2202_13927_amd import vct
+    return slice(vct.MLP_BLOB["mean"], vct.VCT_MLP_BLOB_BYTES)

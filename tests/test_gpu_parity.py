@@ -198,3 +198,18 @@ def test_full_size_c3_sampled(gpu, orc):
     assert np.abs(dt).max() < 5e-3
     assert abs(dt.mean()) < 2e-3
     assert 0.3 < s["mean_tir"] < 0.95 and math.isfinite(s["mean_bg"])
+
+
+def test_population_slices_equal_whole(gpu):
+    """A population run as two slices (first_patient 0 and 600) gives, patient by patient,
+    exactly the results of the whole run: every draw is keyed by the global patient index."""
+    t = W.with_(W.base_trial(), n_patients=1000, n_days=2, precision=W.FP32, pop_seed=3, noise_seed=4)
+    _say("[gpu] population slices vs whole, 1000 x 2 d FP32")
+    _, b = gpu.run(t)
+    whole = gpu.to_host(b)
+    parts = []
+    for first, n in ((0, 600), (600, 400)):
+        _, b = gpu.run(W.with_(t, first_patient=first, n_patients=n))
+        parts.append(gpu.to_host(b))
+    for k in ("bins", "events", "sum_g", "min_g", "argmin_k", "sum_u", "status", "params"):
+        assert np.array_equal(whole[k], np.concatenate([p[k] for p in parts])), k
