@@ -11,7 +11,10 @@ The JSON line also carries
   over its own average launch time (HIP events on its stream) against the 157.3
   TFLOP/s FP32 vector peak;
 * cpu_baseline -- the FP64 oracle on a bounded sample of the same trial, timed on
-  this host's cores.
+  this host's cores;
+* batched -- the 64-arm heterogeneous PID trial in one persistent graph-captured launch;
+* learned -- the learned controller against exact linear MPC on common random numbers
+  (100,000 x 28 days by default, 1,000,000 x 364 days with --learned-full).
 """
 from __future__ import annotations
 
@@ -98,6 +101,46 @@ def batched(stream) -> dict:
         bt.close()
 
 
+def learned_leg(full: bool) -> dict:
+    """The learned controller against exact MPC on common random numbers: train on the MPC's
+    recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
+    evaluation population with both controllers. full: 1,000,000 patients x 364 days as four
+    slices of 250,000 (each slice keeps the patients' global indices); otherwise 100,000 x 28
+    days. Times are the simulation launches only (HIP events); MPC setup and training are
+    reported separately."""
+    from paper_2202_13927_amd import learned as L, workloads as W
+    t0 = time.perf_counter()
+    pol, rep = L.train_policy(W.mlp_training_population(), epochs=10.0, log=log)
+    train_s = time.perf_counter() - t0
+    n, days, slices = (1_000_000, 364, 4) if full else (100_000, 28, 1)
+    tot = {"mpc": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}, "mlp": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}}
+    fb = 0.0
+    always = 0
+    for i in range(slices):
+        ev = W.with_(W.c5_mpc(), n_patients=n // slices, first_patient=i * (n // slices), n_days=days)
+        r = L.evaluate(pol, ev, log=log)
+        for arm in ("mpc", "mlp"):
+            tot[arm]["s"] += r[arm]["sim_s"]
+            tot[arm]["bins"] = [a + b for a, b in zip(tot[arm]["bins"], r[arm]["bins"])]
+            tot[arm]["events"] = [a + b for a, b in zip(tot[arm]["events"], r[arm]["events"])]
+        fb += r["mlp"]["fallback_rate"] / slices
+        always += r["mlp"]["patients_always_fallback"]
+        log(f"[bench] learned: slice {i + 1}/{slices} done (MPC {r['mpc']['sim_s']:.1f} s, "
+            f"network {r['mlp']['sim_s']:.1f} s)")
+    tir = {a: tot[a]["bins"][2] / sum(tot[a]["bins"]) for a in tot}
+    pd = n * days
+    return {"workload": f"{n} patients x {days} days, FP32, exact linear MPC (24 samples, 50 projected-gradient "
+                        "steps) vs 12-64-64-64-1 BF16 network with MPC fallback, common random numbers",
+            "patients": n, "days": days, "tir_mpc": tir["mpc"], "tir_mlp": tir["mlp"],
+            "delta_tir_pp": 100.0 * (tir["mlp"] - tir["mpc"]),
+            "speedup": tot["mpc"]["s"] / tot["mlp"]["s"],
+            "mpc_patient_days_per_s": pd / tot["mpc"]["s"], "mlp_patient_days_per_s": pd / tot["mlp"]["s"],
+            "mpc_sim_s": tot["mpc"]["s"], "mlp_sim_s": tot["mlp"]["s"], "fallback_rate": fb,
+            "patients_always_fallback": always, "bins_mpc": tot["mpc"]["bins"], "bins_mlp": tot["mlp"]["bins"],
+            "train_rows": rep["rounds"][-1]["rows"], "train_s": train_s,
+            "train_mse": rep["rounds"][-1]["mse_full"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +152,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-arm batched trial")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scales HBM byte counters)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-controller comparison")
+    ap.add_argument("--learned-full", action="store_true",
+                    help="run the learned-controller comparison at 1,000,000 x 364 days (minutes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -169,7 +215,7 @@ def main() -> int:
     achieved = FLOP_PER_PATIENT_DAY * pdays / kern_s
     traffic = measured_traffic() if (n, days) == (1_000_000, 364) else None
     out = {
-        "metric": "patient-days simulated/s (1 GPU)",
+        "metric": "patient-days simulated/s (1 GPU) + %FP32 roofline; MLP vs exact MPC at TIR \u0394\u22640.5pp",
         "value": value,
         "unit": "patient-days/s",
         "n_gpus": 1,
@@ -199,6 +245,8 @@ def main() -> int:
     del bufs
     if not args.no_batched:
         out["batched"] = batched(stream)
+    if not args.no_learned:
+        out["learned"] = learned_leg(args.learned_full)
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(trial)
