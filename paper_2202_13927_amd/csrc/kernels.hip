@@ -198,14 +198,15 @@ __device__ __forceinline__ void patient_inputs(const SimArgs &a, int64_t j, R ou
     out[3] = R(a.params[(int64_t)kBW * a.n + j]);
 }
 
-// LDS views of the learned controller (simulate_policy_kernel only): the staged blob and the
-// wave's activation tile.
+// LDS views of the learned controller (simulate_policy_kernel only): the staged network and
+// the wave's input tile.
 struct PolicyShared {
-    MlpNet net;          // BF16 weights + FP32 biases, staged once per workgroup
-    uint16_t *hs;        // [64][64] BF16 activations; the inputs use the first [64][16]
-    float *o;            // [64] network outputs
+    const unsigned char *img;   // LDS image of the blob (NetImage<PaddedLayout>), staged once per workgroup
+    uint16_t *xs;               // [64][PaddedLayout::ldi] BF16 normalised inputs, row = lane
+    float *o;                   // [64] network outputs
     const float *mean, *istd, *lo, *hi;
     int lane;
+    bool rest;                  // this wave's patient is outside the box: the MPC acts on every sample
 };
 
 // Orders this wave's LDS writes before its later LDS reads (LDS operations of one wave
@@ -248,12 +249,11 @@ __device__ __forceinline__ float policy_forward(const PolicyShared &ps, const R 
         w[q] = 2 * q < kMlpIn ? pack_bf16(((float)f[2 * q] - ps.mean[2 * q]) * ps.istd[2 * q],
                                           ((float)f[2 * q + 1] - ps.mean[2 * q + 1]) * ps.istd[2 * q + 1])
                               : 0u;
-    uint4 *dst = (uint4 *)(ps.hs + ps.lane * PaddedLayout::ldi);
+    uint4 *dst = (uint4 *)(ps.xs + ps.lane * PaddedLayout::ldi);
     dst[0] = uint4{w[0], w[1], w[2], w[3]};
     dst[1] = uint4{w[4], w[5], w[6], w[7]};
     wave_lds_sync();
-    mlp_forward<PaddedLayout>(ps.net, ps.hs, ps.hs, ps.hs, ps.hs, ps.o, ps.lane, wave_lds_sync);
-    return ps.o[ps.lane];
+    return mlp_forward_rf<PaddedLayout>(ps.img, ps.xs, ps.o, ps.lane, wave_lds_sync);
 }
 
 // ------------------------------------------------------ wave-cooperative QP ----
@@ -430,7 +430,8 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
 #pragma unroll
         for (int q = 0; q < kMlpIn; ++q)
             ood |= !(f[q] >= R(ps.lo[q]) && f[q] <= R(ps.hi[q]));
-        const float o = policy_forward<R>(ps, f);
+        // (a wave whose patient is outside the box needs no network: its fallback is certain)
+        const float o = ps.rest ? 0.0f : policy_forward<R>(ps, f);
         const bool fb = ood || (y < R(a.mlp_safe_g) && o > (float)a.mlp_safe_out);
         // every live lane that needs the MPC's action gets it from a wave-cooperative solve
         R du_mpc = R(0);
@@ -636,77 +637,37 @@ __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
 
 // The learned controller: the same per-patient loop, with the network evaluated by each
 // wave for its 64 patients on every sample. The weights and biases are staged into LDS
-// once per workgroup; each wave owns an activation tile. Lanes take patients in the order
-// a.order (patients whose fixed inputs lie outside the box, and so hand every sample to
-// the MPC, gathered in the last waves instead of stalling 64-lane waves of network
-// patients). Every lane of a wave takes part in the MFMA chain, so the padding lanes of
-// the last wave replay a patient and write nothing.
+// once per workgroup; each wave owns an input tile, and the hidden activations stay in
+// registers. Lanes take patients in the order a.order: each patient whose fixed inputs lie
+// outside the box (the MPC acts on every sample, so the network is skipped) alone on a
+// wave, then tiles of 64 patients. Every lane of a tile wave takes part in the MFMA chain,
+// so the padding lanes of the last tile replay a patient and write nothing.
 constexpr int kPolicyBlock = 256;
-// LDS image of the blob with padded row strides (PaddedLayout): W1 [64][24], W2 and W3
-// [64][72], W4 [16][72], then the biases, normalisation and box as in the blob.
-constexpr int kLdsW1 = 0;
-constexpr int kLdsW2 = kLdsW1 + kMlpH * PaddedLayout::ldw1 * 2;
-constexpr int kLdsW3 = kLdsW2 + kMlpH * PaddedLayout::ldw * 2;
-constexpr int kLdsW4 = kLdsW3 + kMlpH * PaddedLayout::ldw * 2;
-constexpr int kLdsTail = kLdsW4 + kMlpOutP * PaddedLayout::ldw * 2;
-constexpr int kLdsNet = kLdsTail + (kMlpBlobBytes - kOffB1);
-constexpr int kPolicyWaveBytes = kMlpH * PaddedLayout::ldh * 2 + 64 * 4;
-
-__device__ __forceinline__ void stage_padded(const unsigned char *blob, unsigned char *lds, int tid, int nthreads)
-{
-    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-    const auto src = as_global((const u32x4 *)blob);
-    // 16-byte chunks: W1 128, W2 512, W3 512, W4 128, tail 68
-    for (int c = tid; c < 128 + 512 + 512 + 128 + 68; c += nthreads) {
-        int soff, doff;
-        if (c < 128) {                 // W1: 2 chunks per row
-            soff = kOffW1 + c * 16;
-            doff = kLdsW1 + (c >> 1) * PaddedLayout::ldw1 * 2 + (c & 1) * 16;
-        } else if (c < 640) {          // W2: 8 chunks per row
-            const int q = c - 128;
-            soff = kOffW2 + q * 16;
-            doff = kLdsW2 + (q >> 3) * PaddedLayout::ldw * 2 + (q & 7) * 16;
-        } else if (c < 1152) {         // W3
-            const int q = c - 640;
-            soff = kOffW3 + q * 16;
-            doff = kLdsW3 + (q >> 3) * PaddedLayout::ldw * 2 + (q & 7) * 16;
-        } else if (c < 1280) {         // W4
-            const int q = c - 1152;
-            soff = kOffW4 + q * 16;
-            doff = kLdsW4 + (q >> 3) * PaddedLayout::ldw * 2 + (q & 7) * 16;
-        } else {                       // biases, normalisation, box
-            const int q = c - 1280;
-            soff = kOffB1 + q * 16;
-            doff = kLdsTail + q * 16;
-        }
-        *(u32x4 *)(lds + doff) = src[soff / 16];
-    }
-}
+using PolicyNet = NetImage<PaddedLayout>;
+// per wave: the input tile [64][24] BF16 and the 64 outputs
+constexpr int kPolicyWaveBytes = 64 * PaddedLayout::ldi * 2 + 64 * 4;
+// Waves per SIMD the kernel is compiled for (the register budget): one wave holds ~370
+// registers without spilling, so two would spill to scratch memory.
+constexpr int kPolicyBlocksPerCu = 1;
 
 template <typename R, bool NOISY, int OUT>
-__global__ __launch_bounds__(kPolicyBlock, 2) void simulate_policy_kernel(const SimArgs a, const int32_t *counts,
-                                                                          int32_t nb, uint32_t *queue)
+__global__ __launch_bounds__(kPolicyBlock, kPolicyBlocksPerCu) void simulate_policy_kernel(const SimArgs a,
+                                                                                           const int32_t *counts,
+                                                                                           int32_t nb, uint32_t *queue)
 {
-    __shared__ __align__(16) unsigned char lds[kLdsNet + (kPolicyBlock / 64) * kPolicyWaveBytes];
-    stage_padded(a.mlp, lds, threadIdx.x, kPolicyBlock);
+    __shared__ __align__(16) unsigned char lds[PolicyNet::bytes + (kPolicyBlock / 64) * kPolicyWaveBytes];
+    stage_net<PaddedLayout>(a.mlp, lds, threadIdx.x, kPolicyBlock);
     __syncthreads();
     const int wave = threadIdx.x >> 6;
-    unsigned char *wl = lds + kLdsNet + wave * kPolicyWaveBytes;
+    unsigned char *wl = lds + PolicyNet::bytes + wave * kPolicyWaveBytes;
     PolicyShared ps;
-    ps.net.W1 = (const uint16_t *)(lds + kLdsW1);
-    ps.net.W2 = (const uint16_t *)(lds + kLdsW2);
-    ps.net.W3 = (const uint16_t *)(lds + kLdsW3);
-    ps.net.W4 = (const uint16_t *)(lds + kLdsW4);
-    ps.net.b1 = (const float *)(lds + kLdsTail + (kOffB1 - kOffB1));
-    ps.net.b2 = (const float *)(lds + kLdsTail + (kOffB2 - kOffB1));
-    ps.net.b3 = (const float *)(lds + kLdsTail + (kOffB3 - kOffB1));
-    ps.net.b4 = (const float *)(lds + kLdsTail + (kOffB4 - kOffB1));
-    ps.hs = (uint16_t *)wl;
-    ps.o = (float *)(wl + kMlpH * PaddedLayout::ldh * 2);
-    ps.mean = (const float *)(lds + kLdsTail + (kOffMean - kOffB1));
-    ps.istd = (const float *)(lds + kLdsTail + (kOffIstd - kOffB1));
-    ps.lo = (const float *)(lds + kLdsTail + (kOffLo - kOffB1));
-    ps.hi = (const float *)(lds + kLdsTail + (kOffHi - kOffB1));
+    ps.img = lds;
+    ps.xs = (uint16_t *)wl;
+    ps.o = (float *)(wl + 64 * PaddedLayout::ldi * 2);
+    ps.mean = (const float *)(lds + PolicyNet::tail + (kOffMean - kOffB1));
+    ps.istd = (const float *)(lds + PolicyNet::tail + (kOffIstd - kOffB1));
+    ps.lo = (const float *)(lds + PolicyNet::tail + (kOffLo - kOffB1));
+    ps.hi = (const float *)(lds + PolicyNet::tail + (kOffHi - kOffB1));
     ps.lane = threadIdx.x & 63;
     // Work items, longest first: each patient outside the box alone on a wave (the MPC acts
     // on every sample, solved cooperatively), then tiles of 64 patients inside the box.
@@ -730,6 +691,7 @@ __global__ __launch_bounds__(kPolicyBlock, 2) void simulate_policy_kernel(const 
             live = s0 < n_in;
             slot = live ? s0 : (int64_t)n_in - 1;
         }
+        ps.rest = item < n_rest;
         run_patient<R, kCtrlMlp, NOISY, OUT>(a, (int64_t)a.order[slot], live, ps);
     }
 }

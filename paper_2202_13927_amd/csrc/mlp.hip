@@ -355,25 +355,31 @@ __global__ void mlp_update_kernel(const float *__restrict__ partial, int n_parts
 }
 
 // -------------------------------------------------------------- batched forward ----
-__global__ __launch_bounds__(64) void mlp_forward_kernel(const float *__restrict__ x, int64_t n,
-                                                         const unsigned char *__restrict__ blob, float *__restrict__ out)
+// The learned controller's own evaluation (mlp_forward_rf on the padded LDS image), four
+// waves per block sharing one staged copy of the network, 64 rows per wave.
+constexpr int kFwdBlock = 256;
+using FwdNet = NetImage<PaddedLayout>;
+constexpr int kFwdWaveBytes = 64 * PaddedLayout::ldi * 2 + 64 * 4;
+
+__global__ __launch_bounds__(kFwdBlock) void mlp_forward_kernel(const float *__restrict__ x, int64_t n,
+                                                                const unsigned char *__restrict__ blob,
+                                                                float *__restrict__ out)
 {
-    __shared__ __align__(16) unsigned char net[kMlpNetBytes];
-    __shared__ __align__(16) uint16_t xs[64 * kMlpInP];
-    __shared__ __align__(16) uint16_t hs[64 * kMlpH];
-    __shared__ float o[64];
-    const int lane = threadIdx.x;
-    for (int i = lane; i < kMlpNetBytes / 16; i += 64)
-        ((uint4 *)net)[i] = ((const uint4 *)blob)[i];
-    const int64_t gi = (int64_t)blockIdx.x * 64 + lane;
+    __shared__ __align__(16) unsigned char lds[FwdNet::bytes + (kFwdBlock / 64) * kFwdWaveBytes];
+    stage_net<PaddedLayout>(blob, lds, threadIdx.x, kFwdBlock);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    uint16_t *xs = (uint16_t *)(lds + FwdNet::bytes + wave * kFwdWaveBytes);
+    float *o = (float *)((unsigned char *)xs + 64 * PaddedLayout::ldi * 2);
+    const int64_t gi = (int64_t)blockIdx.x * kFwdBlock + threadIdx.x;
     const int64_t row = gi < n ? gi : n - 1;
     const float *mean = (const float *)(blob + kOffMean), *istd = (const float *)(blob + kOffIstd);
-    for (int f = 0; f < kMlpInP; ++f)
-        xs[lane * kMlpInP + f] = f < kMlpIn ? f2bf((x[row * kMlpIn + f] - mean[f]) * istd[f]) : (uint16_t)0;
+    for (int f = 0; f < PaddedLayout::ldi; ++f)
+        xs[lane * PaddedLayout::ldi + f] =
+            f < kMlpIn ? f2bf((x[row * kMlpIn + f] - mean[f]) * istd[f]) : (uint16_t)0;
     __syncthreads();
-    mlp_forward<DenseLayout>(mlp_net(net), xs, hs, hs, hs, o, lane, wave_sync);
+    const float r = mlp_forward_rf<PaddedLayout>(lds, xs, o, lane, wave_sync);
     if (gi < n)
-        out[gi] = o[lane];
+        out[gi] = r;
 }
 
 // ---------------------------------------------------------------- launchers ----
@@ -414,7 +420,8 @@ hipError_t launch_mlp_step(const MlpTrain &t, const float *data, int64_t n_rows,
 
 hipError_t launch_mlp_forward(const float *x, int64_t n, const unsigned char *blob, float *out, hipStream_t s)
 {
-    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, x, n, blob, out);
+    hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)((n + kFwdBlock - 1) / kFwdBlock)), dim3(kFwdBlock), 0, s, x,
+                       n, blob, out);
     return hipGetLastError();
 }
 

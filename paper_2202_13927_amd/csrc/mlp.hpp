@@ -1,11 +1,13 @@
 // mlp.hpp -- the learned controller: a 12 -> 64 -> 64 -> 64 -> 1 ReLU network evaluated by one
-// wave for 64 samples at a time on BF16 MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulation).
+// wave for 64 samples at a time on BF16 MFMA (v_mfma_f32_16x16x16_bf16 for the 16-wide input
+// layer, v_mfma_f32_16x16x32_bf16 for the 64-wide layers; FP32 accumulation).
 //
-// Operand layouts of v_mfma_f32_16x16x16_bf16 (checked on the device against a CPU matmul):
+// Operand layouts (checked on the device against a CPU matmul), with K = 16 (x32: 8 and k/8):
 //   A[i][k] -> lane i + 16 (k/4), element k % 4;  B[k][j] -> lane j + 16 (k/4), element k % 4;
 //   C[i][j] -> lane j + 16 (i/4), element i % 4.
-// Activations are staged through LDS as BF16 row-major [sample][unit] tiles; weights are
-// BF16 [out][in] (so a B fragment is 4 consecutive BF16 of one weight row).
+// Weights are BF16 [out][in]. Training stages activations through LDS as BF16 row-major
+// [sample][unit] tiles (the backward pass needs them); inference keeps them in registers
+// (mlp_forward_rf).
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -40,6 +42,7 @@ constexpr int kPB1 = kPW4 + kMlpOutP * kMlpH, kPB2 = kPB1 + kMlpH, kPB3 = kPB2 +
 constexpr int kMlpParams = kPB4 + kMlpOutP;
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -238,6 +241,174 @@ __device__ __forceinline__ void mlp_forward(const MlpNet &n, const uint16_t *xs,
     sync();
     dense_out<L::ldh, L::ldw>(h3, n.W4, n.b4, o, lane, sync);
     sync();
+}
+
+// ------------------------------------------------ register-resident inference ----
+// The C fragment of Y^T = W X^T leaves lane j + 16 g holding units 4g..4g+3 of every 16-unit
+// tile for sample j of every 16-sample tile. Two consecutive unit tiles 2t, 2t+1 thus give it
+// eight units of its sample, which is exactly its B fragment for K block t of the next layer
+// when that layer lists its inputs in the order of these fragments: K slot 8g + e of block t
+// stands for unit 32t + 16 (e/4) + 4g + e % 4. The LDS image of the network stores the
+// columns of W2, W3 and W4 in that order (a permutation of 4-column chunks inside each
+// 32-column block), so a weight fragment stays one 16-byte read and the hidden activations
+// never leave registers. Only the inputs (a transpose: each lane owns one sample) and the
+// outputs (row 0 of the last product sits in lanes 0..15) pass through LDS.
+
+// Source chunk (4 columns) of destination chunk q (0..7) of a 32-column block.
+__host__ __device__ constexpr int hidden_chunk_src(int q) { return 4 * (q & 1) + (q >> 1); }
+
+// Byte offsets of the LDS image of a blob: W1 [64][ldw1], W2 and W3 [64][ldw], W4 [16][ldw]
+// (columns of W2..W4 permuted as above), then the biases, normalisation and box as in the blob.
+template <typename L> struct NetImage {
+    static constexpr int w1 = 0;
+    static constexpr int w2 = w1 + kMlpH * L::ldw1 * 2;
+    static constexpr int w3 = w2 + kMlpH * L::ldw * 2;
+    static constexpr int w4 = w3 + kMlpH * L::ldw * 2;
+    static constexpr int tail = w4 + kMlpOutP * L::ldw * 2;
+    static constexpr int bytes = tail + (kMlpBlobBytes - kOffB1);
+    static_assert(tail % 16 == 0, "16-byte aligned tail");
+};
+
+// Copies a blob into its LDS image (threads tid = 0..nthreads-1 of the block; the caller
+// synchronises afterwards). 8-byte chunks: W1 256, W2 1024, W3 1024, W4 256, tail 136.
+template <typename L>
+__device__ __forceinline__ void stage_net(const unsigned char *blob, unsigned char *img, int tid, int nthreads)
+{
+    using I = NetImage<L>;
+    constexpr int kTail = (kMlpBlobBytes - kOffB1) / 8;
+    const uint2 *src = (const uint2 *)blob;
+    for (int c = tid; c < 256 + 1024 + 1024 + 256 + kTail; c += nthreads) {
+        int soff, doff;
+        if (c < 256) {                       // W1: 4 chunks per row, natural order
+            soff = kOffW1 + c * 8;
+            doff = I::w1 + (c >> 2) * L::ldw1 * 2 + (c & 3) * 8;
+        } else if (c < 256 + 2304) {          // W2, W3, W4: 16 chunks per row, permuted
+            const int q = c - 256;
+            const int layer = q < 1024 ? 0 : q < 2048 ? 1 : 2;
+            const int qq = q - 1024 * layer;
+            const int row = qq >> 4, blk = (qq >> 3) & 1, dq = qq & 7;
+            const int sbase = layer == 0 ? kOffW2 : layer == 1 ? kOffW3 : kOffW4;
+            const int dbase = layer == 0 ? I::w2 : layer == 1 ? I::w3 : I::w4;
+            soff = sbase + (row * kMlpH + 32 * blk + 4 * hidden_chunk_src(dq)) * 2;
+            doff = dbase + (row * L::ldw + 32 * blk + 4 * dq) * 2;
+        } else {                              // biases, normalisation, box
+            const int q = c - 256 - 2304;
+            soff = kOffB1 + q * 8;
+            doff = I::tail + q * 8;
+        }
+        *(uint2 *)(img + doff) = src[soff / 8];
+    }
+}
+
+// ReLU of eight accumulators (units 4g..4g+3 of two unit tiles) rounded to BF16 (nearest,
+// ties to even), as one B fragment. ReLU is taken on the rounded pairs as a signed 16-bit
+// maximum with 0, which equals rounding the ReLU: rounding keeps the sign, and every negative
+// BF16 (sign bit set) is a negative 16-bit integer.
+__device__ __forceinline__ uint32_t relu_bf16x2(float lo, float hi)
+{
+    const s16x2 v = __builtin_bit_cast(s16x2, pack_bf16(lo, hi));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, s16x2{0, 0}));
+}
+__device__ __forceinline__ bf16x8 relu_frag(const f32x4 &a, const f32x4 &b)
+{
+    const uint4 w{relu_bf16x2(a[0], a[1]), relu_bf16x2(a[2], a[3]), relu_bf16x2(b[0], b[1]),
+                  relu_bf16x2(b[2], b[3])};
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// One 64 -> 64 hidden layer on register fragments: h[t][s] (K block t, sample tile s) in,
+// the next layer's fragments out. W is the permuted LDS copy, bias the layer's 64 biases.
+template <typename L>
+__device__ __forceinline__ void hidden_rf(const uint16_t *W, const float *bias, bf16x8 h[2][4], int lane)
+{
+    bf16x8 out[2][4];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        f32x4 acc[2][4];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int mt = 2 * t + u;
+            const f32x4 b = *(const f32x4 *)(bias + 16 * mt + 4 * (lane >> 4));
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                acc[u][s] = b;
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt) {
+                const bf16x8 a = frag8_rows(W, L::ldw, 16 * mt, 32 * kt, lane);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[u][s] = mfma32(a, h[kt][s], acc[u][s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            out[t][s] = relu_frag(acc[0][s], acc[1][s]);
+    }
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            h[t][s] = out[t][s];
+}
+
+// Forward pass of one wave on the LDS image `img` (layout L): xs holds the 64 normalised
+// samples (BF16 [64][L::ldi], row = sample, columns 12..15 zero), o is 64 floats of LDS
+// scratch; returns the output for sample `lane`. sync() must order the wave's LDS writes
+// before its later reads. All 64 lanes must be active.
+template <typename L, typename Sync>
+__device__ __forceinline__ float mlp_forward_rf(const unsigned char *img, const uint16_t *xs, float *o, int lane,
+                                                Sync sync)
+{
+    using I = NetImage<L>;
+    const uint16_t *W1 = (const uint16_t *)(img + I::w1);
+    const float *b1 = (const float *)(img + I::tail + (kOffB1 - kOffB1));
+    const float *b2 = (const float *)(img + I::tail + (kOffB2 - kOffB1));
+    const float *b3 = (const float *)(img + I::tail + (kOffB3 - kOffB1));
+    const float *b4 = (const float *)(img + I::tail + (kOffB4 - kOffB1));
+    bf16x8 h[2][4];
+    {   // input layer, K = 16: B = X^T read from the input tile
+        bf16x4 x[4];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            x[s] = frag_rows(xs, L::ldi, 16 * s, 0, lane);
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            f32x4 acc[2][4];
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                const int mt = 2 * t + u;
+                const f32x4 b = *(const f32x4 *)(b1 + 16 * mt + 4 * (lane >> 4));
+                const bf16x4 a = frag_rows(W1, L::ldw1, 16 * mt, 0, lane);
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    acc[u][s] = mfma16(a, x[s], b);
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+                h[t][s] = relu_frag(acc[0][s], acc[1][s]);
+        }
+    }
+    hidden_rf<L>((const uint16_t *)(img + I::w2), b2, h, lane);
+    hidden_rf<L>((const uint16_t *)(img + I::w3), b3, h, lane);
+    f32x4 acc[4];
+    const float bo = b4[0];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        acc[s] = f32x4{bo, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt) {
+        const bf16x8 a = frag8_rows((const uint16_t *)(img + I::w4), L::ldw, 0, 32 * kt, lane);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            acc[s] = mfma32(a, h[kt][s], acc[s]);
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            o[16 * s + lane] = acc[s][0];
+    }
+    sync();
+    return o[lane];
 }
 
 }  // namespace vct
