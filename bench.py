@@ -104,15 +104,15 @@ def batched(stream) -> dict:
 def learned_leg(full: bool) -> dict:
     """The learned controller against exact MPC on common random numbers: train on the MPC's
     recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
-    evaluation population with both controllers. full: 1,000,000 patients x 364 days as four
-    slices of 250,000 (each slice keeps the patients' global indices); otherwise 100,000 x 28
+    evaluation population with both controllers. full: 1,000,000 patients x 364 days as two
+    slices of 500,000 (each slice keeps the patients' global indices); otherwise 100,000 x 28
     days. Times are the simulation launches only (HIP events); MPC setup and training are
     reported separately."""
     from paper_2202_13927_amd import learned as L, workloads as W
     t0 = time.perf_counter()
     pol, rep = L.train_policy(W.mlp_training_population(), epochs=10.0, log=log)
     train_s = time.perf_counter() - t0
-    n, days, slices = (1_000_000, 364, 4) if full else (100_000, 28, 1)
+    n, days, slices = (1_000_000, 364, 2) if full else (100_000, 28, 1)
     tot = {"mpc": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}, "mlp": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}}
     fb = 0.0
     always = 0

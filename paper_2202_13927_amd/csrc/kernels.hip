@@ -258,13 +258,15 @@ __device__ __forceinline__ float policy_forward(const PolicyShared &ps, const R 
 
 // ------------------------------------------------------ wave-cooperative QP ----
 // The MPC's QP for one patient of the learned controller (its fallback, and the labels when
-// recording), solved by the whole wave: lane i < 24 owns entry i of the plan and the two
-// Toeplitz products of a projected-gradient step become 24 steps of a one-lane shift (DPP
-// wave_shr:1 / wave_shl:1 with zero fill) and an FMA with the uniform Markov parameter
-// h_d. The summation orders are those of mpc_pg, so the result equals the SIMD solver's.
-// The plan lives in global memory, untouched while the network acts: the warm start at
-// sample k is the plan computed at sample k_plan moved on k - k_plan samples (entries past
-// the horizon repeat the last), exactly what shifting it once per sample would give.
+// recording), solved by the whole wave: lane i < 24 owns entry i of the plan and holds row i
+// of Gamma (G[c] = h_(i-c)) and of Gamma^T (T[c] = h_(c-i)), zero outside the triangle.
+// Each Toeplitz product of a projected-gradient step is then 24 FMAs of those rows with the
+// broadcast entries of the vector (v_readlane to scalar registers). Pass 1 runs c downwards
+// and pass 2 upwards, so each lane meets its zero entries first and then sums h_d terms in
+// ascending d, the order of mpc_pg: both solvers give identical results. The plan lives in
+// global memory, untouched while the network acts: the warm start at sample k is the plan
+// computed at sample k_plan moved on k - k_plan samples (entries past the horizon repeat
+// the last), exactly what shifting it once per sample would give.
 __device__ __forceinline__ float lane_shr1(float v)
 {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xF, 0xF, true));
@@ -317,31 +319,41 @@ __device__ __forceinline__ R coop_qp(const SimArgs &a, const R *__restrict__ M, 
 #pragma unroll
     for (int c = 0; c < kNx; ++c)
         g = fmaf_t(soa<R>(M, a.n, jL, kMGx + i * kNx + c), xh[c], g);
-    const R hl = soa<R>(M, a.n, jL, kMh + i);
-    R h[kMpcN];
+    // rows of Gamma and Gamma^T from h (lane i: h_i) and its reverse (lane i: h_(23-i)),
+    // both zero beyond lane 23, by one-lane shifts with zero fill
+    R G[kMpcN], T[kMpcN];
+    G[0] = act ? soa<R>(M, a.n, jL, kMh + i) : R(0);
+    T[kMpcN - 1] = act ? soa<R>(M, a.n, jL, kMh + kMpcN - 1 - i) : R(0);
 #pragma unroll
-    for (int d = 0; d < kMpcN; ++d)
-        h[d] = lane_read(hl, d);
+    for (int c = 1; c < kMpcN; ++c) {
+        G[c] = lane_shr1(G[c - 1]);
+        T[kMpcN - 1 - c] = lane_shl1(T[kMpcN - c]);
+    }
     auto P = as_global((R *)a.plan);
     auto KP = as_global(a.kplan);
     const int32_t sh = min(max(k - KP[jL], 0), kMpcN - 1);
     R dU = act ? P[(int64_t)min(i + sh, kMpcN - 1) * a.n + jL] : R(0);
     for (int it = 0; it < a.mpc_iters; ++it) {
-        R s = dU, r = R(0);
+        // all broadcasts first (distinct scalar registers), then the FMA chain: a scalar
+        // register written by v_readlane is read by VALU only after a wait, which the
+        // batching pays once per product instead of once per term
+        R v[kMpcN];
 #pragma unroll
-        for (int d = 0; d < kMpcN; ++d) {
-            r = fmaf_t(h[d], s, r);
-            if (d + 1 < kMpcN)
-                s = lane_shr1(s);
-        }
-        r = act ? r : R(0);
-        R acc = fmaf_t(rho, dU, g), t = r;
+        for (int c = 0; c < kMpcN; ++c)
+            v[c] = lane_read(dU, c);
+        __builtin_amdgcn_sched_barrier(0);
+        R r = R(0);
 #pragma unroll
-        for (int d = 0; d < kMpcN; ++d) {
-            acc = fmaf_t(h[d], t, acc);
-            if (d + 1 < kMpcN)
-                t = lane_shl1(t);
-        }
+        for (int c = kMpcN - 1; c >= 0; --c)
+            r = fmaf_t(G[c], v[c], r);
+#pragma unroll
+        for (int c = 0; c < kMpcN; ++c)
+            v[c] = lane_read(r, c);
+        __builtin_amdgcn_sched_barrier(0);
+        R acc = fmaf_t(rho, dU, g);
+#pragma unroll
+        for (int c = 0; c < kMpcN; ++c)
+            acc = fmaf_t(T[c], v[c], acc);
         dU = act ? vmin(vmax(fmaf_t(-step, acc, dU), lo), hi) : R(0);
     }
     if (liveL && act)
@@ -914,8 +926,9 @@ static void launch_sim_o(const SimArgs &a, hipStream_t s)
                            (int32_t *)a.order);
         // persistent grid: every resident workgroup, but no more waves than there can be items
         int dev = 0, cus = 0, per_cu = 0;
-        hipGetDevice(&dev);
-        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, simulate_policy_kernel<R, NOISY, OUT>, kPolicyBlock,
                                                          0) != hipSuccess)
             per_cu = 1;
