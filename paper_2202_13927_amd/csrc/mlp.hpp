@@ -316,10 +316,29 @@ __device__ __forceinline__ bf16x8 relu_frag(const f32x4 &a, const f32x4 &b)
     return __builtin_bit_cast(bf16x8, w);
 }
 
-// One 64 -> 64 hidden layer on register fragments: h[t][s] (K block t, sample tile s) in,
-// the next layer's fragments out. W is the permuted LDS copy, bias the layer's 64 biases.
+// Weight and bias fragments of one 64 -> 64 layer for this lane: a[mt][kt] rows 16mt..,
+// K block kt of the permuted LDS copy; b[mt] the biases of units 16mt + 4g .. +3.
+struct HiddenFrags {
+    bf16x8 a[4][2];
+    f32x4 b[4];
+};
 template <typename L>
-__device__ __forceinline__ void hidden_rf(const uint16_t *W, const float *bias, bf16x8 h[2][4], int lane)
+__device__ __forceinline__ HiddenFrags hidden_frags(const uint16_t *W, const float *bias, int lane)
+{
+    HiddenFrags f;
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        f.b[mt] = *(const f32x4 *)(bias + 16 * mt + 4 * (lane >> 4));
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+            f.a[mt][kt] = frag8_rows(W, L::ldw, 16 * mt, 32 * kt, lane);
+    }
+    return f;
+}
+
+// One 64 -> 64 hidden layer on register fragments: h[t][s] (K block t, sample tile s) in,
+// the next layer's fragments out.
+__device__ __forceinline__ void hidden_rf(const HiddenFrags &f, bf16x8 h[2][4])
 {
     bf16x8 out[2][4];
 #pragma unroll
@@ -327,18 +346,14 @@ __device__ __forceinline__ void hidden_rf(const uint16_t *W, const float *bias, 
         f32x4 acc[2][4];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
-            const int mt = 2 * t + u;
-            const f32x4 b = *(const f32x4 *)(bias + 16 * mt + 4 * (lane >> 4));
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                acc[u][s] = b;
+                acc[u][s] = f.b[2 * t + u];
 #pragma unroll
-            for (int kt = 0; kt < 2; ++kt) {
-                const bf16x8 a = frag8_rows(W, L::ldw, 16 * mt, 32 * kt, lane);
+            for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
-                    acc[u][s] = mfma32(a, h[kt][s], acc[u][s]);
-            }
+                    acc[u][s] = mfma32(f.a[2 * t + u][kt], h[kt][s], acc[u][s]);
         }
 #pragma unroll
         for (int s = 0; s < 4; ++s)
@@ -354,7 +369,8 @@ __device__ __forceinline__ void hidden_rf(const uint16_t *W, const float *bias, 
 // Forward pass of one wave on the LDS image `img` (layout L): xs holds the 64 normalised
 // samples (BF16 [64][L::ldi], row = sample, columns 12..15 zero), o is 64 floats of LDS
 // scratch; returns the output for sample `lane`. sync() must order the wave's LDS writes
-// before its later reads. All 64 lanes must be active.
+// before its later reads. All 64 lanes must be active. Each layer's weight fragments are
+// read one layer ahead, so the LDS latency overlaps the previous layer's MFMAs.
 template <typename L, typename Sync>
 __device__ __forceinline__ float mlp_forward_rf(const unsigned char *img, const uint16_t *xs, float *o, int lane,
                                                 Sync sync)
@@ -365,43 +381,48 @@ __device__ __forceinline__ float mlp_forward_rf(const unsigned char *img, const 
     const float *b2 = (const float *)(img + I::tail + (kOffB2 - kOffB1));
     const float *b3 = (const float *)(img + I::tail + (kOffB3 - kOffB1));
     const float *b4 = (const float *)(img + I::tail + (kOffB4 - kOffB1));
+    bf16x4 a1[4], x[4];
+    f32x4 bb1[4];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        a1[mt] = frag_rows(W1, L::ldw1, 16 * mt, 0, lane);
+        bb1[mt] = *(const f32x4 *)(b1 + 16 * mt + 4 * (lane >> 4));
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+        x[s] = frag_rows(xs, L::ldi, 16 * s, 0, lane);
+    const HiddenFrags f2 = hidden_frags<L>((const uint16_t *)(img + I::w2), b2, lane);
     bf16x8 h[2][4];
-    {   // input layer, K = 16: B = X^T read from the input tile
-        bf16x4 x[4];
+    // input layer, K = 16: B = X^T read from the input tile
 #pragma unroll
-        for (int s = 0; s < 4; ++s)
-            x[s] = frag_rows(xs, L::ldi, 16 * s, 0, lane);
+    for (int t = 0; t < 2; ++t) {
+        f32x4 acc[2][4];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            f32x4 acc[2][4];
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                const int mt = 2 * t + u;
-                const f32x4 b = *(const f32x4 *)(b1 + 16 * mt + 4 * (lane >> 4));
-                const bf16x4 a = frag_rows(W1, L::ldw1, 16 * mt, 0, lane);
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    acc[u][s] = mfma16(a, x[s], b);
-            }
+        for (int u = 0; u < 2; ++u)
 #pragma unroll
             for (int s = 0; s < 4; ++s)
-                h[t][s] = relu_frag(acc[0][s], acc[1][s]);
-        }
+                acc[u][s] = mfma16(a1[2 * t + u], x[s], bb1[2 * t + u]);
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            h[t][s] = relu_frag(acc[0][s], acc[1][s]);
     }
-    hidden_rf<L>((const uint16_t *)(img + I::w2), b2, h, lane);
-    hidden_rf<L>((const uint16_t *)(img + I::w3), b3, h, lane);
-    f32x4 acc[4];
+    const HiddenFrags f3 = hidden_frags<L>((const uint16_t *)(img + I::w3), b3, lane);
+    hidden_rf(f2, h);
+    bf16x8 a4[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+        a4[kt] = frag8_rows((const uint16_t *)(img + I::w4), L::ldw, 0, 32 * kt, lane);
     const float bo = b4[0];
+    hidden_rf(f3, h);
+    f32x4 acc[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
         acc[s] = f32x4{bo, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int kt = 0; kt < 2; ++kt) {
-        const bf16x8 a = frag8_rows((const uint16_t *)(img + I::w4), L::ldw, 0, 32 * kt, lane);
+    for (int kt = 0; kt < 2; ++kt)
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            acc[s] = mfma32(a, h[kt][s], acc[s]);
-    }
+            acc[s] = mfma32(a4[kt], h[kt][s], acc[s]);
     if (lane < 16) {
 #pragma unroll
         for (int s = 0; s < 4; ++s)
