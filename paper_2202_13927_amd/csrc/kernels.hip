@@ -178,6 +178,7 @@ template <typename R> struct PolicyLane {
     R ins[6], ins0;          // f6 = ins . (S1s, S2s, I, x1h, x2h, e3) + ins0
     R meal_d1, meal_d2, wbar;   // f7 = D1s meal_d1 + D2 meal_d2 + dhat wbar
     R st[4];
+    R kg[kNx];               // Kalman gain (learned controller: held in registers)
     int32_t fallbacks;       // samples on which the MPC acted instead of the network
 };
 
@@ -437,7 +438,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         // the MPC's QP is solved on every sample and its action recorded as the label of
         // the network's inputs (data aggregation along the network's own closed loop).
         const R *M = (const R *)a.mpc;
-        mpc_measure<R>(M, a.n, j, ms, y);
+        mpc_measure_gain<R>(pl.kg, ms, y);
         bool ood = false;
 #pragma unroll
         for (int q = 0; q < kMlpIn; ++q)
@@ -564,6 +565,9 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
         pl.meal_d2 = R(fb[kXD2]);
         pl.wbar = R((double)M[(int64_t)kMwbar * a.n + j]);
         patient_inputs<R>(a, j, pl.st);
+#pragma unroll
+        for (int q = 0; q < kNx; ++q)
+            pl.kg[q] = M[(int64_t)(kMK + q) * a.n + j];
         pl.fallbacks = 0;
     }
 

@@ -94,6 +94,16 @@ __device__ __forceinline__ void mpc_measure(const R *__restrict__ M, int64_t n, 
         L.xh[i] = fmaf_t(soa<R>(M, n, (uint32_t)j, kMK + i), innov, L.xh[i]);
 }
 
+// The same with the Kalman gain held in registers (kg = rows kMK.. of the patient).
+template <typename R>
+__device__ __forceinline__ void mpc_measure_gain(const R kg[kNx], MpcState<R> &L, R y)
+{
+    const R innov = (y - L.gi_ss) - L.xh[kXGI];
+#pragma unroll
+    for (int i = 0; i < kNx; ++i)
+        L.xh[i] = fmaf_t(kg[i], innov, L.xh[i]);
+}
+
 // g = Gamma^T (F xh + w dhat + (G* - ybar) 1).
 template <typename R>
 __device__ __forceinline__ void mpc_linear_term(const R *__restrict__ M, int64_t n, int64_t j, const MpcState<R> &L,
