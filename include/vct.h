@@ -121,7 +121,8 @@ typedef struct {
  * by vct_mpc_setup). The Kalman filter of the MPC runs on every sample; the
  * MPC solves its QP and acts instead of the network (a "fallback") when any input lies
  * outside the box stored with the network, or when y_k < mlp_safe_g and out > mlp_safe_out
- * (e.g. 3.9 mmol/L and 1: never more than basal insulin while the sensor reads low). */
+ * (e.g. 3.0 mmol/L and 1: never more than basal insulin while the sensor reads below
+ * 54 mg/dL). */
 typedef struct {
     int32_t kind;          /* VCT_CTRL_*                                           */
     double  setpoint;      /* mmol/L                                               */

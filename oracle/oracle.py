@@ -167,7 +167,7 @@ def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=N
     c.mpc_rho = float(trial.get("mpc_rho", 1.0))
     c.mpc_riccati_iters = int(trial.get("mpc_riccati_iters", 500))
     c.mpc_power_iters = int(trial.get("mpc_power_iters", 100))
-    c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.9))
+    c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.0))
     c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
     return c
 

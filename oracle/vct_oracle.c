@@ -948,7 +948,7 @@ static void mlp_inputs(const mpc_state *st, const double *p, double ub, const do
 }
 
 /* The network acts unless an input is outside its box or, while the sensor reads low
- * (y_k < mlp_safe_g), its output exceeds mlp_safe_out (e.g. 3.9 mmol/L and 1: not above basal);
+ * (y_k < mlp_safe_g), its output exceeds mlp_safe_out (e.g. 3.0 mmol/L and 1: not above basal);
  * then the MPC solves its QP. The Kalman filter runs on
  * every sample; when the network acts the MPC's plan is only shifted. With `label` non-NULL
  * (data aggregation along the network's closed loop) the QP is solved on every sample and

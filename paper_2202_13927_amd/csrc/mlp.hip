@@ -325,8 +325,10 @@ __global__ void mlp_update_kernel(const float *__restrict__ partial, int n_parts
                                   float lr, float bc1, float bc2, int apply)
 {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    // sequential sums (fixed order); unrolled so that the loads are issued ahead of the adds
     if (p == 0) {
         float l = 0.f;
+#pragma unroll 16
         for (int b = 0; b < n_parts; ++b)
             l += loss_partial[b];
         *loss = l;
@@ -334,6 +336,7 @@ __global__ void mlp_update_kernel(const float *__restrict__ partial, int n_parts
     if (p >= kMlpParams)
         return;
     float gs = 0.f;
+#pragma unroll 16
     for (int b = 0; b < n_parts; ++b)
         gs += partial[(int64_t)b * kMlpParams + p];
     if (padded_param(p))

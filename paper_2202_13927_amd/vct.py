@@ -322,7 +322,7 @@ def controller(trial: dict, mpc_dev=None, mlp_dev=None) -> vct_controller:
     c.mpc_horizon, c.mpc_iters = int(trial["mpc_horizon"]), int(trial["mpc_iters"])
     c.mpc_dev = _ptr(mpc_dev)
     c.mlp_dev = _ptr(mlp_dev)
-    c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.9))
+    c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.0))
     c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
     return c
 

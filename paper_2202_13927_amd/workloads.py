@@ -65,8 +65,8 @@ def base_trial() -> dict:
         "mpc_iters": 50,
         "mpc_rho": 1.0,
         # learned controller: the MPC takes over while the sensor reads below mlp_safe_g
-        # (mmol/L) and the network asks for more than mlp_safe_out u_b
-        "mlp_safe_g": 3.9,
+        # (mmol/L, level-2 hypoglycaemia) and the network asks for more than mlp_safe_out u_b
+        "mlp_safe_g": 3.0,
         "mlp_safe_out": 1.0,
         # (3) model + simulation settings
         "n_days": 7,

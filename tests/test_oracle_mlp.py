@@ -187,9 +187,10 @@ def test_box_excluding_everything_is_mpc(orc):
 
 
 def test_safety_rule(orc):
-    """out = 2 and a box admitting everything: u = 2 u_b except on samples with y < 3.9,
-    where the MPC acts; the fallback count is the number of such samples."""
-    t = _small(W.c5_mlp(), n_patients=24, n_days=3)
+    """out = 2 and a box admitting everything: u = 2 u_b except on samples with y < 3.9
+    (the safety threshold set for this test), where the MPC acts; the fallback count is the
+    number of such samples."""
+    t = _small(W.c5_mlp(), n_patients=24, n_days=3, mlp_safe_g=3.9)
     r = orc.simulate(t, n_traj=24, threads=4, mlp=W.constant_policy_net(2.0))
     low = r["traj_y"] < 3.9
     ub = r["params"][:, 15][:, None]
