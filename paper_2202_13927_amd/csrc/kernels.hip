@@ -439,9 +439,12 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         // the network's inputs (data aggregation along the network's own closed loop).
         const R *M = (const R *)a.mpc;
         mpc_measure_gain<R>(pl.kg, ms, y);
-        bool ood = false;
+        // The fixed inputs f8..f11 decided the lane order: every patient of a tile wave has
+        // them inside the box (the same comparisons), every other patient is alone on a
+        // wave and falls back on every sample. Only the time-varying inputs are tested here.
+        bool ood = ps.rest;
 #pragma unroll
-        for (int q = 0; q < kMlpIn; ++q)
+        for (int q = 0; q < 8; ++q)
             ood |= !(f[q] >= R(ps.lo[q]) && f[q] <= R(ps.hi[q]));
         // (a wave whose patient is outside the box needs no network: its fallback is certain)
         const float o = ps.rest ? 0.0f : policy_forward<R>(ps, f);
