@@ -406,6 +406,45 @@ def test_labels_with_empty_box_equal_mpc_rows(G):
     assert torch.equal(bufs.record.view(-1, 13), rows_mpc)
 
 
+def test_network_in_the_loop_equals_forward(G):
+    """The network inside the simulation kernel and vct_mlp_forward run the same code on the
+    same staged weights: on every sample of the recorded patients where the network acts,
+    the applied insulin is exactly clamp(u_b out, 0, u_max) with out from vct_mlp_forward on
+    the recorded inputs; where the MPC acts it is the recorded MPC label. The fallback
+    decision (box, safety rule) recomputed from the recorded inputs gives each patient's
+    fallback count exactly."""
+    torch, policy, trial = G
+    t = _mlp_trial(precision=W.FP32, n_patients=130, n_days=1, mlp_safe_g=3.9)
+    pol = policy.Policy(batch=64)
+    pol.load(W.synthetic_policy_net(71))
+    net = policy.unpack_blob(pol.blob)
+    bufs = trial.TrialBuffers(t, traj_patients=8)
+    bufs.record = torch.empty(bufs.K * bufs.n * 13, dtype=torch.float32, device="cuda")
+    _say("[gpu] learned controller: network in the loop vs vct_mlp_forward, 130 x 1 d FP32")
+    trial.run(t, bufs=bufs, mlp_blob=pol.blob)
+    h = trial.to_host(bufs)
+    rec = bufs.record.view(bufs.K, bufs.n, 13)
+    f32 = np.float32
+    lo, hi = net["lo"].astype(f32), net["hi"].astype(f32)
+    acted = 0
+    for p in range(8):
+        feats = rec[:, p, :12].contiguous()
+        out = pol.forward(feats).cpu().numpy()
+        f = feats.cpu().numpy()
+        ub = f32(h["params"][p, 15])
+        umax = f32(t["umax_rel"] * h["params"][p, 15])
+        ood = np.any(~((f >= lo) & (f <= hi)), axis=1)
+        fb = ood | ((f[:, 0] < f32(t["mlp_safe_g"])) & (out > f32(t["mlp_safe_out"])))
+        assert int(fb.sum()) == int(h["fallback"][p])
+        u_net = np.minimum(np.maximum(ub * out, f32(0)), umax)
+        u = h["traj_u"][p]
+        assert np.array_equal(u[~fb], u_net[~fb].astype(np.float64))
+        lab = rec[:, p, 12].cpu().numpy().astype(np.float64) * float(ub)
+        assert np.allclose(u[fb], lab[fb], rtol=1e-6, atol=0)
+        acted += int((~fb).sum())
+    assert acted > 0
+
+
 def test_trained_network_gain(G):
     """End to end, on the GPU only: record the MPC's closed loop on a training population,
     fit the network, then run a separate population three ways on common random numbers.
