@@ -13,6 +13,8 @@ The JSON line also carries
 * cpu_baseline -- the FP64 oracle on a bounded sample of the same trial, timed on
   this host's cores;
 * batched -- the 64-arm heterogeneous PID trial in one persistent graph-captured launch;
+* nordic -- the paper's Northern-European protocol (Tables I-II) for 1,000,000 patients x
+  364 days, PID, one simulation launch;
 * learned -- the learned controller against exact linear MPC on common random numbers
   (100,000 x 28 days by default, 1,000,000 x 364 days with --learned-full).
 """
@@ -101,6 +103,35 @@ def batched(stream) -> dict:
         bt.close()
 
 
+def nordic_leg(stream) -> dict:
+    """The paper's Northern-European year (four seasons of standard / active / vacation
+    weeks, per-patient arrangements, BW-scaled meals) for the paper-scale population, PID:
+    one simulation launch timed with HIP events on its stream."""
+    import torch
+    from paper_2202_13927_amd import trial as T, vct, workloads as W
+    t = W.nordic_year()
+    bufs = T.TrialBuffers(t)
+    pop = T.create_population(t, bufs, stream)
+    try:
+        T.simulate(t, pop, bufs, stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        T.simulate(t, pop, bufs, stream)
+        e1.record(stream)
+        s = T.read_metrics(bufs, stream)
+        ms = e0.elapsed_time(e1)
+    finally:
+        vct.vct_destroy_population(pop)
+    pd = t["n_patients"] * t["n_days"]
+    log(f"[bench] nordic: {ms:.1f} ms, mean TIR {s['mean_tir']:.4f}")
+    return {"workload": "Northern-European protocol (Sec. II-B, Tables I-II), 1000000 patients x 364 days, PID, "
+                        "FP32, meal size SD 10 %, onset jitter +-30 min", "patient_days": pd, "ms": ms,
+            "patient_days_per_s": pd / ms * 1e3, "mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"],
+            "mean_bg_mmol": s["mean_bg"]}
+
+
 def learned_leg(full: bool) -> dict:
     """The learned controller against exact MPC on common random numbers: train on the MPC's
     recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
@@ -150,6 +181,7 @@ def main() -> int:
     ap.add_argument("--days", type=int, default=None, help="override the horizon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-arm batched trial")
+    ap.add_argument("--no-nordic", action="store_true", help="skip the Northern-European protocol run")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scales HBM byte counters)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-controller comparison")
@@ -245,6 +277,8 @@ def main() -> int:
     del bufs
     if not args.no_batched:
         out["batched"] = batched(stream)
+    if not args.no_nordic:
+        out["nordic"] = nordic_leg(stream)
     if not args.no_learned:
         out["learned"] = learned_leg(args.learned_full)
     if not args.no_cpu_baseline:

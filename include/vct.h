@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VCT_ABI_VERSION 1
+#define VCT_ABI_VERSION 2
 #define VCT_NP 15          /* sampled parameters per patient                         */
 #define VCT_NX 11          /* model states per patient                               */
 #define VCT_NPARAM_ROWS 19 /* rows of the population buffer: 15 parameters, u_b, I*, attempts, status */
@@ -83,19 +83,34 @@ typedef struct {
     int64_t  first_patient;    /* global index of the first patient, >= 0, first + n <= 2^32 */
 } vct_population_desc;
 
-/* (2) protocol -- Sec. II-B: disturbances with type, size and time. Each day and slot
- * draws one Philox block (counter (day, patient, 1, slot), simulation key):
- * carbs = max(0, mean + sd z), onset = minute_of_day + jitter with jitter uniform on
- * the integers [-jitter_min, jitter_min], present with probability prob. The meal is
- * a constant glucose intake over the sampling interval that contains the onset.
- * Slots must be in increasing time order, non-overlapping after jitter. */
+/* (2) protocol -- Sec. II-B: disturbances with type, size and time. A meal is a constant
+ * glucose intake over the sampling interval that contains its onset; the onset jitter is
+ * uniform on the integers [-jitter_min, jitter_min].
+ * VCT_PROTO_SLOTS: each day and slot draws one Philox block (counter (day, patient, 1,
+ * slot), simulation key): carbs = max(0, mean + sd z), onset = minute_of_day + jitter,
+ * present with probability prob. Slots must be in increasing time order, non-overlapping
+ * after jitter.
+ * VCT_PROTO_NORDIC: the Northern-European protocol of Sec. II-B (Tables I and II): four
+ * 13-week seasons of standard / active / vacation weeks (winter 6/4/3, spring 6/6/1,
+ * summer 7/3/3, autumn 9/3/1), weeks of standard / active / movie-night / late-night days
+ * (standard 4/1/1/1, active 3/3/1/0, vacation 5/0/0/2), each patient's arrangement of
+ * weeks in a season and of days in a week a Fisher-Yates shuffle on Philox blocks
+ * (d / 91, patient, 8, 0..2) and (d / 7, patient, 8, 4..5); meal sizes 1.29 / 0.86 / 0.57 /
+ * 0.29 g carbohydrate per kg body weight (large / medium / small / snack), times and sizes
+ * per day type and season as documented in the kernels; carbs = max(0, size BW (1 +
+ * meal_cv z)) from Philox block (day, patient, 1, meal kind). The slot fields are unused;
+ * jitter_min <= 40. Day 0 is the first day of winter. */
+#define VCT_PROTO_SLOTS  0
+#define VCT_PROTO_NORDIC 1
 typedef struct {
     int32_t n_slots;                        /* 0..VCT_MAX_SLOTS                    */
     int32_t minute_of_day[VCT_MAX_SLOTS];
     double  carbs_mean_g[VCT_MAX_SLOTS];
     double  carbs_sd_g[VCT_MAX_SLOTS];
     double  prob[VCT_MAX_SLOTS];            /* in [0, 1]                           */
-    int32_t jitter_min;                     /* 0..120                              */
+    int32_t jitter_min;                     /* 0..120 (VCT_PROTO_NORDIC: 0..40)    */
+    int32_t kind;                           /* VCT_PROTO_SLOTS or VCT_PROTO_NORDIC */
+    double  meal_cv;                        /* VCT_PROTO_NORDIC: relative SD of each meal, 0..1 */
 } vct_protocol;
 
 /* (5) controller -- Sec. III-B (x^c_{k+1} = kappa(x^c_k, y_k, ...), u_k = lambda(...)).

@@ -24,6 +24,7 @@ class OrcConfig(C.Structure):
         ("g_target", C.c_double),
         ("n_slots", C.c_int32), ("minute_of_day", C.c_int32 * MAX_SLOTS), ("carbs_mean", C.c_double * MAX_SLOTS),
         ("carbs_sd", C.c_double * MAX_SLOTS), ("prob", C.c_double * MAX_SLOTS), ("jitter", C.c_int32),
+        ("proto", C.c_int32), ("meal_cv", C.c_double),
         ("ctrl_kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
         ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double),
         ("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("sigma_q1", C.c_double),
@@ -107,6 +108,9 @@ def lib() -> C.CDLL:
         L.orc_reduce.argtypes = [C.c_int64, C.c_int64, _P(C.c_int32), _P(C.c_int32), _P(C.c_double),
                                  _P(C.c_double), _P(C.c_int32), _P(C.c_uint32), _P(OrcSummary)]
         L.orc_meals.argtypes = [_P(OrcConfig), C.c_uint32, C.c_int32, _P(C.c_double)]
+        L.orc_nordic_day.argtypes = [_P(OrcConfig), C.c_uint32, C.c_int32, _P(C.c_int32)]
+        L.orc_day_meals.argtypes = [_P(OrcConfig), C.c_uint32, C.c_int32, _P(C.c_double)]
+        L.orc_day_meals.restype = C.c_int
         L.orc_jacobian.argtypes = [_P(OrcConfig), _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_double),
                                    _P(C.c_double)]
         L.orc_mpc_setup.argtypes = [_P(OrcConfig), _P(C.c_double), _P(OrcMpc)]
@@ -151,6 +155,8 @@ def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=N
         c.carbs_sd[m] = float(trial["carbs_sd"][m])
         c.prob[m] = float(trial["prob"][m])
     c.jitter = int(trial["jitter"])
+    c.proto = int(trial.get("proto", 0))
+    c.meal_cv = float(trial.get("meal_cv", 0.0))
     c.ctrl_kind = int(trial["ctrl_kind"])
     for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel", "sigma_q1", "cgm_var"):
         setattr(c, k, float(trial[k]))
@@ -235,6 +241,22 @@ def meals(trial: dict, patient: int, day: int) -> np.ndarray:
     cfg = config(trial)
     lib().orc_meals(C.byref(cfg), int(patient), int(day), _ptr(out, C.c_double))
     return out
+
+
+def nordic_day(trial: dict, patient: int, day: int) -> tuple[int, int, int]:
+    """(season, week type, day type) of a patient's day under the Northern-European protocol."""
+    out = np.zeros(3, dtype=np.int32)
+    cfg = config(trial)
+    lib().orc_nordic_day(C.byref(cfg), int(patient), int(day), _ptr(out, C.c_int32))
+    return int(out[0]), int(out[1]), int(out[2])
+
+
+def day_meals(trial: dict, patient: int, day: int) -> np.ndarray:
+    """The day's meals in time order: rows (sample index within the day, carbs g, mmol/min)."""
+    out = np.zeros((8, 3))
+    cfg = config(trial)
+    n = lib().orc_day_meals(C.byref(cfg), int(patient), int(day), _ptr(out, C.c_double))
+    return out[:n].copy()
 
 
 def pid_run(trial: dict, u_b: float, y) -> tuple[np.ndarray, np.ndarray]:

@@ -262,9 +262,128 @@ static void meal_draw(const orc_config *cfg, uint32_t patient, int32_t day, int 
     *kd = (cfg->minute_of_day[m] + *jit) / cfg->ts_min;
 }
 
-static int meals_for_day(const orc_config *cfg, uint32_t patient, int32_t day, const uint32_t key[2],
-                         meal_t meals[ORC_MAX_SLOTS])
+/* ------------------------------------------- Northern-European protocol ---- */
+/* Sec. II-B. A year is four seasons of 13 weeks (winter, spring, summer, autumn; day 0 is
+ * the first day of winter). Table I gives how many standard, active and vacation weeks
+ * each season has, and how many standard days, active days, movie-night days and
+ * late-night days each week type has. The order within a season and within a week is not
+ * given: each patient gets a random arrangement, a Fisher-Yates shuffle (the last slot
+ * swapped with a uniformly chosen slot at or before it, then the one before, ...) of the
+ * list written out in table order, with 24-bit uniforms from Philox blocks (season index,
+ * patient, PROTO, 0..2) for the weeks and (week index, patient, PROTO, 4..5) for the days,
+ * used in order. Table II gives the meal sizes per kg of body weight. The day's meals
+ * (clock times and which meal has which size are this project's reading of the text around
+ * the missing figure): breakfast 07:00 small; lunch 12:00 medium; dinner 18:00 large in
+ * winter and autumn, medium in spring and summer; one snack, at 10:00 in spring and summer
+ * and at 15:00 in winter and autumn; a movie night adds a snack at 21:00 and a late night
+ * adds snacks at 21:00 and 22:30. In vacation weeks breakfast, lunch and dinner are one
+ * size larger (large stays large). The exercise session of an active day is not an input of
+ * this model. Each meal draws Philox block (day, patient, MEAL, q) for its kind q (0
+ * breakfast, 1 morning snack, 2 lunch, 3 afternoon snack, 4 dinner, 5, 6 evening snacks):
+ * carbs = max(0, size BW (1 + meal_cv z)), z the cosine normal of (u0, u1), and the
+ * onset jitter from u2 as for the slot protocol. */
+#define TAG_PROTO 8u
+static const int nordic_season_weeks[4][3] = {{6, 4, 3}, {6, 6, 1}, {7, 3, 3}, {9, 3, 1}};
+static const int nordic_week_days[3][4] = {{4, 1, 1, 1}, {3, 3, 1, 0}, {5, 0, 0, 2}};
+enum { SIZE_LARGE, SIZE_MEDIUM, SIZE_SMALL, SIZE_SNACK };
+static const double nordic_g_per_kg[4] = {1.29, 0.86, 0.57, 0.29};
+
+static void nordic_words(uint32_t c0, uint32_t patient, uint32_t first_sub, int nblocks, const uint32_t key[2],
+                         uint32_t *w)
 {
+    for (int b = 0; b < nblocks; ++b) {
+        uint32_t ctr[4] = {c0, patient, TAG_PROTO, first_sub + (uint32_t)b};
+        orc_philox4x32_10(ctr, key, w + 4 * b);
+    }
+}
+
+static void fisher_yates(int *list, int n, const uint32_t *w)
+{
+    int used = 0;
+    for (int i = n - 1; i >= 1; --i) {
+        uint64_t u24 = w[used++] >> 8;
+        int j = (int)((u24 * (uint64_t)(i + 1)) >> 24);
+        int t = list[i];
+        list[i] = list[j];
+        list[j] = t;
+    }
+}
+
+static void nordic_day_types(uint32_t patient, int32_t day, const uint32_t key[2], int *season, int *wtype,
+                             int *dtype)
+{
+    *season = (day / 91) % 4;
+    int weeks[13], n = 0;
+    for (int t = 0; t < 3; ++t)
+        for (int e = 0; e < nordic_season_weeks[*season][t]; ++e)
+            weeks[n++] = t;
+    uint32_t w[12];
+    nordic_words((uint32_t)(day / 91), patient, 0u, 3, key, w);
+    fisher_yates(weeks, 13, w);
+    *wtype = weeks[(day % 91) / 7];
+    int days[7];
+    n = 0;
+    for (int t = 0; t < 4; ++t)
+        for (int e = 0; e < nordic_week_days[*wtype][t]; ++e)
+            days[n++] = t;
+    uint32_t v[8];
+    nordic_words((uint32_t)(day / 7), patient, 4u, 2, key, v);
+    fisher_yates(days, 7, v);
+    *dtype = days[day % 7];
+}
+
+void orc_nordic_day(const orc_config *cfg, uint32_t patient, int32_t day, int32_t *out)
+{
+    uint32_t key[2];
+    make_key(cfg->noise_seed, cfg->arm_id, key);
+    int s, wt, dt;
+    nordic_day_types(patient, day, key, &s, &wt, &dt);
+    out[0] = s;
+    out[1] = wt;
+    out[2] = dt;
+}
+
+static int nordic_meals(const orc_config *cfg, uint32_t patient, int32_t day, double bw, const uint32_t key[2],
+                        meal_t meals[ORC_MAX_DAY_MEALS])
+{
+    int season, wtype, dtype;
+    nordic_day_types(patient, day, key, &season, &wtype, &dtype);
+    const int winter_autumn = season == 0 || season == 3, vacation = wtype == 2;
+    /* kind, minute, size, present */
+    const int plan[7][3] = {
+        {420, vacation ? SIZE_MEDIUM : SIZE_SMALL, 1},
+        {600, SIZE_SNACK, !winter_autumn},
+        {720, vacation ? SIZE_LARGE : SIZE_MEDIUM, 1},
+        {900, SIZE_SNACK, winter_autumn},
+        {1080, (winter_autumn || vacation) ? SIZE_LARGE : SIZE_MEDIUM, 1},
+        {1260, SIZE_SNACK, dtype == 2 || dtype == 3},
+        {1350, SIZE_SNACK, dtype == 3},
+    };
+    int n = 0;
+    for (int q = 0; q < 7; ++q) {
+        if (!plan[q][2])
+            continue;
+        uint32_t ctr[4] = {(uint32_t)day, patient, TAG_MEAL, (uint32_t)q};
+        uint32_t x[4];
+        orc_philox4x32_10(ctr, key, x);
+        double z0, z1;
+        box_muller(orc_uniform(x[0]), orc_uniform(x[1]), &z0, &z1);
+        double c = nordic_g_per_kg[plan[q][1]] * bw * (1.0 + cfg->meal_cv * z0);
+        uint32_t odd = 2u * (x[2] >> 9) + 1u;
+        int32_t jit = (int32_t)(((uint64_t)odd * (uint64_t)(2 * cfg->jitter + 1)) >> 24) - cfg->jitter;
+        meals[n].kd = (plan[q][0] + jit) / cfg->ts_min;
+        meals[n].carbs = c < 0.0 ? 0.0 : c;
+        meals[n].rate = meals[n].carbs * (1000.0 / 180.16) / (double)cfg->ts_min;
+        ++n;
+    }
+    return n;
+}
+
+static int meals_for_day(const orc_config *cfg, uint32_t patient, int32_t day, double bw, const uint32_t key[2],
+                         meal_t meals[ORC_MAX_DAY_MEALS])
+{
+    if (cfg->proto == ORC_PROTO_NORDIC)
+        return nordic_meals(cfg, patient, day, bw, key, meals);
     int n = 0;
     for (int m = 0; m < cfg->n_slots; ++m) {
         int present;
@@ -277,6 +396,24 @@ static int meals_for_day(const orc_config *cfg, uint32_t patient, int32_t day, c
         meals[n].carbs = carbs;
         meals[n].rate = carbs * (1000.0 / 180.16) / (double)cfg->ts_min;
         ++n;
+    }
+    return n;
+}
+
+/* The day's meals in time order under either protocol (tests): out[n][3] = (sample index
+ * within the day, carbs g, intake mmol/min); returns n. */
+int orc_day_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out)
+{
+    uint32_t key[2];
+    make_key(cfg->noise_seed, cfg->arm_id, key);
+    double prm[ORC_NPOUT];
+    sample_patient(cfg, patient, prm);
+    meal_t meals[ORC_MAX_DAY_MEALS];
+    int n = meals_for_day(cfg, patient, day, prm[14], key, meals);
+    for (int m = 0; m < n; ++m) {
+        out[3 * m + 0] = (double)meals[m].kd;
+        out[3 * m + 1] = meals[m].carbs;
+        out[3 * m + 2] = meals[m].rate;
     }
     return n;
 }
@@ -1055,8 +1192,8 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
     }
 
     for (int32_t day = 0; day < cfg->n_days; ++day) {
-        meal_t meals[ORC_MAX_SLOTS];
-        int nm = meals_for_day(cfg, patient, day, nkey, meals);
+        meal_t meals[ORC_MAX_DAY_MEALS];
+        int nm = meals_for_day(cfg, patient, day, p[14], nkey, meals);
         for (int32_t kd = 0; kd < kday; ++kd) {
             int64_t k = (int64_t)day * kday + kd;
             double G = x[X_Q1] / vg;
@@ -1175,7 +1312,9 @@ int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_thre
         return -1;
     if (cfg->n_slots < 0 || cfg->n_slots > ORC_MAX_SLOTS || cfg->n_days < 0 || count < 0)
         return -1;
-    for (int m = 0; m < cfg->n_slots; ++m)
+    if (cfg->proto != ORC_PROTO_SLOTS && cfg->proto != ORC_PROTO_NORDIC)
+        return -1;
+    for (int m = 0; m < (cfg->proto == ORC_PROTO_SLOTS ? cfg->n_slots : 0); ++m)
         if (cfg->minute_of_day[m] - cfg->jitter < 0 || cfg->minute_of_day[m] + cfg->jitter >= 1440)
             return -1;
     if (cfg->integrator == ORC_INT_RK4 && (cfg->sigma_q1 != 0.0 || cfg->cgm_var != 0.0 || cfg->rk4_sub < 1))

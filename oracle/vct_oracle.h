@@ -29,6 +29,9 @@ extern "C" {
 #define ORC_NX 11          /* model states                                     */
 #define ORC_NPOUT 19       /* 15 parameters + u_b, I*, attempts, status        */
 #define ORC_MAX_SLOTS 4
+#define ORC_MAX_DAY_MEALS 8   /* meals of one day, either protocol */
+#define ORC_PROTO_SLOTS  0
+#define ORC_PROTO_NORDIC 1
 
 /* controller kinds */
 #define ORC_CTRL_OPEN 0    /* constant u = u_rel * u_b (test mode)              */
@@ -65,6 +68,8 @@ typedef struct {
     double   carbs_sd[ORC_MAX_SLOTS];
     double   prob[ORC_MAX_SLOTS];
     int32_t  jitter;            /* onset jitter uniform on the integers [-jitter, jitter] min */
+    int32_t  proto;             /* ORC_PROTO_SLOTS: the slots above; ORC_PROTO_NORDIC: Sec. II-B */
+    double   meal_cv;           /* ORC_PROTO_NORDIC: relative SD of each meal's carbohydrate */
     /* (5) controller */
     int32_t  ctrl_kind;
     double   setpoint;          /* mmol/L */
@@ -161,6 +166,13 @@ void     orc_rhs(const orc_config *cfg, const double p[ORC_NP], const double x[O
 /* Test hooks: the meal draws of one (patient, day) -> [n_slots][4] = (present, sample index
    in the day, carbs g, jitter min); a PID run over a scripted measurement sequence. */
 void     orc_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out);
+/* Northern-European protocol (Sec. II-B, Tables I and II): out[0..2] = season (0 winter,
+ * 1 spring, 2 summer, 3 autumn), week type (0 standard, 1 active, 2 vacation) and day type
+ * (0 standard, 1 active, 2 movie night, 3 late night) of a patient's day. */
+void     orc_nordic_day(const orc_config *cfg, uint32_t patient, int32_t day, int32_t *out);
+/* The meals of one (patient, day) under either protocol, in time order: returns their
+ * number n and writes out[n][3] = (sample index within the day, carbs g, intake mmol/min). */
+int      orc_day_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out);
 void     orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *y, double *u, double *integ);
 
 /* Linear MPC. Jacobian of the drift at (x, u, D = 0); B_c = df/du, E_c = df/dD. */

@@ -125,12 +125,24 @@ vct_status vct_create_population(const vct_population_desc *d, void *params_dev,
 
 void vct_destroy_population(vct_population *p) { delete p; }
 
+static_assert(vct::kProtoSlots == VCT_PROTO_SLOTS && vct::kProtoNordic == VCT_PROTO_NORDIC, "protocol kinds");
+
 static vct_status check_protocol(const vct_protocol *pr, int32_t ts)
 {
     if (pr->n_slots < 0 || pr->n_slots > VCT_MAX_SLOTS)
         return fail(VCT_EINVAL, "protocol: n_slots %d out of [0, %d]", pr->n_slots, VCT_MAX_SLOTS);
     if (pr->jitter_min < 0 || pr->jitter_min > 120)
         return fail(VCT_EINVAL, "protocol: jitter_min %d out of [0, 120]", pr->jitter_min);
+    if (pr->kind == VCT_PROTO_NORDIC) {
+        // the closest meals are 90 min apart (21:00, 22:30)
+        if (pr->jitter_min > 40 || 2 * pr->jitter_min + ts > 90)
+            return fail(VCT_EINVAL, "protocol: jitter_min %d too large for the Northern-European day", pr->jitter_min);
+        if (!(pr->meal_cv >= 0.0 && pr->meal_cv <= 1.0))
+            return fail(VCT_EINVAL, "protocol: meal_cv outside [0, 1]");
+        return VCT_OK;
+    }
+    if (pr->kind != VCT_PROTO_SLOTS)
+        return fail(VCT_EINVAL, "protocol: kind %d unknown", pr->kind);
     for (int m = 0; m < pr->n_slots; ++m) {
         const int lo = pr->minute_of_day[m] - pr->jitter_min, hi = pr->minute_of_day[m] + pr->jitter_min;
         if (lo < 0 || hi >= 1440)
@@ -206,7 +218,9 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.n_days = sim->n_days;
     a.kday = 1440 / sim->ts_min;
     split_key(sim->noise_seed, pop->arm_id, a.key0, a.key1);
-    a.n_slots = pr->n_slots;
+    a.proto = pr->kind;
+    a.meal_cv = pr->meal_cv;
+    a.n_slots = pr->kind == VCT_PROTO_NORDIC ? 0 : pr->n_slots;
     for (int m = 0; m < VCT_MAX_SLOTS; ++m) {
         a.minute_of_day[m] = pr->minute_of_day[m];
         a.carbs_mean[m] = pr->carbs_mean_g[m];

@@ -17,6 +17,8 @@ struct PopArgs {
     double g_target;
 };
 
+enum : int32_t { kProtoSlots = 0, kProtoNordic = 1 };   // VCT_PROTO_SLOTS, VCT_PROTO_NORDIC
+
 struct SimArgs {
     const double *params; // SoA [kRows][n], FP64
     int64_t n;
@@ -24,6 +26,8 @@ struct SimArgs {
     int32_t n_days, kday; // samples per day
     uint32_t key0, key1;  // simulation key (meals + noise)
     // protocol
+    int32_t proto;            // kProtoSlots or kProtoNordic
+    double meal_cv;           // NORDIC: relative SD of each meal's carbohydrate
     int32_t n_slots;
     int32_t minute_of_day[4];
     double carbs_mean[4], carbs_sd[4], prob[4];

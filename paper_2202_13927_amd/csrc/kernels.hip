@@ -93,22 +93,38 @@ hipError_t launch_population(const PopArgs &a, hipStream_t s)
 enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2, kCtrlMlp = 3 };
 enum { kOutTraj = 1, kOutRecord = 2 };   // optional per-sample outputs (template bits)
 
-// Meals of one (patient, day): Philox block (day, patient, MEAL, slot) gives
-// carbs = max(0, mean + sd z) (cosine normal of u0, u1), integer jitter
-// floor(u2 (2J + 1)) - J and presence u3 < prob. The present meals are returned in
-// slot order in (k0..k3, r0..r3): sample index within the day and the held glucose
-// intake rate (mmol/min); absent entries have k = -1. The normal is drawn in the
-// kernel's precision; jitter and presence are exact integer tests (u3 < prob is
-// (2m + 1) < ceil(prob 2^24), precomputed on the host).
+// Meals of one (patient, day) as a queue in time order: sample index within the day and
+// the held glucose intake rate (mmol/min) of up to six meals; unused entries have k = -1.
 template <typename R> struct DayMeals {
-    int32_t k0, k1, k2, k3;
-    R r0, r1, r2, r3;
+    int32_t k0, k1, k2, k3, k4, k5;
+    R r0, r1, r2, r3, r4, r5;
 };
 
 template <typename R>
-__device__ __forceinline__ DayMeals<R> draw_meals(const SimArgs &a, uint32_t pid, int32_t day)
+__device__ __forceinline__ void push_front(DayMeals<R> &d, int32_t k, R r)
 {
-    DayMeals<R> d{-1, -1, -1, -1, R(0), R(0), R(0), R(0)};
+    d.k5 = d.k4; d.r5 = d.r4;
+    d.k4 = d.k3; d.r4 = d.r3;
+    d.k3 = d.k2; d.r3 = d.r2;
+    d.k2 = d.k1; d.r2 = d.r1;
+    d.k1 = d.k0; d.r1 = d.r0;
+    d.k0 = k;
+    d.r0 = r;
+}
+
+// Onset jitter from a Philox word: floor(u (2J + 1)) - J minutes, u the word's top 24 bits.
+__device__ __forceinline__ int32_t meal_jitter(uint32_t x, int32_t J)
+{
+    return (int32_t)(((uint64_t)((x >> 8) | 1u) * (uint64_t)(2 * J + 1)) >> 24) - J;
+}
+
+// Slot protocol: Philox block (day, patient, MEAL, slot) gives carbs = max(0, mean + sd z)
+// (cosine normal of u0, u1), the jitter from u2 and presence u3 < prob. The normal is
+// drawn in the kernel's precision; jitter and presence are exact integer tests (u3 < prob
+// is (2m + 1) < ceil(prob 2^24), precomputed on the host).
+template <typename R>
+__device__ __forceinline__ void draw_slot_meals(const SimArgs &a, uint32_t pid, int32_t day, DayMeals<R> &d)
+{
 #pragma unroll
     for (int m = 3; m >= 0; --m) {
         if (m < a.n_slots) {
@@ -118,16 +134,140 @@ __device__ __forceinline__ DayMeals<R> draw_meals(const SimArgs &a, uint32_t pid
                 R z0, z1;
                 Rng<R>::box_muller(Rng<R>::uniform(r.x), Rng<R>::uniform(r.y), z0, z1);
                 const R carbs = vmax(R(0), R(a.carbs_mean[m]) + R(a.carbs_sd[m]) * z0);
-                const uint32_t odd2 = (r.z >> 8) | 1u;
-                const int32_t jit = (int32_t)(((uint64_t)odd2 * (uint64_t)(2 * a.jitter + 1)) >> 24) - a.jitter;
-                d.k3 = d.k2; d.r3 = d.r2;
-                d.k2 = d.k1; d.r2 = d.r1;
-                d.k1 = d.k0; d.r1 = d.r0;
-                d.k0 = (a.minute_of_day[m] + jit) / a.ts_min;
-                d.r0 = carbs * R(a.rate_per_g);
+                push_front(d, (a.minute_of_day[m] + meal_jitter(r.z, a.jitter)) / a.ts_min, carbs * R(a.rate_per_g));
             }
         }
     }
+}
+
+// ------------------------------------------------ Northern-European protocol ----
+// Sec. II-B, Table I: a year of four 13-week seasons (winter, spring, summer, autumn) made of
+// standard, active and vacation weeks; each week of standard days, active days, days with a
+// movie night and days with a late night. Table II: meal sizes per kg of body weight.
+// Each patient's year is a random arrangement of these compositions: at day d the season's
+// 13 week types are shuffled (Fisher-Yates, i = 12..1 swapping slots i and
+// floor(u_i (i + 1)), u_i the top 24 bits of word 12 - i of the Philox blocks
+// (d / 91, patient, PROTO, 0..2)) from the order standard, active, vacation; the week's 7
+// day types likewise (i = 6..1, blocks (d / 7, patient, PROTO, 4..5)) from the order
+// standard, active, movie, late. Meals in time order (the figure with the clock times is
+// not in the text; these are this implementation's choices): breakfast 07:00 small,
+// snack 10:00 in spring and summer, lunch 12:00 medium, snack 15:00 in winter and autumn,
+// dinner 18:00 large in winter and autumn and medium in spring and summer, one evening
+// snack 21:00 on movie and late nights and a second at 22:30 on late nights. Vacation
+// weeks ("they eat more") move breakfast, lunch and dinner one size up (large stays
+// large). An active day has an exercise session, which this model has no input for: its
+// meals are the standard day's. Meal kind q (0 breakfast, 1 morning snack, 2 lunch,
+// 3 afternoon snack, 4 dinner, 5 and 6 evening snacks) draws Philox block (day, patient,
+// MEAL, q): carbs = max(0, g BW (1 + meal_cv z)) with z the cosine normal of u0, u1, and
+// the onset jitter from u2 as for the slot protocol.
+enum : uint32_t { kTagProto = 8u };
+constexpr int kDaysPerSeason = 91;
+constexpr double kGramsLarge = 1.29, kGramsMedium = 0.86, kGramsSmall = 0.57, kGramsSnack = 0.29;
+
+// Fisher-Yates on n 2-bit entries packed in a word, with 24-bit uniforms from the words w.
+template <int N>
+__device__ __forceinline__ uint32_t shuffle2(uint32_t arr, const uint32_t *w)
+{
+#pragma unroll
+    for (int i = N - 1; i >= 1; --i) {
+        const uint32_t j = (uint32_t)(((uint64_t)(w[N - 1 - i] >> 8) * (uint64_t)(i + 1)) >> 24);
+        const uint32_t x = ((arr >> (2 * i)) ^ (arr >> (2 * j))) & 3u;
+        arr ^= (x << (2 * i)) | (x << (2 * j));
+    }
+    return arr;
+}
+
+// n entries of value v appended from position p of a packed 2-bit array.
+__device__ __forceinline__ uint32_t fill2(uint32_t arr, int &p, int n, uint32_t v)
+{
+    for (int e = 0; e < n; ++e, ++p)
+        arr |= v << (2 * p);
+    return arr;
+}
+
+// Season (0 winter .. 3 autumn), week type (0 standard, 1 active, 2 vacation) and day type
+// (0 standard, 1 active, 2 movie night, 3 late night) of day d of a patient.
+__device__ __forceinline__ void nordic_day(const SimArgs &a, uint32_t pid, int32_t d, int &season, int &wtype,
+                                           int &dtype)
+{
+    season = (d / kDaysPerSeason) % 4;
+    const int wk = (d % kDaysPerSeason) / 7;
+    {   // Table I, top: standard / active / vacation weeks per season
+        const int ns = season == 3 ? 9 : season == 2 ? 7 : 6;
+        const int na = season == 1 ? 6 : season == 0 ? 4 : 3;
+        const int nv = 13 - ns - na;
+        int p = 0;
+        uint32_t arr = fill2(0u, p, ns, 0u);
+        arr = fill2(arr, p, na, 1u);
+        arr = fill2(arr, p, nv, 2u);
+        uint32_t w[12];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            const U4 r = philox4x32_10((uint32_t)(d / kDaysPerSeason), pid, kTagProto, (uint32_t)b, a.key0, a.key1);
+            w[4 * b] = r.x; w[4 * b + 1] = r.y; w[4 * b + 2] = r.z; w[4 * b + 3] = r.w;
+        }
+        wtype = (int)((shuffle2<13>(arr, w) >> (2 * wk)) & 3u);
+    }
+    {   // Table I, bottom: standard / active / movie / late days per week type
+        const int n0 = wtype == 2 ? 5 : wtype == 1 ? 3 : 4;
+        const int n1 = wtype == 2 ? 0 : wtype == 1 ? 3 : 1;
+        const int n2 = wtype == 2 ? 0 : 1;
+        const int n3 = 7 - n0 - n1 - n2;
+        int p = 0;
+        uint32_t arr = fill2(0u, p, n0, 0u);
+        arr = fill2(arr, p, n1, 1u);
+        arr = fill2(arr, p, n2, 2u);
+        arr = fill2(arr, p, n3, 3u);
+        uint32_t w[8];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            const U4 r = philox4x32_10((uint32_t)(d / 7), pid, kTagProto, (uint32_t)(4 + b), a.key0, a.key1);
+            w[4 * b] = r.x; w[4 * b + 1] = r.y; w[4 * b + 2] = r.z; w[4 * b + 3] = r.w;
+        }
+        dtype = (int)((shuffle2<7>(arr, w) >> (2 * (d % 7))) & 3u);
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void draw_nordic_meals(const SimArgs &a, uint32_t pid, int32_t day, R bw,
+                                                  DayMeals<R> &d)
+{
+    int season, wtype, dtype;
+    nordic_day(a, pid, day, season, wtype, dtype);
+    const bool cold = season == 0 || season == 3, vac = wtype == 2;
+    // meal kinds 6..0 pushed to the front (the queue ends in time order)
+#pragma unroll
+    for (int q = 6; q >= 0; --q) {
+        double g;
+        int minute;
+        bool on;
+        switch (q) {
+        case 0: g = vac ? kGramsMedium : kGramsSmall; minute = 420; on = true; break;
+        case 1: g = kGramsSnack; minute = 600; on = !cold; break;
+        case 2: g = vac ? kGramsLarge : kGramsMedium; minute = 720; on = true; break;
+        case 3: g = kGramsSnack; minute = 900; on = cold; break;
+        case 4: g = (cold || vac) ? kGramsLarge : kGramsMedium; minute = 1080; on = true; break;
+        case 5: g = kGramsSnack; minute = 1260; on = dtype >= 2; break;
+        default: g = kGramsSnack; minute = 1350; on = dtype == 3; break;
+        }
+        if (on) {
+            const U4 r = philox4x32_10((uint32_t)day, pid, kTagMeal, (uint32_t)q, a.key0, a.key1);
+            R z0, z1;
+            Rng<R>::box_muller(Rng<R>::uniform(r.x), Rng<R>::uniform(r.y), z0, z1);
+            const R carbs = vmax(R(0), R(g) * bw * (R(1) + R(a.meal_cv) * z0));
+            push_front(d, (minute + meal_jitter(r.z, a.jitter)) / a.ts_min, carbs * R(a.rate_per_g));
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ DayMeals<R> draw_meals(const SimArgs &a, uint32_t pid, int32_t day, R bw)
+{
+    DayMeals<R> d{-1, -1, -1, -1, -1, -1, R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (a.proto == kProtoNordic)
+        draw_nordic_meals<R>(a, pid, day, bw, d);
+    else
+        draw_slot_meals<R>(a, pid, day, d);
     return d;
 }
 
@@ -403,7 +543,9 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         ml.k0 = ml.k1; ml.r0 = ml.r1;
         ml.k1 = ml.k2; ml.r1 = ml.r2;
         ml.k2 = ml.k3; ml.r2 = ml.r3;
-        ml.k3 = -1;
+        ml.k3 = ml.k4; ml.r3 = ml.r4;
+        ml.k4 = ml.k5; ml.r4 = ml.r5;
+        ml.k5 = -1;
     }
 
     constexpr bool kFeat = CTRL == kCtrlMlp || (OUT & kOutRecord);
@@ -587,9 +729,10 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     cc.sig_sqh = R(a.sig_sqh);
     cc.sqrt_r = R(a.sqrt_r);
     cc.ts_d = (double)a.ts_min;
+    const R bw = R(p[kBW]);   // body weight: the Northern-European protocol's meal sizes are per kg
 
     for (int32_t day = 0; day < a.n_days; ++day) {
-        DayMeals<R> ml = draw_meals<R>(a, pid, day);
+        DayMeals<R> ml = draw_meals<R>(a, pid, day, bw);
         for (int32_t kk = 0; kk < a.kday; kk += 2) {
             const int32_t k = day * a.kday + kk;
             // normals of the sample pair (k, k+1): blocks (k/2, patient, DIFF, 0..2), normals

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libvct.so")
 VCT_NP, VCT_NX, VCT_NPARAM_ROWS, VCT_MAX_SLOTS = 15, 11, 19, 4
 VCT_OK, VCT_EINVAL, VCT_ENOMEM, VCT_EHIP, VCT_ESTATE, VCT_ENOTSUP = 0, -1, -2, -3, -4, -5
 VCT_CTRL_OPEN, VCT_CTRL_PID, VCT_CTRL_MPC, VCT_CTRL_MLP = 0, 1, 2, 3
+VCT_PROTO_SLOTS, VCT_PROTO_NORDIC = 0, 1
 VCT_FP64, VCT_FP32 = 0, 1
 VCT_POP_MIN_BASAL = 1
 VCT_MLP_IN, VCT_MLP_PARAMS, VCT_MLP_BLOB_BYTES = 12, 10448, 21568
@@ -42,7 +43,8 @@ class vct_population_desc(C.Structure):
 class vct_protocol(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("minute_of_day", C.c_int32 * VCT_MAX_SLOTS),
                 ("carbs_mean_g", C.c_double * VCT_MAX_SLOTS), ("carbs_sd_g", C.c_double * VCT_MAX_SLOTS),
-                ("prob", C.c_double * VCT_MAX_SLOTS), ("jitter_min", C.c_int32)]
+                ("prob", C.c_double * VCT_MAX_SLOTS), ("jitter_min", C.c_int32), ("kind", C.c_int32),
+                ("meal_cv", C.c_double)]
 
 
 class vct_controller(C.Structure):
@@ -311,6 +313,8 @@ def protocol(trial: dict) -> vct_protocol:
         p.carbs_sd_g[m] = float(trial["carbs_sd"][m])
         p.prob[m] = float(trial["prob"][m])
     p.jitter_min = int(trial["jitter"])
+    p.kind = int(trial.get("proto", VCT_PROTO_SLOTS))
+    p.meal_cv = float(trial.get("meal_cv", 0.0))
     return p
 
 

@@ -26,6 +26,7 @@ NOMINAL = (0.0161, 0.0097, 0.066, 0.006, 0.06, 0.03, 51.2e-4, 8.2e-4, 520e-4,
 STATE_NAMES = ("D1", "D2", "S1", "S2", "I", "x1", "x2", "x3", "Q1", "Q2", "GI")
 
 CTRL_OPEN, CTRL_PID, CTRL_MPC, CTRL_MLP = 0, 1, 2, 3
+PROTO_SLOTS, PROTO_NORDIC = 0, 1
 FP64, FP32 = 0, 1
 
 MG_PER_DL_PER_MMOL = 18.0
@@ -52,6 +53,10 @@ def base_trial() -> dict:
         "carbs_sd": [10.0, 10.0, 10.0, 5.0],
         "prob": [1.0, 1.0, 1.0, 0.0],
         "jitter": 30,
+        # protocol kind: PROTO_SLOTS (the slots above) or PROTO_NORDIC (the paper's
+        # Northern-European year, meal sizes per kg; meal_cv = relative SD of each meal)
+        "proto": PROTO_SLOTS,
+        "meal_cv": 0.0,
         # (5) controller: PID on CGM, gains relative to the basal rate
         "ctrl_kind": CTRL_PID,
         "setpoint": 6.0,
@@ -107,6 +112,15 @@ def c3_paper_scale() -> dict:
     """1,000,000 patients x 364 days, plus a 21:00 snack with probability 0.2, N(20, 5) g."""
     return with_(base_trial(), n_patients=1_000_000, n_days=364, pop_seed=2, noise_seed=2, precision=FP32,
                  n_slots=4, prob=[1.0, 1.0, 1.0, 0.2])
+
+
+def nordic_year(seed: int = 6) -> dict:
+    """The paper's Northern-European protocol (Sec. II-B, Tables I-II) for 1,000,000 patients
+    x 364 days (one year: four 13-week seasons), PID, FP32: each patient's own arrangement of
+    the season's weeks and the week's days, BW-scaled meals with a 10 % relative SD and
+    +-30 min onset jitter."""
+    return with_(base_trial(), n_patients=1_000_000, n_days=364, pop_seed=seed, noise_seed=seed, precision=FP32,
+                 proto=PROTO_NORDIC, meal_cv=0.1)
 
 
 def c5_mpc(seed: int = 5) -> dict:

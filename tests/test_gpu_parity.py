@@ -213,3 +213,49 @@ def test_population_slices_equal_whole(gpu):
         parts.append(gpu.to_host(b))
     for k in ("bins", "events", "sum_g", "min_g", "argmin_k", "sum_u", "status", "params"):
         assert np.array_equal(whole[k], np.concatenate([p[k] for p in parts])), k
+
+
+def test_nordic_fp64_matches_oracle(gpu, orc):
+    """The paper's Northern-European protocol over a whole year (all four seasons, vacation
+    weeks, movie and late nights), FP64 state: the GPU's counts equal the oracle's on every
+    patient with no sample near a range edge, trajectories agree to rounding."""
+    t = W.with_(W.c1_fp64_pid(), proto=W.PROTO_NORDIC, meal_cv=0.1, n_patients=130, n_days=364)
+    s, g = run_gpu(gpu, t, traj=4)
+    o = orc.simulate(t, n_traj=4, threads=THREADS, guard_rel=1e-9)
+    assert np.array_equal(g["status"], o["status"])
+    ok = o["n_near"] == 0
+    assert ok.mean() > 0.95
+    for k in ("bins", "events", "argmin_k"):
+        assert np.array_equal(g[k][ok], o[k][ok]), k
+    assert np.allclose(g["sum_g"], o["sum_g"], rtol=1e-9)
+    rel = np.abs(g["traj_g"] - o["traj_g"]) / np.abs(o["traj_g"])
+    _say("Nordic FP64 max rel traj error", rel.max())
+    assert rel.max() < 1e-4
+
+
+def test_nordic_fp32_stochastic(gpu, orc):
+    """FP32 state on the same Philox stream: population TIR within 0.1 pp of the oracle."""
+    t = W.with_(W.nordic_year(), n_patients=2053, n_days=56)
+    s, g = run_gpu(gpu, t)
+    o = orc.simulate(t, threads=THREADS)
+    dtir = (g["bins"][:, 2].astype(np.int64) - o["bins"][:, 2]) / o["K"]
+    _say("Nordic FP32 per-patient |dTIR| max", np.abs(dtir).max(), "mean", dtir.mean())
+    assert abs(dtir.mean()) < 1e-3
+    assert np.mean(np.abs(dtir) <= 1e-3) > 0.95
+    assert np.array_equal(g["status"], o["status"])
+
+
+def test_nordic_rejects_bad_settings(gpu):
+    """Invalid protocol settings are refused before any device work."""
+    from paper_2202_13927_amd import vct
+    t = W.with_(W.c1_fp64_pid(), proto=W.PROTO_NORDIC, n_patients=64, n_days=1)
+    bufs = gpu.TrialBuffers(t)
+    pop = gpu.create_population(t, bufs)
+    try:
+        for bad in ({"jitter": 41}, {"meal_cv": -0.1}, {"meal_cv": 1.5}, {"proto": 7}):
+            with pytest.raises(vct.VctError) as e:
+                gpu.simulate(W.with_(t, **bad), pop, bufs)
+            assert e.value.code == vct.VCT_EINVAL, bad
+        gpu.simulate(W.with_(t, jitter=40, meal_cv=1.0), pop, bufs)    # the limits themselves are valid
+    finally:
+        vct.vct_destroy_population(pop)
