@@ -15,6 +15,9 @@ The JSON line also carries
 * batched -- the 64-arm heterogeneous PID trial in one persistent graph-captured launch;
 * nordic -- the paper's Northern-European protocol (Tables I-II) for 1,000,000 patients x
   364 days, PID, one simulation launch;
+* scenarios -- the paper's comparison of trial A (correct basal rate) and trial B (basal
+  rate underestimated by 50 %) on that protocol, the same 1,000,000 patients each, as two
+  arms of one batched launch: TIR and the distribution of the daily insulin per arm;
 * learned -- the learned controller against exact linear MPC on common random numbers
   (100,000 x 28 days by default, 1,000,000 x 364 days with --learned-full).
 """
@@ -132,6 +135,40 @@ def nordic_leg(stream) -> dict:
             "mean_bg_mmol": s["mean_bg"]}
 
 
+def scenarios_leg(stream) -> dict:
+    """Trial A vs trial B (Sec. IV-E) on the Northern-European year: two arms (same patients,
+    meals and noise; the controller's basal rate at 100 % and 50 %) in one batched launch."""
+    import torch
+    from paper_2202_13927_amd import trial as T, vct, workloads as W
+    a = W.nordic_year()
+    arms = [a, W.with_(a, basal_scale=0.5)]
+    bt = T.Batch(arms, stream=stream)
+    try:
+        bt.run(stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        bt.run(stream)
+        e1.record(stream)
+        stream.synchronize()
+        ms = e0.elapsed_time(e1)
+        out = {"workload": "trial A (basal correct) vs trial B (basal x 0.5), Northern-European protocol, "
+                           "1000000 patients x 364 days each, PID, FP32, one batched launch",
+               "ms": ms, "patient_days_per_s": bt.patient_days / ms * 1e3}
+        qs = torch.tensor([0.05, 0.25, 0.5, 0.75, 0.95], dtype=torch.float64, device=bt.bufs[0].metrics.device)
+        for name, t, b, s in zip(("A", "B"), arms, bt.bufs, bt.summaries(stream)):
+            sum_u = vct.metric_views(b.metrics, b.n)["sum_u"]
+            daily = sum_u / (1000.0 * t["n_days"])          # U per day
+            out[name] = {"mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"], "mean_bg_mmol": s["mean_bg"],
+                         "worst_min_g": s["worst_min_g"], "bins": s["bins"],
+                         "daily_insulin_u_quantiles": torch.quantile(daily, qs).tolist()}
+        log(f"[bench] scenarios: {ms:.1f} ms, TIR A {out['A']['mean_tir']:.4f} B {out['B']['mean_tir']:.4f}")
+        return out
+    finally:
+        bt.close()
+
+
 def learned_leg(full: bool) -> dict:
     """The learned controller against exact MPC on common random numbers: train on the MPC's
     recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
@@ -181,7 +218,8 @@ def main() -> int:
     ap.add_argument("--days", type=int, default=None, help="override the horizon")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-arm batched trial")
-    ap.add_argument("--no-nordic", action="store_true", help="skip the Northern-European protocol run")
+    ap.add_argument("--no-nordic", action="store_true",
+                    help="skip the Northern-European protocol run and the trial A vs B scenarios")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scales HBM byte counters)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-controller comparison")
@@ -279,6 +317,7 @@ def main() -> int:
         out["batched"] = batched(stream)
     if not args.no_nordic:
         out["nordic"] = nordic_leg(stream)
+        out["scenarios"] = scenarios_leg(stream)
     if not args.no_learned:
         out["learned"] = learned_leg(args.learned_full)
     if not args.no_cpu_baseline:

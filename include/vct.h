@@ -151,6 +151,9 @@ typedef struct {
     const void *mlp_dev;   /* VCT_CTRL_MLP: network blob (vct_mlp_blob_bytes), read-only */
     double  mlp_safe_g;    /* VCT_CTRL_MLP: the MPC acts when y_k < mlp_safe_g (mmol/L) ... */
     double  mlp_safe_out;  /*   ... and the network's output exceeds mlp_safe_out (u / u_b) */
+    double  basal_scale;   /* > 0: the controller's basal rate is basal_scale u_b (1 = correct;
+                              Sec. IV-E trial B: 0.5). It replaces u_b in the PID law and bound
+                              and in the open-loop rate; other values than 1 need PID or open loop */
 } vct_controller;
 
 /* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl
@@ -219,6 +222,7 @@ typedef struct {
     int32_t n_days;
     double  kp, ki, kd;       /* relative to u_b, as in vct_controller            */
     void   *metrics_dev;
+    double  basal_scale;      /* the arm's controller basal rate / u_b, as in vct_controller */
 } vct_arm;
 
 typedef struct vct_batch vct_batch;             /* opaque, owned by the library */

@@ -26,7 +26,7 @@ class OrcConfig(C.Structure):
         ("carbs_sd", C.c_double * MAX_SLOTS), ("prob", C.c_double * MAX_SLOTS), ("jitter", C.c_int32),
         ("proto", C.c_int32), ("meal_cv", C.c_double),
         ("ctrl_kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
-        ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double),
+        ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double), ("basal_scale", C.c_double),
         ("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("sigma_q1", C.c_double),
         ("cgm_var", C.c_double), ("noise_seed", C.c_uint64), ("integrator", C.c_int32), ("rk4_sub", C.c_int32),
         ("x0_offset", C.c_double * NX), ("guard_rel", C.c_double),
@@ -156,6 +156,7 @@ def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=N
         c.prob[m] = float(trial["prob"][m])
     c.jitter = int(trial["jitter"])
     c.proto = int(trial.get("proto", 0))
+    c.basal_scale = float(trial.get("basal_scale", 1.0))
     c.meal_cv = float(trial.get("meal_cv", 0.0))
     c.ctrl_kind = int(trial["ctrl_kind"])
     for k in ("setpoint", "kp", "ki", "kd", "umax_rel", "u_rel", "sigma_q1", "cgm_var"):

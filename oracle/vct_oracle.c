@@ -527,7 +527,8 @@ static void acc_sample(acc_t *a, double G, int32_t k, double guard)
 }
 
 /* ------------------------------------------------------------ controller ---- */
-/* PID on the CGM value, gains scaled by the patient's basal rate:
+/* PID on the CGM value, gains scaled by the controller's basal rate u_b (the patient's
+ * basal rate times basal_scale; a mis-set basal rate as in trial B of Sec. IV-E):
  *   e = y_k - ybar, u_unc = u_b + Kp e + Ki I_k + Kd (y_k - y_{k-1})/Ts (y_{-1} = y_0),
  *   u_k = min(max(u_unc, 0), u_max),
  *   I_{k+1} = I_k + e Ts only if 0 <= u_unc <= u_max (conditional integration).
@@ -1232,13 +1233,13 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
 
             double u;
             if (cfg->ctrl_kind == ORC_CTRL_PID)
-                u = pid_step(cfg, &pid, y, ub, &a.ctrl_margin);
+                u = pid_step(cfg, &pid, y, cfg->basal_scale * ub, &a.ctrl_margin);
             else if (cfg->ctrl_kind == ORC_CTRL_MPC)
                 u = mpc ? mpc_step(cfg, mpc, y, d) : NAN;
             else if (cfg->ctrl_kind == ORC_CTRL_MLP)
                 u = mpc ? mlp_step(cfg, mpc, f, y, d, &fallbacks, out->record ? &label : NULL) : NAN;
             else
-                u = cfg->u_rel * ub;
+                u = cfg->u_rel * (cfg->basal_scale * ub);
 
             if (use_inputs) {
                 for (int i = 5; i > 0; --i) yh[i] = yh[i - 1];
@@ -1313,6 +1314,8 @@ int orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_thre
     if (cfg->n_slots < 0 || cfg->n_slots > ORC_MAX_SLOTS || cfg->n_days < 0 || count < 0)
         return -1;
     if (cfg->proto != ORC_PROTO_SLOTS && cfg->proto != ORC_PROTO_NORDIC)
+        return -1;
+    if (!(cfg->basal_scale > 0.0))
         return -1;
     for (int m = 0; m < (cfg->proto == ORC_PROTO_SLOTS ? cfg->n_slots : 0); ++m)
         if (cfg->minute_of_day[m] - cfg->jitter < 0 || cfg->minute_of_day[m] + cfg->jitter >= 1440)

@@ -76,6 +76,7 @@ typedef struct {
     double   kp, ki, kd;        /* relative to u_b: u_b/(mmol/L), u_b/(mmol/L min), u_b min/(mmol/L) */
     double   umax_rel;          /* u_max = umax_rel * u_b */
     double   u_rel;             /* open-loop mode: u = u_rel * u_b */
+    double   basal_scale;       /* the controller's basal rate is basal_scale * u_b (PID, open loop) */
     /* (3) model + simulation settings */
     int32_t  n_days;
     int32_t  em_per_ctrl;       /* EM substeps per control interval */

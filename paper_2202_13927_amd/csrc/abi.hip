@@ -207,6 +207,10 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     if (!(std::isfinite(ctrl->setpoint) && std::isfinite(ctrl->kp) && std::isfinite(ctrl->ki) &&
           std::isfinite(ctrl->kd) && finite_pos(ctrl->umax_rel) && std::isfinite(ctrl->u_rel) && ctrl->u_rel >= 0))
         return fail(VCT_EINVAL, "controller gains must be finite, umax_rel > 0, u_rel >= 0");
+    if (!finite_pos(ctrl->basal_scale))
+        return fail(VCT_EINVAL, "basal_scale must be finite and > 0");
+    if (ctrl->basal_scale != 1.0 && ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_OPEN)
+        return fail(VCT_ENOTSUP, "basal_scale != 1 needs the PID or open-loop controller");
     vct_status st = check_protocol(pr, sim->ts_min);
     if (st != VCT_OK)
         return st;
@@ -240,6 +244,7 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.kd = ctrl->kd;
     a.umax_rel = ctrl->umax_rel;
     a.u_rel = ctrl->u_rel;
+    a.basal_scale = ctrl->basal_scale;
     a.mpc = uses_mpc ? ctrl->mpc_dev : nullptr;
     a.mpc_iters = ctrl->mpc_iters;
     a.mlp = ctrl->kind == VCT_CTRL_MLP ? (const unsigned char *)ctrl->mlp_dev : nullptr;
@@ -623,6 +628,7 @@ vct_status vct_batch_create(const vct_arm *arms, int32_t n_arms, const vct_proto
         c.kp = arms[q].kp;
         c.ki = arms[q].ki;
         c.kd = arms[q].kd;
+        c.basal_scale = arms[q].basal_scale;
         vct_status st = build_sim_args(arms[q].pop, pr, &c, &s, true, hargs[q]);
         if (st != VCT_OK) {
             g_err = "vct_batch_create: arm " + std::to_string(q) + ": " + g_err;

@@ -39,6 +39,7 @@ struct SimArgs {
     // controller
     int32_t ctrl;
     double setpoint, kp, ki, kd, umax_rel, u_rel;
+    double basal_scale;   // controller's basal rate / patient's (1 except PID / open loop)
     const void *mpc;      // per-patient MPC data (SoA [kMRows][n], working precision) or null
     int32_t mpc_iters;
     const unsigned char *mlp;   // learned-controller blob (VCT_CTRL_MLP) or null

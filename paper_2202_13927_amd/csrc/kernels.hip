@@ -717,13 +717,16 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     }
 
     CtrlConst<R> cc;   // gains relative to u_b
-    cc.kp = R(a.kp * ub_d);
-    cc.ki = R(a.ki * ub_d);
-    cc.kd_ts = R(a.kd * ub_d / (double)a.ts_min);
-    cc.umax = R(a.umax_rel * ub_d);
-    cc.ub = R(ub_d);
+    // the controller's own basal rate: the patient's, or a mis-set one (basal_scale != 1,
+    // PID and open loop only; Sec. IV-E trial B underestimates it by 50 %)
+    const double ubc = a.basal_scale * ub_d;
+    cc.kp = R(a.kp * ubc);
+    cc.ki = R(a.ki * ubc);
+    cc.kd_ts = R(a.kd * ubc / (double)a.ts_min);
+    cc.umax = R(a.umax_rel * ubc);
+    cc.ub = R(ubc);
     cc.sp = R(a.setpoint);
-    cc.u_open = R(a.u_rel * ub_d);
+    cc.u_open = R(a.u_rel * ubc);
     cc.ts = R(a.ts_min);
     cc.k_sig = Rng<R>::scaled_const(a.sig_sqh);
     cc.sig_sqh = R(a.sig_sqh);

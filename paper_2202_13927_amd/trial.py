@@ -64,6 +64,19 @@ def run(trial: dict, device="cuda", traj_patients: int = 0, stream=None, bufs: T
     return summary, bufs
 
 
+def replay_patient(trial: dict, patient: int, device="cuda", stream=None, mlp_blob=None) -> dict:
+    """Re-simulate patient `patient` (index within the trial) alone, with its trajectory.
+    Every random number is keyed by the global patient index, so the replay reproduces the
+    patient's run inside the whole population bit for bit (the paper keeps only the worst
+    simulations; here any one, e.g. the summary's worst_patient, is rebuilt on demand from
+    the counters). Returns the one-patient record of to_host with traj_g, traj_y, traj_u."""
+    t = dict(trial)
+    t["first_patient"] = int(trial.get("first_patient", 0)) + int(patient)
+    t["n_patients"] = 1
+    _, bufs = run(t, device, traj_patients=1, stream=stream, mlp_blob=mlp_blob)
+    return to_host(bufs)
+
+
 def to_host(bufs: TrialBuffers) -> dict:
     """Per-patient arrays (numpy) in the oracle's layout, for comparisons."""
     torch.cuda.synchronize()
@@ -109,7 +122,7 @@ class Batch:
         self.arms = arms
         self.bufs = [TrialBuffers(t, device) for t in arms]
         self.pops = [create_population(t, b, stream) for t, b in zip(arms, self.bufs)]
-        c_arms = [vct.arm(p, t["n_days"], t["kp"], t["ki"], t["kd"], b.metrics)
+        c_arms = [vct.arm(p, t["n_days"], t["kp"], t["ki"], t["kd"], b.metrics, t.get("basal_scale", 1.0))
                   for p, t, b in zip(self.pops, arms, self.bufs)]
         t0 = arms[0]
         sim = vct.sim_settings(t0, None)

@@ -51,7 +51,8 @@ class vct_controller(C.Structure):
     _fields_ = [("kind", C.c_int32), ("setpoint", C.c_double), ("kp", C.c_double), ("ki", C.c_double),
                 ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double), ("mpc_horizon", C.c_int32),
                 ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double), ("mpc_dev", C.c_void_p),
-                ("mlp_dev", C.c_void_p), ("mlp_safe_g", C.c_double), ("mlp_safe_out", C.c_double)]
+                ("mlp_dev", C.c_void_p), ("mlp_safe_g", C.c_double), ("mlp_safe_out", C.c_double),
+                ("basal_scale", C.c_double)]
 
 
 class vct_sim(C.Structure):
@@ -80,7 +81,7 @@ class vct_summary(C.Structure):
 
 class vct_arm(C.Structure):
     _fields_ = [("pop", C.c_void_p), ("n_days", C.c_int32), ("kp", C.c_double), ("ki", C.c_double),
-                ("kd", C.c_double), ("metrics_dev", C.c_void_p)]
+                ("kd", C.c_double), ("metrics_dev", C.c_void_p), ("basal_scale", C.c_double)]
 
 
 class vct_batch_stats(C.Structure):
@@ -328,6 +329,7 @@ def controller(trial: dict, mpc_dev=None, mlp_dev=None) -> vct_controller:
     c.mlp_dev = _ptr(mlp_dev)
     c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.0))
     c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
+    c.basal_scale = float(trial.get("basal_scale", 1.0))
     return c
 
 
@@ -346,12 +348,13 @@ def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None
     return s
 
 
-def arm(pop, n_days: int, kp: float, ki: float, kd: float, metrics_dev) -> vct_arm:
+def arm(pop, n_days: int, kp: float, ki: float, kd: float, metrics_dev, basal_scale: float = 1.0) -> vct_arm:
     a = vct_arm()
     a.pop = pop.value if isinstance(pop, C.c_void_p) else pop
     a.n_days = int(n_days)
     a.kp, a.ki, a.kd = float(kp), float(ki), float(kd)
     a.metrics_dev = _ptr(metrics_dev)
+    a.basal_scale = float(basal_scale)
     return a
 
 

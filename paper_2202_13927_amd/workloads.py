@@ -73,6 +73,8 @@ def base_trial() -> dict:
         # (mmol/L, level-2 hypoglycaemia) and the network asks for more than mlp_safe_out u_b
         "mlp_safe_g": 3.0,
         "mlp_safe_out": 1.0,
+        # the controller's basal rate relative to the patient's (Sec. IV-E trial B: 0.5)
+        "basal_scale": 1.0,
         # (3) model + simulation settings
         "n_days": 7,
         "em_per_ctrl": 5,

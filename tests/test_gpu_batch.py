@@ -130,3 +130,33 @@ def test_c4_full_sampled(T, orc):
         assert np.abs(dt).max() < 1e-2 and abs(dt.mean()) < 3e-3
     finally:
         bt.close()
+
+
+def test_trial_a_vs_b_arms(T, orc):
+    """The scenario comparison of Sec. IV-E as two arms of one batched launch: the same
+    patients, meals and noise (same population seed and arm id) under the Northern-European
+    protocol, trial B with the controller's basal rate at 50 %. Each arm equals its
+    single-arm launch bit for bit; FP64 counts equal the oracle's; trial B delivers less
+    insulin."""
+    base = W.with_(W.c1_fp64_pid(), proto=W.PROTO_NORDIC, meal_cv=0.1, n_patients=200, n_days=14, pop_seed=12,
+                   noise_seed=12)
+    arms = [base, W.with_(base, basal_scale=0.5)]
+    _say("[gpu] trial A vs B in one batched launch, 200 x 14 d FP64")
+    bt = T.Batch(arms, block=128)
+    try:
+        bt.run()
+        got = [T.to_host(b) for b in bt.bufs]
+    finally:
+        bt.close()
+    for t, g in zip(arms, got):
+        _, b = T.run(t)
+        one = T.to_host(b)
+        for k in KEYS:
+            assert np.array_equal(g[k], one[k]), k
+        o = orc.simulate(t, threads=THREADS, guard_rel=1e-9)
+        ok = o["n_near"] == 0
+        assert ok.mean() > 0.95
+        for k in ("bins", "events", "argmin_k"):
+            assert np.array_equal(g[k][ok], o[k][ok]), k
+        assert np.allclose(g["sum_u"], o["sum_u"], rtol=1e-9)
+    assert got[1]["sum_u"].sum() < got[0]["sum_u"].sum()

@@ -259,3 +259,43 @@ def test_nordic_rejects_bad_settings(gpu):
         gpu.simulate(W.with_(t, jitter=40, meal_cv=1.0), pop, bufs)    # the limits themselves are valid
     finally:
         vct.vct_destroy_population(pop)
+
+
+def test_worst_patient_replay(gpu):
+    """The worst-case patient of a population run, re-simulated alone from its counters,
+    reproduces its record bit for bit; its trajectory reaches min G at argmin_k, and the
+    range counts recomputed from the trajectory equal the streamed counts."""
+    t = W.with_(W.c2_fp32_pid(), n_patients=3000, n_days=3)
+    s, b = gpu.run(t)
+    whole = gpu.to_host(b)
+    w = s["worst_patient"]
+    _say("[gpu] replay of worst patient", w, "min G", s["worst_min_g"])
+    r = gpu.replay_patient(t, w)
+    for k in ("bins", "events", "sum_g", "min_g", "argmin_k", "sum_u", "status"):
+        assert np.array_equal(r[k][0], whole[k][w]), k
+    g = r["traj_g"][0]
+    assert g.min() == whole["min_g"][w] and int(np.argmin(g)) == whole["argmin_k"][w] == s["worst_k"]
+    g32 = g.astype(np.float32)
+    edges = [np.float32(3.0), np.float32(3.9), np.float32(10.0), np.float32(13.9)]
+    counts = [int((g32 < edges[0]).sum()), int(((g32 >= edges[0]) & (g32 < edges[1])).sum()),
+              int(((g32 >= edges[1]) & (g32 <= edges[2])).sum()), int(((g32 > edges[2]) & (g32 <= edges[3])).sum()),
+              int((g32 > edges[3]).sum())]
+    assert counts == [int(v) for v in whole["bins"][w]]
+
+
+def test_basal_scale_needs_pid_or_open_loop(gpu):
+    """basal_scale != 1 is refused for the MPC (before any device work)."""
+    from paper_2202_13927_amd import vct
+    t = W.with_(W.c5_mpc(), n_patients=64, n_days=1)
+    bufs = gpu.TrialBuffers(t)
+    pop = gpu.create_population(t, bufs)
+    try:
+        gpu.mpc_setup(t, pop, bufs)
+        with pytest.raises(vct.VctError) as e:
+            gpu.simulate(W.with_(t, basal_scale=0.5), pop, bufs)
+        assert e.value.code == vct.VCT_ENOTSUP
+        with pytest.raises(vct.VctError) as e:
+            gpu.simulate(W.with_(t, ctrl_kind=W.CTRL_PID, basal_scale=0.0), pop, bufs)
+        assert e.value.code == vct.VCT_EINVAL
+    finally:
+        vct.vct_destroy_population(pop)
