@@ -127,12 +127,32 @@ def nordic_leg(stream) -> dict:
         ms = e0.elapsed_time(e1)
     finally:
         vct.vct_destroy_population(pop)
+    # the same launch with the population BG per sample (mean, min, max over the patients)
+    bufs_p = T.TrialBuffers(t, popbg=True)
+    pop = T.create_population(t, bufs_p, stream)
+    try:
+        e2 = torch.cuda.Event(enable_timing=True)
+        e3 = torch.cuda.Event(enable_timing=True)
+        e2.record(stream)
+        T.simulate(t, pop, bufs_p, stream)
+        e3.record(stream)
+        stream.synchronize()
+        ms_p = e2.elapsed_time(e3)
+        curve = vct.popbg_decode(bufs_p.popbg, bufs_p.n, bufs_p.K)
+    finally:
+        vct.vct_destroy_population(pop)
     pd = t["n_patients"] * t["n_days"]
-    log(f"[bench] nordic: {ms:.1f} ms, mean TIR {s['mean_tir']:.4f}")
+    log(f"[bench] nordic: {ms:.1f} ms, mean TIR {s['mean_tir']:.4f}; with population BG per sample {ms_p:.1f} ms")
+    pm = curve["pop_mean"]
     return {"workload": "Northern-European protocol (Sec. II-B, Tables I-II), 1000000 patients x 364 days, PID, "
                         "FP32, meal size SD 10 %, onset jitter +-30 min", "patient_days": pd, "ms": ms,
             "patient_days_per_s": pd / ms * 1e3, "mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"],
-            "mean_bg_mmol": s["mean_bg"]}
+            "mean_bg_mmol": s["mean_bg"],
+            "population_bg_per_sample": {"ms": ms_p, "samples": int(bufs_p.K),
+                                         "mean_of_mean_curve": float(pm.mean()),
+                                         "mean_curve_range": [float(pm.min()), float(pm.max())],
+                                         "lowest": float(curve["pop_min"].min()),
+                                         "highest": float(curve["pop_max"].max())}}
 
 
 def scenarios_leg(stream) -> dict:

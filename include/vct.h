@@ -190,6 +190,9 @@ typedef struct {
     void    *traj_dev;
     float   *record_dev;
     int32_t *fallback_dev;
+    void    *popbg_dev;       /* optional (NULL = off): the population's BG as a function of
+                                 time, Sec. III-C, vct_popbg_bytes(n_days, ts_min) bytes; see
+                                 vct_popbg_bytes. Not with traj_dev or record_dev. */
 } vct_sim;
 
 /* Population summary (Sec. III-C indicators, Sec. IV-A ranges). Quantiles are nearest
@@ -260,6 +263,15 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
  * iterations). mpc_dev: caller buffer of vct_mpc_bytes(n, precision) bytes, SoA rows of
  * the working precision; sim->precision must equal the precision later simulated, and
  * ctrl->umax_rel / mpc_rho are baked in. */
+/* Population BG as a function of time (optional output of vct_simulate): for every sample
+ * k = 0..K-1, over the patients of the call,
+ *   int64  sum[K]  @0      sum of round(G 2^32) (G in mmol/L; exact, order-free integer sum:
+ *                          the mean is sum / (n 2^32));
+ *   uint64 min[K]  @8K     order-preserving key of the smallest G (as FP64):
+ *   uint64 max[K]  @16K    key = bits ^ (sign ? all ones : sign bit); G = the key inverted;
+ * vct_simulate writes all three (the buffer need not be initialised). Returns 24 K bytes,
+ * or 0 for invalid arguments. */
+size_t      vct_popbg_bytes(int32_t n_days, int32_t ts_min);
 size_t      vct_mpc_bytes(int64_t n_patients, int32_t precision);
 vct_status  vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, const vct_sim *sim, void *mpc_dev,
                           void *stream);

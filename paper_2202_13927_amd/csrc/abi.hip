@@ -65,6 +65,13 @@ size_t vct_population_bytes(int64_t n) { return n > 0 ? (size_t)n * VCT_NPARAM_R
 
 size_t vct_metrics_bytes(int64_t n) { return n > 0 ? (size_t)n * 64u : 0; }
 
+size_t vct_popbg_bytes(int32_t n_days, int32_t ts_min)
+{
+    if (n_days <= 0 || ts_min <= 0 || 1440 % ts_min != 0)
+        return 0;
+    return (size_t)3 * (size_t)n_days * (size_t)(1440 / ts_min) * sizeof(int64_t);
+}
+
 size_t vct_traj_bytes(int32_t traj_patients, int32_t n_days, int32_t ts_min)
 {
     if (traj_patients <= 0 || n_days <= 0 || ts_min <= 0 || 1440 % ts_min != 0)
@@ -183,6 +190,10 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     if (sim->traj_patients < 0 || sim->traj_patients > 64 || sim->traj_patients > pop->n ||
         (sim->traj_patients > 0 && !sim->traj_dev))
         return fail(VCT_EINVAL, "traj_patients %d invalid (0..min(64, n), buffer required)", sim->traj_patients);
+    if (sim->popbg_dev && (sim->traj_patients > 0 || sim->record_dev))
+        return fail(VCT_EINVAL, "popbg_dev cannot be combined with traj_dev or record_dev");
+    if (sim->popbg_dev && ((uintptr_t)sim->popbg_dev % 8 != 0))
+        return fail(VCT_EINVAL, "popbg_dev must be 8-byte aligned");
     const int64_t K = (int64_t)sim->n_days * (1440 / sim->ts_min);
     if (K >= ((int64_t)1 << 31))
         return fail(VCT_EINVAL, "horizon too long");
@@ -270,6 +281,9 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.n_traj = sim->traj_patients;
     a.traj = sim->traj_patients > 0 ? (double *)sim->traj_dev : nullptr;
     a.K = K;
+    a.pop_sum = (int64_t *)sim->popbg_dev;
+    a.pop_min = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + K : nullptr;
+    a.pop_max = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 2 * K : nullptr;
     return VCT_OK;
 }
 
@@ -613,8 +627,8 @@ vct_status vct_batch_create(const vct_arm *arms, int32_t n_arms, const vct_proto
         return fail(VCT_EINVAL, "vct_batch_create: null argument");
     if (ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_OPEN)
         return fail(VCT_ENOTSUP, "vct_batch_create: batched arms run the PID or open-loop controller");
-    if (sim->record_dev || sim->fallback_dev)
-        return fail(VCT_EINVAL, "vct_batch_create: record_dev / fallback_dev are per-population outputs");
+    if (sim->record_dev || sim->fallback_dev || sim->popbg_dev)
+        return fail(VCT_EINVAL, "vct_batch_create: record_dev / fallback_dev / popbg_dev are per-population outputs");
     std::vector<vct::SimArgs> hargs(n_arms);
     for (int32_t q = 0; q < n_arms; ++q) {
         if (!arms[q].pop)

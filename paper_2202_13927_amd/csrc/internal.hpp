@@ -59,6 +59,8 @@ struct SimArgs {
     int64_t out_stride;   // n of the metrics buffer (row stride of bins/events)
     int32_t n_traj;
     double *traj;         // [3][n_traj][K] or null
+    int64_t *pop_sum;     // [K] sum of round(G 2^32) over the patients, or null
+    uint64_t *pop_min, *pop_max;   // [K] order-preserving keys of min / max G
     int64_t K;
 };
 

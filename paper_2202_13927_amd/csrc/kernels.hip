@@ -91,7 +91,45 @@ hipError_t launch_population(const PopArgs &a, hipStream_t s)
 
 // ---------------------------------------------------------------- simulation ----
 enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2, kCtrlMlp = 3 };
-enum { kOutTraj = 1, kOutRecord = 2 };   // optional per-sample outputs (template bits)
+enum { kOutTraj = 1, kOutRecord = 2, kOutPop = 4 };   // optional per-sample outputs (template bits)
+
+// Population BG as a function of time (Sec. III-C: mean, minimum and maximum BG over the
+// patients at every sample): each wave reduces its live lanes' G(t_k) -- the sum of
+// round(G 2^32) as a 64-bit integer (exact, so the total does not depend on the order of
+// the atomics) and order-preserving keys of the FP64 value for min and max -- and one lane
+// adds them with three 64-bit atomics. All 64 lanes of the wave must be active.
+__device__ __forceinline__ unsigned long long order_key(double g)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(g);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ void pop_accumulate(const SimArgs &a, int32_t k, double g, bool live)
+{
+    long long q = live ? __double2ll_rn(g * 4294967296.0) : 0ll;
+    unsigned long long mn = live ? order_key(g) : ~0ull, mx = live ? order_key(g) : 0ull;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        q += __shfl_xor(q, off);
+        const unsigned long long omn = __shfl_xor(mn, off), omx = __shfl_xor(mx, off);
+        mn = omn < mn ? omn : mn;
+        mx = omx > mx ? omx : mx;
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicAdd((unsigned long long *)&a.pop_sum[k], (unsigned long long)q);
+        atomicMin((unsigned long long *)&a.pop_min[k], mn);
+        atomicMax((unsigned long long *)&a.pop_max[k], mx);
+    }
+}
+
+__global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, int64_t K)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        sum[i] = 0;
+        mn[i] = ~0ull;
+        mx[i] = 0ull;
+    }
+}
 
 // Meals of one (patient, day) as a queue in time order: sample index within the day and
 // the held glucose intake rate (mmol/min) of up to six meals; unused entries have k = -1.
@@ -517,6 +555,8 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
 {
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
+    if (OUT & kOutPop)
+        pop_accumulate(a, k, (double)G, live);
     L.c30 += G >= R(3.0);
     L.c39 += G >= R(3.9);
     L.c100 += G > R(10.0);
@@ -796,8 +836,16 @@ template <typename R, int CTRL, bool NOISY, int OUT>
 __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j < a.n)
+    if (OUT & kOutPop) {
+        // the population reduction needs every lane of a wave: lanes past the last patient
+        // replay it and write nothing; a wave wholly past it exits
+        if ((j & ~(int64_t)63) >= a.n)
+            return;
+        const bool live = j < a.n;
+        run_patient<R, CTRL, NOISY, OUT>(a, live ? j : a.n - 1, live, PolicyShared{});
+    } else if (j < a.n) {
         run_patient<R, CTRL, NOISY, OUT>(a, j, true, PolicyShared{});
+    }
 }
 
 // The learned controller: the same per-patient loop, with the network evaluated by each
@@ -1100,6 +1148,11 @@ static void launch_sim_n(const SimArgs &a, hipStream_t s)
 {
     const bool traj = a.traj != nullptr && a.n_traj > 0;
     const bool rec = a.record != nullptr;
+    if (a.pop_sum) {   // not combined with traj / record (checked by the ABI)
+        hipLaunchKernelGGL(popbg_init_kernel, dim3(256), dim3(256), 0, s, a.pop_sum, a.pop_min, a.pop_max, a.K);
+        launch_sim_o<R, CTRL, NOISY, kOutPop>(a, s);
+        return;
+    }
     if (CTRL == kCtrlMpc || CTRL == kCtrlMlp) {
         if (rec) {
             if (traj)

@@ -12,7 +12,7 @@ from .workloads import samples_per_day
 class TrialBuffers:
     """Caller-owned device buffers of one trial (the library only borrows them)."""
 
-    def __init__(self, trial: dict, device="cuda", traj_patients: int = 0):
+    def __init__(self, trial: dict, device="cuda", traj_patients: int = 0, popbg: bool = False):
         n = int(trial["n_patients"])
         self.n = n
         self.K = int(trial["n_days"]) * samples_per_day(trial)
@@ -24,6 +24,10 @@ class TrialBuffers:
         self.mpc = None
         if int(trial["ctrl_kind"]) in (vct.VCT_CTRL_MPC, vct.VCT_CTRL_MLP):
             self.mpc = torch.empty(vct.vct_mpc_bytes(n, int(trial["precision"])), dtype=torch.uint8, device=device)
+        self.popbg = None      # optional int64 [3][K]: population BG per sample (sum, min, max keys)
+        if popbg:
+            self.popbg = torch.empty(vct.vct_popbg_bytes(int(trial["n_days"]), int(trial["ts_min"])) // 8,
+                                     dtype=torch.int64, device=device)
         self.record = None     # optional float [K][n][13] (MPC / learned controller)
         self.fallback = None   # optional int32 [n] (learned controller)
         if int(trial["ctrl_kind"]) == vct.VCT_CTRL_MLP:
@@ -40,7 +44,8 @@ def mpc_setup(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
 
 
 def simulate(trial: dict, pop, bufs: TrialBuffers, stream=None, mlp_blob=None) -> None:
-    sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj, bufs.record, bufs.fallback)
+    sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj, bufs.record, bufs.fallback,
+                           getattr(bufs, "popbg", None))
     vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial, bufs.mpc, mlp_blob), sim, stream)
 
 
@@ -93,6 +98,8 @@ def to_host(bufs: TrialBuffers) -> dict:
         out["record"] = bufs.record.view(bufs.K, bufs.n, 13).cpu().numpy()
     if bufs.fallback is not None:
         out["fallback"] = bufs.fallback.cpu().numpy()
+    if getattr(bufs, "popbg", None) is not None:
+        out.update(vct.popbg_decode(bufs.popbg, bufs.n, bufs.K))
     return out
 
 

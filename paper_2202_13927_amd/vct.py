@@ -59,7 +59,7 @@ class vct_sim(C.Structure):
     _fields_ = [("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("precision", C.c_int32),
                 ("sigma_q1", C.c_double), ("cgm_var", C.c_double), ("noise_seed", C.c_uint64),
                 ("metrics_dev", C.c_void_p), ("traj_patients", C.c_int32), ("traj_dev", C.c_void_p),
-                ("record_dev", C.c_void_p), ("fallback_dev", C.c_void_p)]
+                ("record_dev", C.c_void_p), ("fallback_dev", C.c_void_p), ("popbg_dev", C.c_void_p)]
 
 
 class vct_summary(C.Structure):
@@ -104,7 +104,7 @@ EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_met
            "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population",
            "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy", "vct_mpc_bytes",
            "vct_mpc_setup", "vct_mlp_blob_bytes", "vct_mlp_train_bytes", "vct_mlp_init", "vct_mlp_normalize",
-           "vct_mlp_train_step", "vct_mlp_forward")
+           "vct_mlp_train_step", "vct_mlp_forward", "vct_popbg_bytes")
 
 _lib = None
 
@@ -123,6 +123,8 @@ def lib() -> C.CDLL:
         L.vct_metrics_bytes.restype = C.c_size_t
         L.vct_traj_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
         L.vct_traj_bytes.restype = C.c_size_t
+        L.vct_popbg_bytes.argtypes = [C.c_int32, C.c_int32]
+        L.vct_popbg_bytes.restype = C.c_size_t
         L.vct_create_population.argtypes = [C.POINTER(vct_population_desc), C.c_void_p, C.c_void_p,
                                              C.POINTER(C.c_void_p)]
         L.vct_create_population.restype = C.c_int
@@ -205,6 +207,23 @@ def vct_metrics_bytes(n: int) -> int:
 
 def vct_traj_bytes(traj_patients: int, n_days: int, ts_min: int) -> int:
     return lib().vct_traj_bytes(traj_patients, n_days, ts_min)
+
+
+def vct_popbg_bytes(n_days: int, ts_min: int) -> int:
+    return lib().vct_popbg_bytes(n_days, ts_min)
+
+
+def popbg_decode(buf, n: int, K: int) -> dict:
+    """Population BG per sample from a vct_popbg_bytes buffer (torch int64 [3K]): mean, min,
+    max in mmol/L as numpy float64 arrays (the layout documented in vct.h)."""
+    import numpy as np
+    a = buf.view(3, K).cpu().numpy()
+    keys = a[1:].view(np.uint64)
+    neg = (keys >> np.uint64(63)) == 0
+    bits = np.where(neg, ~keys, keys ^ np.uint64(1 << 63))
+    mn, mx = bits.view(np.float64)
+    return {"pop_mean": a[0].astype(np.float64) / (n * 4294967296.0), "pop_sum_q32": a[0].copy(),
+            "pop_min": mn.copy(), "pop_max": mx.copy()}
 
 
 def vct_create_population(desc: vct_population_desc, params_dev, stream=None) -> C.c_void_p:
@@ -334,7 +353,7 @@ def controller(trial: dict, mpc_dev=None, mlp_dev=None) -> vct_controller:
 
 
 def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None, record_dev=None,
-                 fallback_dev=None) -> vct_sim:
+                 fallback_dev=None, popbg_dev=None) -> vct_sim:
     s = vct_sim()
     s.n_days, s.em_per_ctrl, s.ts_min = int(trial["n_days"]), int(trial["em_per_ctrl"]), int(trial["ts_min"])
     s.precision = int(trial["precision"])
@@ -345,6 +364,7 @@ def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None
     s.traj_dev = _ptr(traj_dev)
     s.record_dev = _ptr(record_dev)
     s.fallback_dev = _ptr(fallback_dev)
+    s.popbg_dev = _ptr(popbg_dev)
     return s
 
 

@@ -299,3 +299,48 @@ def test_basal_scale_needs_pid_or_open_loop(gpu):
         assert e.value.code == vct.VCT_EINVAL
     finally:
         vct.vct_destroy_population(pop)
+
+
+def _pop_from_traj(traj_g):
+    g = np.asarray(traj_g, np.float64)
+    return np.rint(g * 4294967296.0).astype(np.int64).sum(0), g.min(0), g.max(0)
+
+
+@pytest.mark.parametrize("case", ["pid45", "pid64", "mpc45", "mlp45"])
+def test_population_bg_equals_trajectories(gpu, case):
+    """Population BG per sample (Sec. III-C) equals what the patients' own trajectories give:
+    the integer sum of round(G 2^32) exactly, min and max exactly, for a full wave and a
+    ragged one, in the plain, MPC and learned-controller kernels."""
+    import torch
+    from paper_2202_13927_amd import policy
+    kind, n = case[:3], int(case[3:])
+    base = {"pid": W.c2_fp32_pid(), "mpc": W.c5_mpc(), "mlp": W.c5_mlp()}[kind]
+    t = W.with_(base, n_patients=n, n_days=2, precision=W.FP32)
+    blob = None
+    if kind == "mlp":
+        pol = policy.Policy(batch=64)
+        pol.load(W.synthetic_policy_net(71))
+        blob = pol.blob
+    _say(f"[gpu] population BG, {case}")
+    b1 = gpu.TrialBuffers(t, popbg=True)
+    gpu.run(t, bufs=b1, mlp_blob=blob)
+    p = gpu.to_host(b1)
+    b2 = gpu.TrialBuffers(t, traj_patients=n)
+    gpu.run(t, bufs=b2, mlp_blob=blob)
+    s, mn, mx = _pop_from_traj(gpu.to_host(b2)["traj_g"])
+    assert np.array_equal(p["pop_sum_q32"], s)
+    assert np.array_equal(p["pop_min"], mn) and np.array_equal(p["pop_max"], mx)
+    assert np.allclose(p["pop_mean"], s / (n * 4294967296.0), rtol=1e-15)
+
+
+def test_population_bg_matches_oracle(gpu, orc):
+    t = W.with_(W.c1_fp64_pid(), n_patients=3000, n_days=2)
+    _say("[gpu] population BG vs oracle, 3000 x 2 d FP64")
+    b = gpu.TrialBuffers(t, popbg=True)
+    gpu.run(t, bufs=b)
+    p = gpu.to_host(b)
+    o = orc.simulate(t, n_traj=3000, threads=THREADS)
+    s, mn, mx = _pop_from_traj(o["traj_g"])
+    assert np.allclose(p["pop_mean"], s / (3000 * 4294967296.0), rtol=1e-9)
+    assert np.allclose(p["pop_min"], mn, rtol=1e-9) and np.allclose(p["pop_max"], mx, rtol=1e-9)
+    assert np.all(p["pop_min"] <= p["pop_mean"]) and np.all(p["pop_mean"] <= p["pop_max"])
