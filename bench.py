@@ -144,6 +144,13 @@ def nordic_leg(stream) -> dict:
     pd = t["n_patients"] * t["n_days"]
     log(f"[bench] nordic: {ms:.1f} ms, mean TIR {s['mean_tir']:.4f}; with population BG per sample {ms_p:.1f} ms")
     pm = curve["pop_mean"]
+    import numpy as np
+    cdf = np.cumsum(curve["pop_hist"].astype(np.float64))
+    cdf /= cdf[-1]
+    # pooled BG distribution (every patient and sample): quantiles to the 0.1 mmol/L bin
+    # (upper edge of the bin where the cumulative share first reaches p; bin b >= 1 covers
+    # [(b-1)/10, b/10))
+    pooled_q = [float(np.searchsorted(cdf, q) / 10.0) for q in (0.05, 0.25, 0.5, 0.75, 0.95)]
     return {"workload": "Northern-European protocol (Sec. II-B, Tables I-II), 1000000 patients x 364 days, PID, "
                         "FP32, meal size SD 10 %, onset jitter +-30 min", "patient_days": pd, "ms": ms,
             "patient_days_per_s": pd / ms * 1e3, "mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"],
@@ -152,7 +159,8 @@ def nordic_leg(stream) -> dict:
                                          "mean_of_mean_curve": float(pm.mean()),
                                          "mean_curve_range": [float(pm.min()), float(pm.max())],
                                          "lowest": float(curve["pop_min"].min()),
-                                         "highest": float(curve["pop_max"].max())}}
+                                         "highest": float(curve["pop_max"].max()),
+                                         "pooled_bg_quantiles_mmol": pooled_q}}
 
 
 def scenarios_leg(stream) -> dict:

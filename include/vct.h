@@ -269,8 +269,11 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
  *                          the mean is sum / (n 2^32));
  *   uint64 min[K]  @8K     order-preserving key of the smallest G (as FP64):
  *   uint64 max[K]  @16K    key = bits ^ (sign ? all ones : sign bit); G = the key inverted;
- * vct_simulate writes all three (the buffer need not be initialised). Returns 24 K bytes,
- * or 0 for invalid arguments. */
+ *   uint64 hist[402] @24K  the BG of every patient and sample in bins of 0.1 mmol/L: bin 0
+ *                          below 0 (and NaN), bin 1 + floor(10 G) for 0 <= G < 40, bin 401
+ *                          at or above 40 (the population's BG distribution, Sec. IV-D);
+ * vct_simulate writes all of it (the buffer need not be initialised). Returns 24 K + 3216
+ * bytes, or 0 for invalid arguments. */
 size_t      vct_popbg_bytes(int32_t n_days, int32_t ts_min);
 size_t      vct_mpc_bytes(int64_t n_patients, int32_t precision);
 vct_status  vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, const vct_sim *sim, void *mpc_dev,

@@ -61,6 +61,7 @@ struct SimArgs {
     double *traj;         // [3][n_traj][K] or null
     int64_t *pop_sum;     // [K] sum of round(G 2^32) over the patients, or null
     uint64_t *pop_min, *pop_max;   // [K] order-preserving keys of min / max G
+    uint64_t *pop_hist;   // [402] pooled BG bins of 0.1 mmol/L
     int64_t K;
 };
 

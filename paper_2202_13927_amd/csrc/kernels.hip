@@ -122,13 +122,46 @@ __device__ __forceinline__ void pop_accumulate(const SimArgs &a, int32_t k, doub
     }
 }
 
-__global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, int64_t K)
+// The pooled BG distribution (every patient and sample): bins of 0.1 mmol/L, bin 0 below
+// 0 (and NaN), bin 1 + floor(10 G) for 0 <= G < 40, bin 401 at or above 40. Counted per wave
+// in LDS, added to the 64-bit global bins when the wave ends.
+constexpr int kPopBins = 402;
+
+__device__ __forceinline__ int pop_bin(double g)
+{
+    return g >= 0.0 ? 1 + (int)fmin(g * 10.0, 400.5) : 0;
+}
+
+// Zeroes (start) or flushes (end) a wave's LDS bins; all lanes of the wave take part.
+__device__ __forceinline__ void pop_hist_clear(uint32_t *h, int lane)
+{
+    for (int b = lane; b < kPopBins; b += 64)
+        h[b] = 0u;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+__device__ __forceinline__ void pop_hist_flush(const SimArgs &a, uint32_t *h, int lane)
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    for (int b = lane; b < kPopBins; b += 64) {
+        const uint32_t c = h[b];
+        if (c)
+            atomicAdd((unsigned long long *)&a.pop_hist[b], (unsigned long long)c);
+    }
+}
+
+__global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, uint64_t *hist, int64_t K)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
         sum[i] = 0;
         mn[i] = ~0ull;
         mx[i] = 0ull;
     }
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kPopBins; i += (int64_t)gridDim.x * blockDim.x)
+        hist[i] = 0ull;
 }
 
 // Meals of one (patient, day) as a queue in time order: sample index within the day and
@@ -384,6 +417,7 @@ struct PolicyShared {
     uint16_t *xs;               // [64][PaddedLayout::ldi] BF16 normalised inputs, row = lane
     float *o;                   // [64] network outputs
     const float *mean, *istd, *lo, *hi;
+    uint32_t *hist;             // population BG bins of this wave (kOutPop)
     int lane;
     bool rest;                  // this wave's patient is outside the box: the MPC acts on every sample
 };
@@ -555,8 +589,11 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
 {
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
-    if (OUT & kOutPop)
+    if (OUT & kOutPop) {
         pop_accumulate(a, k, (double)G, live);
+        if (live)
+            atomicAdd(&ps.hist[pop_bin((double)G)], 1u);
+    }
     L.c30 += G >= R(3.0);
     L.c39 += G >= R(3.9);
     L.c100 += G > R(10.0);
@@ -836,13 +873,18 @@ template <typename R, int CTRL, bool NOISY, int OUT>
 __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (OUT & kOutPop) {
+    if constexpr ((OUT & kOutPop) != 0) {
         // the population reduction needs every lane of a wave: lanes past the last patient
         // replay it and write nothing; a wave wholly past it exits
+        __shared__ uint32_t hist[4][kPopBins];
         if ((j & ~(int64_t)63) >= a.n)
             return;
         const bool live = j < a.n;
-        run_patient<R, CTRL, NOISY, OUT>(a, live ? j : a.n - 1, live, PolicyShared{});
+        PolicyShared ps{};
+        ps.hist = hist[threadIdx.x >> 6];
+        pop_hist_clear(ps.hist, threadIdx.x & 63);
+        run_patient<R, CTRL, NOISY, OUT>(a, live ? j : a.n - 1, live, ps);
+        pop_hist_flush(a, ps.hist, threadIdx.x & 63);
     } else if (j < a.n) {
         run_patient<R, CTRL, NOISY, OUT>(a, j, true, PolicyShared{});
     }
@@ -882,6 +924,12 @@ __global__ __launch_bounds__(kPolicyBlock, kPolicyBlocksPerCu) void simulate_pol
     ps.lo = (const float *)(lds + PolicyNet::tail + (kOffLo - kOffB1));
     ps.hi = (const float *)(lds + PolicyNet::tail + (kOffHi - kOffB1));
     ps.lane = threadIdx.x & 63;
+    ps.hist = nullptr;
+    if constexpr ((OUT & kOutPop) != 0) {
+        __shared__ uint32_t phist[kPolicyBlock / 64][kPopBins];
+        ps.hist = phist[wave];
+        pop_hist_clear(ps.hist, ps.lane);
+    }
     // Work items, longest first: each patient outside the box alone on a wave (the MPC acts
     // on every sample, solved cooperatively), then tiles of 64 patients inside the box.
     const int32_t n_in = counts[nb];
@@ -907,6 +955,8 @@ __global__ __launch_bounds__(kPolicyBlock, kPolicyBlocksPerCu) void simulate_pol
         ps.rest = item < n_rest;
         run_patient<R, kCtrlMlp, NOISY, OUT>(a, (int64_t)a.order[slot], live, ps);
     }
+    if constexpr ((OUT & kOutPop) != 0)
+        pop_hist_flush(a, ps.hist, ps.lane);
 }
 
 // Lane order of the learned controller: a stable partition of the patients into those whose
@@ -1149,7 +1199,8 @@ static void launch_sim_n(const SimArgs &a, hipStream_t s)
     const bool traj = a.traj != nullptr && a.n_traj > 0;
     const bool rec = a.record != nullptr;
     if (a.pop_sum) {   // not combined with traj / record (checked by the ABI)
-        hipLaunchKernelGGL(popbg_init_kernel, dim3(256), dim3(256), 0, s, a.pop_sum, a.pop_min, a.pop_max, a.K);
+        hipLaunchKernelGGL(popbg_init_kernel, dim3(256), dim3(256), 0, s, a.pop_sum, a.pop_min, a.pop_max, a.pop_hist,
+                           a.K);
         launch_sim_o<R, CTRL, NOISY, kOutPop>(a, s);
         return;
     }

@@ -217,13 +217,14 @@ def popbg_decode(buf, n: int, K: int) -> dict:
     """Population BG per sample from a vct_popbg_bytes buffer (torch int64 [3K]): mean, min,
     max in mmol/L as numpy float64 arrays (the layout documented in vct.h)."""
     import numpy as np
-    a = buf.view(3, K).cpu().numpy()
+    full = buf.cpu().numpy()
+    a = full[:3 * K].reshape(3, K)
     keys = a[1:].view(np.uint64)
     neg = (keys >> np.uint64(63)) == 0
     bits = np.where(neg, ~keys, keys ^ np.uint64(1 << 63))
     mn, mx = bits.view(np.float64)
     return {"pop_mean": a[0].astype(np.float64) / (n * 4294967296.0), "pop_sum_q32": a[0].copy(),
-            "pop_min": mn.copy(), "pop_max": mx.copy()}
+            "pop_min": mn.copy(), "pop_max": mx.copy(), "pop_hist": full[3 * K:3 * K + 402].view(np.uint64).copy()}
 
 
 def vct_create_population(desc: vct_population_desc, params_dev, stream=None) -> C.c_void_p:

@@ -301,6 +301,13 @@ def test_basal_scale_needs_pid_or_open_loop(gpu):
         vct.vct_destroy_population(pop)
 
 
+def _pop_hist(traj_g):
+    """Bins of 0.1 mmol/L: 0 below 0, 1 + floor(10 G) for 0 <= G < 40, 401 at or above 40."""
+    g = np.asarray(traj_g, np.float64).ravel()
+    b = np.where(g >= 0.0, 1 + np.floor(np.minimum(g * 10.0, 400.5)).astype(np.int64), 0)
+    return np.bincount(b, minlength=402).astype(np.uint64)
+
+
 def _pop_from_traj(traj_g):
     g = np.asarray(traj_g, np.float64)
     return np.rint(g * 4294967296.0).astype(np.int64).sum(0), g.min(0), g.max(0)
@@ -331,6 +338,7 @@ def test_population_bg_equals_trajectories(gpu, case):
     assert np.array_equal(p["pop_sum_q32"], s)
     assert np.array_equal(p["pop_min"], mn) and np.array_equal(p["pop_max"], mx)
     assert np.allclose(p["pop_mean"], s / (n * 4294967296.0), rtol=1e-15)
+    assert np.array_equal(p["pop_hist"], _pop_hist(gpu.to_host(b2)["traj_g"]))
 
 
 def test_population_bg_matches_oracle(gpu, orc):
@@ -344,3 +352,12 @@ def test_population_bg_matches_oracle(gpu, orc):
     assert np.allclose(p["pop_mean"], s / (3000 * 4294967296.0), rtol=1e-9)
     assert np.allclose(p["pop_min"], mn, rtol=1e-9) and np.allclose(p["pop_max"], mx, rtol=1e-9)
     assert np.all(p["pop_min"] <= p["pop_mean"]) and np.all(p["pop_mean"] <= p["pop_max"])
+    h = _pop_hist(o["traj_g"]).astype(np.int64)
+    assert int(p["pop_hist"].sum()) == 3000 * o["K"]
+    # a value within rounding of a bin edge may land on either side (every patient starts at
+    # G* = 6.0 exactly, an edge): each such value can move one count between two bins
+    g10 = np.asarray(o["traj_g"], np.float64).ravel() * 10.0
+    near = int((np.abs(g10 - np.rint(g10)) < 1e-8).sum())
+    diff = int(np.abs(p["pop_hist"].astype(np.int64) - h).sum())
+    _say("   histogram: counts moved", diff, "values near an edge", near)
+    assert diff <= 2 * near
