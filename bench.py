@@ -160,7 +160,13 @@ def nordic_leg(stream) -> dict:
                                          "mean_curve_range": [float(pm.min()), float(pm.max())],
                                          "lowest": float(curve["pop_min"].min()),
                                          "highest": float(curve["pop_max"].max()),
-                                         "pooled_bg_quantiles_mmol": pooled_q}}
+                                         "pooled_bg_quantiles_mmol": pooled_q,
+                                         # Fig. 3's span: the least and the most time any patient
+                                         # spends below 4.0 and below 10.0 mmol/L
+                                         "span_fraction_below_4": [float(curve["span_min"][7]) / bufs_p.K,
+                                                                   float(curve["span_max"][7]) / bufs_p.K],
+                                         "span_fraction_below_10": [float(curve["span_min"][19]) / bufs_p.K,
+                                                                    float(curve["span_max"][19]) / bufs_p.K]}}
 
 
 def scenarios_leg(stream) -> dict:

@@ -272,7 +272,11 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
  *   uint64 hist[402] @24K  the BG of every patient and sample in bins of 0.1 mmol/L: bin 0
  *                          below 0 (and NaN), bin 1 + floor(10 G) for 0 <= G < 40, bin 401
  *                          at or above 40 (the population's BG distribution, Sec. IV-D);
- * vct_simulate writes all of it (the buffer need not be initialised). Returns 24 K + 3216
+ *   uint64 span_min[50] @24K+3216, span_max[50] @24K+3616: over the patients, the smallest
+ *                          and largest number of their samples with G below (b + 1) / 2
+ *                          mmol/L, b = 0..48 (b = 49: all samples) -- the span of the
+ *                          patients' own BG distributions (Fig. 3);
+ * vct_simulate writes all of it (the buffer need not be initialised). Returns 24 K + 4016
  * bytes, or 0 for invalid arguments. */
 size_t      vct_popbg_bytes(int32_t n_days, int32_t ts_min);
 size_t      vct_mpc_bytes(int64_t n_patients, int32_t precision);

@@ -69,7 +69,7 @@ size_t vct_popbg_bytes(int32_t n_days, int32_t ts_min)
 {
     if (n_days <= 0 || ts_min <= 0 || 1440 % ts_min != 0)
         return 0;
-    return ((size_t)3 * (size_t)n_days * (size_t)(1440 / ts_min) + 402) * sizeof(int64_t);
+    return ((size_t)3 * (size_t)n_days * (size_t)(1440 / ts_min) + 502) * sizeof(int64_t);
 }
 
 size_t vct_traj_bytes(int32_t traj_patients, int32_t n_days, int32_t ts_min)
@@ -285,6 +285,8 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.pop_min = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + K : nullptr;
     a.pop_max = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 2 * K : nullptr;
     a.pop_hist = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K : nullptr;
+    a.span_min = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K + 402 : nullptr;
+    a.span_max = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K + 452 : nullptr;
     return VCT_OK;
 }
 

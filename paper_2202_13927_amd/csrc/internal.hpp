@@ -62,6 +62,7 @@ struct SimArgs {
     int64_t *pop_sum;     // [K] sum of round(G 2^32) over the patients, or null
     uint64_t *pop_min, *pop_max;   // [K] order-preserving keys of min / max G
     uint64_t *pop_hist;   // [402] pooled BG bins of 0.1 mmol/L
+    uint64_t *span_min, *span_max;   // [50] min / max over patients of the cumulative 0.5 mmol/L bins
     int64_t K;
 };
 

@@ -153,6 +153,38 @@ __device__ __forceinline__ void pop_hist_flush(const SimArgs &a, uint32_t *h, in
     }
 }
 
+// The span of the patients' own BG distributions (Fig. 3's shaded area): each lane counts its
+// patient's samples in bins of 0.5 mmol/L (bin floor(2 G), clamped to 0..49) in LDS laid out
+// [bin][lane]; at the patient's end the cumulative counts (samples with G below
+// (b + 1) / 2, all samples in the last bin) are reduced over the wave's live lanes to their
+// minimum and maximum and added with 64-bit atomics. All lanes of the wave take part.
+constexpr int kSpanBins = 50;
+
+__device__ __forceinline__ int span_bin(double g)
+{
+    return g >= 0.0 ? (int)fmin(g * 2.0, 49.5) : 0;
+}
+
+__device__ __forceinline__ void span_flush(const SimArgs &a, uint32_t *cnt, int lane, bool live)
+{
+    uint32_t cum = 0;
+    for (int b = 0; b < kSpanBins; ++b) {
+        cum += cnt[b * 64 + lane];
+        cnt[b * 64 + lane] = 0u;
+        uint32_t mn = live ? cum : ~0u, mx = live ? cum : 0u;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t omn = __shfl_xor(mn, off), omx = __shfl_xor(mx, off);
+            mn = omn < mn ? omn : mn;
+            mx = omx > mx ? omx : mx;
+        }
+        if (lane == 0) {
+            atomicMin((unsigned long long *)&a.span_min[b], (unsigned long long)mn);
+            atomicMax((unsigned long long *)&a.span_max[b], (unsigned long long)mx);
+        }
+    }
+}
+
 __global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, uint64_t *hist, int64_t K)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
@@ -162,6 +194,11 @@ __global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, uint
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kPopBins; i += (int64_t)gridDim.x * blockDim.x)
         hist[i] = 0ull;
+    // then the span: min[kSpanBins], max[kSpanBins]
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kSpanBins; i += (int64_t)gridDim.x * blockDim.x) {
+        hist[kPopBins + i] = ~0ull;
+        hist[kPopBins + kSpanBins + i] = 0ull;
+    }
 }
 
 // Meals of one (patient, day) as a queue in time order: sample index within the day and
@@ -418,6 +455,7 @@ struct PolicyShared {
     float *o;                   // [64] network outputs
     const float *mean, *istd, *lo, *hi;
     uint32_t *hist;             // population BG bins of this wave (kOutPop)
+    uint32_t *span;             // [kSpanBins][64] per-lane BG bins of this wave (kOutPop)
     int lane;
     bool rest;                  // this wave's patient is outside the box: the MPC acts on every sample
 };
@@ -593,6 +631,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         pop_accumulate(a, k, (double)G, live);
         if (live)
             atomicAdd(&ps.hist[pop_bin((double)G)], 1u);
+        atomicAdd(&ps.span[span_bin((double)G) * 64 + ps.lane], 1u);   // this lane's own counters
     }
     L.c30 += G >= R(3.0);
     L.c39 += G >= R(3.9);
@@ -847,6 +886,8 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
         if (!all_finite(s))
             L.status |= kStNonFinite;
     }
+    if (OUT & kOutPop)
+        span_flush(a, ps.span, ps.lane, live);
 
     if (!live)
         return;
@@ -877,11 +918,16 @@ __global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
         // the population reduction needs every lane of a wave: lanes past the last patient
         // replay it and write nothing; a wave wholly past it exits
         __shared__ uint32_t hist[4][kPopBins];
+        __shared__ uint32_t span[4][kSpanBins * 64];
         if ((j & ~(int64_t)63) >= a.n)
             return;
         const bool live = j < a.n;
         PolicyShared ps{};
+        ps.lane = threadIdx.x & 63;
         ps.hist = hist[threadIdx.x >> 6];
+        ps.span = span[threadIdx.x >> 6];
+        for (int b = 0; b < kSpanBins; ++b)
+            ps.span[b * 64 + ps.lane] = 0u;
         pop_hist_clear(ps.hist, threadIdx.x & 63);
         run_patient<R, CTRL, NOISY, OUT>(a, live ? j : a.n - 1, live, ps);
         pop_hist_flush(a, ps.hist, threadIdx.x & 63);
@@ -925,9 +971,14 @@ __global__ __launch_bounds__(kPolicyBlock, kPolicyBlocksPerCu) void simulate_pol
     ps.hi = (const float *)(lds + PolicyNet::tail + (kOffHi - kOffB1));
     ps.lane = threadIdx.x & 63;
     ps.hist = nullptr;
+    ps.span = nullptr;
     if constexpr ((OUT & kOutPop) != 0) {
         __shared__ uint32_t phist[kPolicyBlock / 64][kPopBins];
+        __shared__ uint32_t pspan[kPolicyBlock / 64][kSpanBins * 64];
         ps.hist = phist[wave];
+        ps.span = pspan[wave];
+        for (int b = 0; b < kSpanBins; ++b)
+            ps.span[b * 64 + ps.lane] = 0u;
         pop_hist_clear(ps.hist, ps.lane);
     }
     // Work items, longest first: each patient outside the box alone on a wave (the MPC acts

@@ -224,7 +224,8 @@ def popbg_decode(buf, n: int, K: int) -> dict:
     bits = np.where(neg, ~keys, keys ^ np.uint64(1 << 63))
     mn, mx = bits.view(np.float64)
     return {"pop_mean": a[0].astype(np.float64) / (n * 4294967296.0), "pop_sum_q32": a[0].copy(),
-            "pop_min": mn.copy(), "pop_max": mx.copy(), "pop_hist": full[3 * K:3 * K + 402].view(np.uint64).copy()}
+            "pop_min": mn.copy(), "pop_max": mx.copy(), "pop_hist": full[3 * K:3 * K + 402].view(np.uint64).copy(),
+            "span_min": full[3 * K + 402:3 * K + 452].copy(), "span_max": full[3 * K + 452:3 * K + 502].copy()}
 
 
 def vct_create_population(desc: vct_population_desc, params_dev, stream=None) -> C.c_void_p:

@@ -308,6 +308,15 @@ def _pop_hist(traj_g):
     return np.bincount(b, minlength=402).astype(np.uint64)
 
 
+def _span(traj_g):
+    """Over the patients, min and max of the number of samples with G below (b + 1) / 2
+    mmol/L (bin floor(2 G) clamped to 0..49, cumulative)."""
+    g = np.asarray(traj_g, np.float64)
+    b = np.where(g >= 0.0, np.floor(np.minimum(g * 2.0, 49.5)).astype(np.int64), 0)
+    counts = np.stack([(b == q).sum(1) for q in range(50)], axis=1).cumsum(1)
+    return counts.min(0), counts.max(0)
+
+
 def _pop_from_traj(traj_g):
     g = np.asarray(traj_g, np.float64)
     return np.rint(g * 4294967296.0).astype(np.int64).sum(0), g.min(0), g.max(0)
@@ -338,7 +347,10 @@ def test_population_bg_equals_trajectories(gpu, case):
     assert np.array_equal(p["pop_sum_q32"], s)
     assert np.array_equal(p["pop_min"], mn) and np.array_equal(p["pop_max"], mx)
     assert np.allclose(p["pop_mean"], s / (n * 4294967296.0), rtol=1e-15)
-    assert np.array_equal(p["pop_hist"], _pop_hist(gpu.to_host(b2)["traj_g"]))
+    tg = gpu.to_host(b2)["traj_g"]
+    assert np.array_equal(p["pop_hist"], _pop_hist(tg))
+    smin, smax = _span(tg)
+    assert np.array_equal(p["span_min"], smin) and np.array_equal(p["span_max"], smax)
 
 
 def test_population_bg_matches_oracle(gpu, orc):
@@ -361,3 +373,8 @@ def test_population_bg_matches_oracle(gpu, orc):
     diff = int(np.abs(p["pop_hist"].astype(np.int64) - h).sum())
     _say("   histogram: counts moved", diff, "values near an edge", near)
     assert diff <= 2 * near
+    smin, smax = _span(o["traj_g"])
+    g2 = np.asarray(o["traj_g"], np.float64) * 2.0
+    near2 = int((np.abs(g2 - np.rint(g2)) < 1e-8).sum())
+    assert np.abs(p["span_min"] - smin).max() <= near2 and np.abs(p["span_max"] - smax).max() <= near2
+    assert p["span_max"][-1] == o["K"] and np.all(np.diff(p["span_min"]) >= 0)
