@@ -19,7 +19,7 @@ The JSON line also carries
   rate underestimated by 50 %) on that protocol, the same 1,000,000 patients each, as two
   arms of one batched launch: TIR and the distribution of the daily insulin per arm;
 * learned -- the learned controller against exact linear MPC on common random numbers
-  (100,000 x 28 days by default, 1,000,000 x 364 days with --learned-full).
+  (1,000,000 x 28 days by default, 1,000,000 x 364 days with --learned-full).
 """
 from __future__ import annotations
 
@@ -207,14 +207,14 @@ def learned_leg(full: bool) -> dict:
     """The learned controller against exact MPC on common random numbers: train on the MPC's
     recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
     evaluation population with both controllers. full: 1,000,000 patients x 364 days as two
-    slices of 500,000 (each slice keeps the patients' global indices); otherwise 100,000 x 28
+    slices of 500,000 (each slice keeps the patients' global indices); otherwise 1,000,000 x 28
     days. Times are the simulation launches only (HIP events); MPC setup and training are
     reported separately."""
     from paper_2202_13927_amd import learned as L, workloads as W
     t0 = time.perf_counter()
     pol, rep = L.train_policy(W.mlp_training_population(), epochs=10.0, log=log)
     train_s = time.perf_counter() - t0
-    n, days, slices = (1_000_000, 364, 2) if full else (100_000, 28, 1)
+    n, days, slices = (1_000_000, 364, 2) if full else (1_000_000, 28, 1)
     tot = {"mpc": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}, "mlp": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}}
     fb = 0.0
     always = 0
