@@ -485,7 +485,9 @@ void orc_em_ou(double theta, double s, double x0, double h, int32_t n_steps, int
  * range), [3] 10.0-13.9, [4] > 13.9. The index is the number of edges passed, so a
  * non-finite G lands in [0] (and raises a status bit). Events: a maximal run of at
  * least 3 consecutive samples below 3.9, below 3.0, or above 13.9, counted once
- * when the run reaches 3 samples. */
+ * when the run reaches 3 samples. "Below an edge" is "not at or above it", so a
+ * non-finite G, counted in the lowest range, also continues the runs below 3.9
+ * and 3.0; for finite G this is the plain comparison. */
 static const double EDGE[4] = {3.0, 3.9, 10.0, 13.9};
 
 typedef struct {
@@ -500,7 +502,7 @@ static void acc_sample(acc_t *a, double G, int32_t k, double guard)
 {
     int b = (G >= EDGE[0]) + (G >= EDGE[1]) + (G > EDGE[2]) + (G > EDGE[3]);
     a->bins[b] += 1;
-    int cond[3] = {G < 3.9, G < 3.0, G > 13.9};
+    int cond[3] = {!(G >= 3.9), !(G >= 3.0), G > 13.9};
     for (int e = 0; e < 3; ++e) {
         if (cond[e]) {
             a->run[e] += 1;

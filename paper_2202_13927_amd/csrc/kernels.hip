@@ -208,6 +208,20 @@ template <typename R> struct DayMeals {
     R r0, r1, r2, r3, r4, r5;
 };
 
+// Takes the first meal off the queue and returns its intake rate.
+template <typename R>
+__device__ __forceinline__ R pop_front(DayMeals<R> &d)
+{
+    const R r = d.r0;
+    d.k0 = d.k1; d.r0 = d.r1;
+    d.k1 = d.k2; d.r1 = d.r2;
+    d.k2 = d.k3; d.r2 = d.r3;
+    d.k3 = d.k4; d.r3 = d.r4;
+    d.k4 = d.k5; d.r4 = d.r5;
+    d.k5 = -1;
+    return r;
+}
+
 template <typename R>
 __device__ __forceinline__ void push_front(DayMeals<R> &d, int32_t k, R r)
 {
@@ -605,7 +619,7 @@ __device__ __forceinline__ R coop_qp(const SimArgs &a, const R *__restrict__ M, 
 #pragma unroll
         for (int c = 0; c < kMpcN; ++c)
             acc = fmaf_t(T[c], v[c], acc);
-        dU = act ? vmin(vmax(fmaf_t(-step, acc, dU), lo), hi) : R(0);
+        dU = act ? vclamp(fmaf_t(-step, acc, dU), lo, hi) : R(0);
     }
     if (liveL && act)
         P[(int64_t)i * a.n + jL] = dU;
@@ -615,13 +629,14 @@ __device__ __forceinline__ R coop_qp(const SimArgs &a, const R *__restrict__ M, 
 }
 
 // One sampling instant t_k: indicators on the true glucose, sensor value, controller,
-// held inputs, then the EM steps of [t_k, t_k+1). z[0..4] are the EM noise increments
+// held inputs, then the EM steps of [t_k, t_k+1). dr is the held meal input of the
+// interval (also the MPC's announcement). z[0..4] are the EM noise increments
 // (sqrt(h) sigma xi), z[5] the sensor noise (sqrt(R) v). `live` is false for the padding
 // lanes of the learned controller's last wave, which compute but write nothing.
 template <typename R, int CTRL, int OUT>
-__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool live, int32_t kk, int32_t k,
+__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool live, int32_t k, R dr,
                                             const R *z, State<R> &s, const StepConst<R> &c,
-                                            const CtrlConst<R> &cc, DayMeals<R> &ml, Lane<R> &L, MpcState<R> &ms,
+                                            const CtrlConst<R> &cc, Lane<R> &L, MpcState<R> &ms,
                                             MpcPlan<R> &mplan, const LinStep<R> &lin,
                                             PolicyLane<R> &pl, const PolicyShared &ps)
 {
@@ -633,13 +648,17 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
             atomicAdd(&ps.hist[pop_bin((double)G)], 1u);
         atomicAdd(&ps.span[span_bin((double)G) * 64 + ps.lane], 1u);   // this lane's own counters
     }
-    L.c30 += G >= R(3.0);
-    L.c39 += G >= R(3.9);
+    // one comparison per edge serves both the range count and the run: a run below an edge
+    // continues while G is not at or above it, so a non-finite G (in the lowest range, with
+    // its status bit) also continues the runs below 3.9 and 3.0
+    const bool at30 = G >= R(3.0), at39 = G >= R(3.9), above139 = G > R(13.9);
+    L.c30 += at30;
+    L.c39 += at39;
     L.c100 += G > R(10.0);
-    L.c139 += G > R(13.9);
-    L.r_hypo = G < R(3.9) ? L.r_hypo + 1 : 0;
-    L.r_sev = G < R(3.0) ? L.r_sev + 1 : 0;
-    L.r_hyper = G > R(13.9) ? L.r_hyper + 1 : 0;
+    L.c139 += above139;
+    L.r_hypo = at39 ? 0 : L.r_hypo + 1;
+    L.r_sev = at30 ? 0 : L.r_sev + 1;
+    L.r_hyper = above139 ? L.r_hyper + 1 : 0;
     L.e_hypo += L.r_hypo == 3;
     L.e_sev += L.r_sev == 3;
     L.e_hyper += L.r_hyper == 3;
@@ -652,17 +671,6 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         L.status |= kStNegQ1;
 
     const R y = fmaf_t(s.GIs, c.gi_scale, z[5]);   // y_k = g(x(t_k)) + v_k
-
-    R dr = R(0);   // held meal input of this interval (also the MPC's announcement)
-    if (kk == ml.k0) {
-        dr = ml.r0;
-        ml.k0 = ml.k1; ml.r0 = ml.r1;
-        ml.k1 = ml.k2; ml.r1 = ml.r2;
-        ml.k2 = ml.k3; ml.r2 = ml.r3;
-        ml.k3 = ml.k4; ml.r3 = ml.r4;
-        ml.k4 = ml.k5; ml.r4 = ml.r5;
-        ml.k5 = -1;
-    }
 
     constexpr bool kFeat = CTRL == kCtrlMlp || (OUT & kOutRecord);
     R f[kMlpIn];
@@ -681,7 +689,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
             L.y_prev = y;
         const R e = y - cc.sp;
         const R u_unc = cc.ub + cc.kp * e + cc.ki * L.integ + cc.kd_ts * (y - L.y_prev);
-        u = vmin(vmax(u_unc, R(0)), cc.umax);
+        u = vclamp(u_unc, R(0), cc.umax);
         if (u_unc >= R(0) && u_unc <= cc.umax)
             L.integ += e * cc.ts;
         L.y_prev = y;
@@ -721,7 +729,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
             u = cc.ub + du;
             ++pl.fallbacks;
         } else {
-            u = vmin(vmax(cc.ub * R(o), R(0)), cc.umax);
+            u = vclamp(cc.ub * R(o), R(0), cc.umax);
             du = u - cc.ub;
         }
         label = cc.ub + du_mpc;
@@ -859,9 +867,9 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
             R z[12];
             if (NOISY) {
                 const uint32_t jp = (uint32_t)(k >> 1);
-                const U4 b0 = philox4x32_10(jp, pid, kTagDiff, 0u, a.key0, a.key1);
-                const U4 b1 = philox4x32_10(jp, pid, kTagDiff, 1u, a.key0, a.key1);
-                const U4 b2 = philox4x32_10(jp, pid, kTagDiff, 2u, a.key0, a.key1);
+                const U4 b0 = philox4x32_10_lane1(jp, pid, kTagDiff, 0u, a.key0, a.key1);
+                const U4 b1 = philox4x32_10_lane1(jp, pid, kTagDiff, 1u, a.key0, a.key1);
+                const U4 b2 = philox4x32_10_lane1(jp, pid, kTagDiff, 2u, a.key0, a.key1);
                 // pure diffusion pairs come out scaled by sqrt(h) sigma; the two pairs that
                 // mix an EM normal with the sensor normal are scaled per normal
                 R r0, r1;
@@ -880,8 +888,17 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
                 for (int q = 0; q < 12; ++q)
                     z[q] = R(0);
             }
-            sample_step<R, CTRL, OUT>(a, j, live, kk, k, z, s, c, cc, ml, L, ms, mplan, lin, pl, ps);
-            sample_step<R, CTRL, OUT>(a, j, live, kk + 1, k + 1, z + 6, s, c, cc, ml, L, ms, mplan, lin, pl, ps);
+            // held meal inputs of the pair: the queue is touched only when its first meal
+            // starts at kk or kk + 1 (one unsigned compare per pair; -1 never matches)
+            R dr0 = R(0), dr1 = R(0);
+            if ((uint32_t)(ml.k0 - kk) <= 1u) {
+                if (ml.k0 == kk)
+                    dr0 = pop_front(ml);
+                if (ml.k0 == kk + 1)
+                    dr1 = pop_front(ml);
+            }
+            sample_step<R, CTRL, OUT>(a, j, live, k, dr0, z, s, c, cc, L, ms, mplan, lin, pl, ps);
+            sample_step<R, CTRL, OUT>(a, j, live, k + 1, dr1, z + 6, s, c, cc, L, ms, mplan, lin, pl, ps);
         }
         if (!all_finite(s))
             L.status |= kStNonFinite;

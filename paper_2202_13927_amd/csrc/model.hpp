@@ -38,6 +38,11 @@ __device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
 __device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
 __device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+// min(max(x, lo), hi) for lo <= hi. In FP32 this is one v_med3_f32: the median of x, lo
+// and hi is the clamp when lo <= hi, and a NaN x gives lo in both forms (the instruction
+// then returns the smallest of the other two). Every caller has lo <= hi.
+__device__ __forceinline__ float vclamp(float x, float lo, float hi) { return __builtin_amdgcn_fmed3f(x, lo, hi); }
+__device__ __forceinline__ double vclamp(double x, double lo, double hi) { return fmin(fmax(x, lo), hi); }
 __device__ __forceinline__ float fmaf_t(float a, float b, float c) { return fmaf(a, b, c); }
 __device__ __forceinline__ double fmaf_t(double a, double b, double c) { return fma(a, b, c); }
 

@@ -143,7 +143,7 @@ __device__ __forceinline__ void mpc_pg(const MpcState<R> &L, const R h[kMpcN], c
 #pragma unroll
             for (int jj = i; jj < kMpcN; ++jj)
                 acc = fmaf_t(h[jj - i], r[jj], acc);
-            dU[i] = vmin(vmax(fmaf_t(-L.step, acc, dU[i]), L.lo), L.hi);
+            dU[i] = vclamp(fmaf_t(-L.step, acc, dU[i]), L.lo, L.hi);
         }
     }
 }

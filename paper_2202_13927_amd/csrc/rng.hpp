@@ -45,6 +45,57 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
+// The same function for a counter whose words 0, 2 and 3 and key are the same on every
+// lane of the wave and whose word 1 differs (the per-sample noise blocks: sample pair,
+// patient, tag, block). Until word 1 has reached both multiplied words, some products and
+// XORs depend on wave-uniform values only: words 0 and 2 of round 1, word 2 of round 2 and
+// word 0 of round 3. Written with plain XORs, grouped so that the uniform operands meet
+// first, those stay on the scalar unit (the three-way XOR instruction is vector only and
+// takes at most one scalar operand). The result is bit-identical to philox4x32_10.
+__device__ __forceinline__ U4 philox4x32_10_lane1(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t k0,
+                                                  uint32_t k1)
+{
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u, W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    // round 1: both products uniform; the new word 0 takes the lane's word 1
+    uint64_t a = (uint64_t)M0 * c0, b = (uint64_t)M1 * c2;
+    uint32_t n0 = c1 ^ ((uint32_t)(b >> 32) ^ k0);
+    uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)b; c3 = (uint32_t)a; c0 = n0; c2 = n2;
+    k0 += W0; k1 += W1;
+    // round 2: word 2 (and so the product b) still uniform, and so are words 1 and 3
+    a = (uint64_t)M0 * c0;
+    b = (uint64_t)M1 * c2;
+    n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+    n2 = (uint32_t)(a >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)b; c3 = (uint32_t)a; c0 = n0; c2 = n2;
+    k0 += W0; k1 += W1;
+    // round 3: word 0 (and so the product a) and word 1 uniform
+    a = (uint64_t)M0 * c0;
+    b = (uint64_t)M1 * c2;
+    n0 = (uint32_t)(b >> 32) ^ (c1 ^ k0);
+    n2 = c3 ^ ((uint32_t)(a >> 32) ^ k1);
+    c1 = (uint32_t)b; c3 = (uint32_t)a; c0 = n0; c2 = n2;
+    k0 += W0; k1 += W1;
+    // round 4: only word 3 uniform
+    a = (uint64_t)M0 * c0;
+    b = (uint64_t)M1 * c2;
+    n0 = xor3((uint32_t)(b >> 32), c1, k0);
+    n2 = (uint32_t)(a >> 32) ^ (c3 ^ k1);
+    c1 = (uint32_t)b; c3 = (uint32_t)a; c0 = n0; c2 = n2;
+    k0 += W0; k1 += W1;
+    // rounds 5..10: every word differs per lane
+#pragma unroll
+    for (int r = 4; r < 10; ++r) {
+        a = (uint64_t)M0 * c0;
+        b = (uint64_t)M1 * c2;
+        n0 = xor3((uint32_t)(b >> 32), c1, k0);
+        n2 = xor3((uint32_t)(a >> 32), c3, k1);
+        c1 = (uint32_t)b; c3 = (uint32_t)a; c0 = n0; c2 = n2;
+        k0 += W0; k1 += W1;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
 // Uniform on (0, 1): (2m + 1) 2^-24 with m the top 23 bits -- exact in both precisions.
 // FP32: the bit pattern 1 + m 2^-23 minus (1 - 2^-24) is that value, and the
 // subtraction is exact because the result has at most 24 significant bits.

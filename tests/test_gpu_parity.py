@@ -166,8 +166,10 @@ def test_edge_cases_fp64(gpu, orc, case):
     s, g = run_gpu(gpu, t)
     o = orc.simulate(t, threads=THREADS, guard_rel=1e-9)
     assert np.array_equal(g["status"], o["status"])
-    if case == "infeasible_nominal":
+    if case == "infeasible_nominal":   # non-finite from the start: lowest range, endless low runs
         assert np.all(g["status"] & 4) and np.all(g["status"] & 1)
+        for k in ("bins", "events"):
+            assert np.array_equal(g[k], o[k]), k
         return
     ok = o["n_near"] == 0
     assert ok.mean() > 0.99

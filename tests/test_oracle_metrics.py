@@ -20,13 +20,13 @@ EDGES = (3.0, 3.9, 10.0, 13.9)
 
 def brute_force(g):
     bins = np.zeros(5, int)
-    bins[0] = np.sum(g < 3.0)
+    bins[0] = np.sum(~(g >= 3.0))     # below the first edge, or not a number
     bins[1] = np.sum((g >= 3.0) & (g < 3.9))
     bins[2] = np.sum((g >= 3.9) & (g <= 10.0))
     bins[3] = np.sum((g > 10.0) & (g <= 13.9))
     bins[4] = np.sum(g > 13.9)
     ev = []
-    for cond in (g < 3.9, g < 3.0, g > 13.9):
+    for cond in (~(g >= 3.9), ~(g >= 3.0), g > 13.9):   # "below" = not at or above
         runs, n = 0, 0
         for c in cond:
             n = n + 1 if c else 0
@@ -54,6 +54,24 @@ def test_accumulators_equal_brute_force(orc, noisy):
         seen |= set(np.nonzero(bins)[0])
         assert r["sum_u"][j] == pytest.approx(r["traj_u"][j].sum() * 5.0, rel=1e-12)
     assert seen == {0, 1, 2, 3, 4}
+
+
+def test_non_finite_glucose_counts_as_lowest(orc):
+    """A patient with no basal state (nominal vector infeasible) has a non-finite state from
+    the start: every sample falls in the lowest range, the runs below 3.9 and 3.0 never end
+    (one event each), and the non-finite and resample status bits are set."""
+    t = W.with_(W.c1_fp64_pid(), n_patients=3, n_days=1, cv=1e-9,
+                nominal=[W.NOMINAL[0], W.NOMINAL[0] * 1.5, *W.NOMINAL[2:]])
+    r = orc.simulate(t, n_traj=3, threads=3)
+    K = r["bins"].sum(1)[0]
+    assert K == 288
+    for j in range(3):
+        assert not np.isfinite(r["traj_g"][j]).any()
+        assert np.array_equal(r["bins"][j], [K, 0, 0, 0, 0])
+        assert np.array_equal(r["events"][j], [1, 1, 0])
+        assert r["status"][j] & 1 and r["status"][j] & 4
+        bins, ev, *_ = brute_force(r["traj_g"][j])
+        assert np.array_equal(bins, r["bins"][j]) and np.array_equal(ev, r["events"][j])
 
 
 def test_meal_draws(orc):
