@@ -397,14 +397,14 @@ template <typename R>
 __device__ __forceinline__ bool all_finite(const State<R> &s)
 {
     return isfinite(s.D1s) && isfinite(s.D2) && isfinite(s.S1s) && isfinite(s.S2s) && isfinite(s.I) &&
-           isfinite(s.x1h) && isfinite(s.x2h) && isfinite(s.e3) && isfinite(s.Q1) && isfinite(s.Q2) &&
+           isfinite(s.x1h) && isfinite(s.x2s) && isfinite(s.e3) && isfinite(s.Q1) && isfinite(s.Q2) &&
            isfinite(s.GIs);
 }
 
 // Loop-carried state of one patient besides the model state: controller, meal queue,
 // metric accumulators.
 template <typename R> struct Lane {
-    R integ, y_prev;
+    R pid_b, y_prev;   // PID: the part of the unclamped output fixed before y_k (below), y_k-1
     int32_t c30, c39, c100, c139;                 // cumulative edge counters (bins by differences)
     int32_t r_hypo, r_sev, r_hyper, e_hypo, e_sev, e_hyper;
     double sum_g, sum_u;
@@ -415,7 +415,7 @@ template <typename R> struct Lane {
 
 // Per-patient constants of the controller and of the sampled inputs.
 template <typename R> struct CtrlConst {
-    R kp, ki, kd_ts, umax, ub, sp, u_open, ts;
+    R kpd, kd_ts, kits, kits_sp, umax, ub, u_open;   // PID in the form below; output bounds; open loop
     R k_sig;          // Box-Muller constant giving normals scaled by sqrt(h) sigma
     R sig_sqh, sqrt_r;
     double ts_d;
@@ -437,7 +437,7 @@ template <typename R> struct CtrlConst {
 // is read from them (the coefficients below undo the state scaling).
 template <typename R> struct PolicyLane {
     R yh[5];                 // y_k-1 .. y_k-5
-    R ins[6], ins0;          // f6 = ins . (S1s, S2s, I, x1h, x2h, e3) + ins0
+    R ins[6], ins0;          // f6 = ins . (S1s, S2s, I, x1h, x2s, e3) + ins0
     R meal_d1, meal_d2, wbar;   // f7 = D1s meal_d1 + D2 meal_d2 + dhat wbar
     R st[4];
     R kg[kNx];               // Kalman gain (learned controller: held in registers)
@@ -495,7 +495,7 @@ __device__ __forceinline__ void policy_features(const PolicyLane<R> &P, const St
     a6 = fmaf_t(P.ins[1], s.S2s, a6);
     a6 = fmaf_t(P.ins[2], s.I, a6);
     a6 = fmaf_t(P.ins[3], s.x1h, a6);
-    a6 = fmaf_t(P.ins[4], s.x2h, a6);
+    a6 = fmaf_t(P.ins[4], s.x2s, a6);
     f[6] = fmaf_t(P.ins[5], s.e3, a6);
     f[7] = fmaf_t(s.D1s, P.meal_d1, fmaf_t(s.D2, P.meal_d2, dr * P.wbar));
 #pragma unroll
@@ -685,13 +685,15 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
 
     R u, label = R(0);
     if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
+        // u = u_b + kp e_k + ki sum_{i<k} ts e_i + kd (y_k - y_k-1)/ts with e = y - sp,
+        // clamped to [0, umax]; the integral grows only while u is not clamped. Regrouped
+        // as pid_b + (kp + kd/ts) y_k - (kd/ts) y_k-1 with pid_b = u_b - kp sp + ki sum ts e_i.
         if (k == 0)
             L.y_prev = y;
-        const R e = y - cc.sp;
-        const R u_unc = cc.ub + cc.kp * e + cc.ki * L.integ + cc.kd_ts * (y - L.y_prev);
+        const R u_unc = fmaf_t(cc.kpd, y, fmaf_t(-cc.kd_ts, L.y_prev, L.pid_b));
         u = vclamp(u_unc, R(0), cc.umax);
-        if (u_unc >= R(0) && u_unc <= cc.umax)
-            L.integ += e * cc.ts;
+        if (u == u_unc)   // not clamped (a NaN u_unc is clamped to 0 and never integrates)
+            L.pid_b = fmaf_t(cc.kits, y, L.pid_b - cc.kits_sp);
         L.y_prev = y;
     } else if (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
         u = mpc_step<R>((const R *)a.mpc, a.n, j, ms, mplan, c, lin, R(a.h), R(a.h * a.ag), a.em_per_ctrl, y, dr,
@@ -820,13 +822,13 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
             fb[q] = (double)M[(int64_t)(kMFbar + q) * a.n + j];
         const double ti = p[kTmaxI], vi = p[kVI] * p[kBW], h = a.h, egp0 = p[kEGP0] * p[kBW];
         const double c_ui = h / (ti * vi), b_i = h / ti;
-        // unscaled states: S1 = S1s/(c_ui b_i), S2 = S2s/c_ui, x1 = x1h/h, x2 = x2h/h,
+        // unscaled states: S1 = S1s/(c_ui b_i), S2 = S2s/c_ui, x1 = x1h/h, x2 = x2s h ka2 SID,
         // x3 = 1 - e3/(h EGP0); basal: S1* = S2* = u_b tmaxI, I*, x_j* = S_j I*
         pl.ins[0] = R(fb[kXS1] / (c_ui * b_i));
         pl.ins[1] = R(fb[kXS2] / c_ui);
         pl.ins[2] = R(fb[kXI]);
         pl.ins[3] = R(fb[kXx1] / h);
-        pl.ins[4] = R(fb[kXx2] / h);
+        pl.ins[4] = R(fb[kXx2] * h * p[kKa2] * p[kSID]);
         pl.ins[5] = R(-fb[kXx3] / (h * egp0));
         pl.ins0 = R(fb[kXx3] - (fb[kXS1] + fb[kXS2]) * ub_d * ti - fb[kXI] * istar -
                     (fb[kXx1] * p[kSIT] + fb[kXx2] * p[kSID] + fb[kXx3] * p[kSIE]) * istar);
@@ -844,14 +846,15 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     // the controller's own basal rate: the patient's, or a mis-set one (basal_scale != 1,
     // PID and open loop only; Sec. IV-E trial B underestimates it by 50 %)
     const double ubc = a.basal_scale * ub_d;
-    cc.kp = R(a.kp * ubc);
-    cc.ki = R(a.ki * ubc);
-    cc.kd_ts = R(a.kd * ubc / (double)a.ts_min);
+    const double kp = a.kp * ubc, ki = a.ki * ubc, kd_ts = a.kd * ubc / (double)a.ts_min;
+    cc.kpd = R(kp + kd_ts);
+    cc.kd_ts = R(kd_ts);
+    cc.kits = R(ki * a.ts_min);
+    cc.kits_sp = R(ki * a.ts_min * a.setpoint);
+    L.pid_b = R(ubc - kp * a.setpoint);
     cc.umax = R(a.umax_rel * ubc);
     cc.ub = R(ubc);
-    cc.sp = R(a.setpoint);
     cc.u_open = R(a.u_rel * ubc);
-    cc.ts = R(a.ts_min);
     cc.k_sig = Rng<R>::scaled_const(a.sig_sqh);
     cc.sig_sqh = R(a.sig_sqh);
     cc.sqrt_r = R(a.sqrt_r);
@@ -927,8 +930,18 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     a.status[j] = L.status;
 }
 
+// Waves per SIMD the plain kernels are compiled for: the FP32 open-loop and PID loops
+// without per-sample outputs fit in 128 registers without spilling, which lets four waves
+// share a SIMD; the rest keep the compiler's choice.
+template <typename R, int CTRL, int OUT>
+constexpr int sim_waves_per_simd()
+{
+    return (sizeof(R) == 4 && CTRL <= kCtrlPid && OUT == 0) ? 4 : 1;
+}
+
 template <typename R, int CTRL, bool NOISY, int OUT>
-__global__ __launch_bounds__(256) void simulate_kernel(const SimArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sim_waves_per_simd<R, CTRL, OUT>())))
+void simulate_kernel(const SimArgs a)
 {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if constexpr ((OUT & kOutPop) != 0) {
@@ -1142,7 +1155,8 @@ static int32_t *policy_counts(const SimArgs &a)
 // patient runs exactly the code of simulate_kernel, so results do not depend on the
 // batching.
 template <typename R, int CTRL, bool NOISY, int BLOCK>
-__global__ __launch_bounds__(BLOCK) void batch_kernel(const SimArgs *__restrict__ arms,
+__global__ __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(sim_waves_per_simd<R, CTRL, 0>())))
+void batch_kernel(const SimArgs *__restrict__ arms,
                                                       const BatchItem *__restrict__ items, int32_t n_items,
                                                       uint32_t *__restrict__ counter)
 {

@@ -57,14 +57,16 @@ enum : uint32_t { kStNonFinite = 1u, kStNegQ1 = 2u, kStResample = 4u };
 // Several states are carried pre-multiplied by the coefficient through which they act
 // on the next state, so that each linear update is a single FMA:
 //   D1s = (h/tmaxG) D1,  S1s = (h/(tmaxI VI)) (h/tmaxI) S1,  S2s = (h/(tmaxI VI)) S2,
-//   x1h = h x1,  x2h = h x2,  e3 = h EGP0 (1 - x3),  GIs = GI (tau VG)/h,
-// e3 being exactly the factor through which x3 acts on EGP. (x2 is not folded into
-// 1 - h k12 - h x2 the same way: that sum is ~0.93 while h x2 is ~0.004, and FP32 would
-// keep only four digits of x2.)
+//   x1h = h x1,  x2s = x2 / (h ka2 SID),  e3 = h EGP0 (1 - x3),  GIs = GI (tau VG)/h,
+// e3 being exactly the factor through which x3 acts on EGP. x2s is scaled so that its own
+// update is one FMA (x2s' = (1 - h ka2) x2s + I); where it acts on Q2, the factor
+// 1 - h k12 - h x2 = (1 - h k12) - (h^2 ka2 SID) x2s is one FMA per step and is not carried
+// as a state (that sum is ~0.93 while h x2 is ~0.004, and FP32 would keep only four digits
+// of x2).
 // Unscaled values are recovered only where they are observed (G at the samples, GI for
 // the sensor).
 template <typename R> struct State {
-    R D1s, D2, S1s, S2s, I, x1h, x2h, e3, Q1, Q2, GIs;
+    R D1s, D2, S1s, S2s, I, x1h, x2s, e3, Q1, Q2, GIs;
 };
 
 // Per-patient constants of the EM step; everything that multiplies h is prescaled.
@@ -73,7 +75,7 @@ template <typename R> struct StepConst {
     R a_i;             // 1 - h/tmaxI
     R a_e;             // 1 - h ke
     R a1, hb1;         // 1 - h ka1, h^2 ka1 SIT                     (x1h update)
-    R a2, hb2;         // 1 - h ka2, h^2 ka2 SID                     (x2h update)
+    R a2, hb2;         // 1 - h ka2, h^2 ka2 SID                     (x2s update; h x2 = hb2 x2s)
     R a3, b3e, c3;     // 1 - h ka3, h EGP0 h ka3 SIE, h EGP0 h ka3 (e3 update)
     R a_12, hk12;      // 1 - h k12, h k12
     R f01h, f01h_q;    // h F01, h F01/(4.5 VG)      (h F01c = min(h F01, Q1 h F01/(4.5 VG)))
@@ -99,7 +101,7 @@ __device__ __forceinline__ void basal_state(const double *p, double I, double ub
     s.S2s = R(c_ui * ub * ti);
     s.I = R(I);
     s.x1h = R(h * x1);
-    s.x2h = R(h * x2);
+    s.x2s = R(I / (h * p[kKa2]));   // x2 / (h ka2 SID) with x2 = SID I
     s.e3 = R(h * p[kEGP0] * p[kBW] * (1.0 - x3));
     s.Q1 = R(q1);
     s.Q2 = R(q1 * x1 / (p[kK12] + x2));
@@ -151,7 +153,7 @@ __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R du
     const R hf01c = vmin(c.f01h, s.Q1 * c.f01h_q);                   // h F01c
     const R hfr = vmax(R(0), fmaf_t(s.Q1, c.fr1, -c.fr0));           // h F_R
     const R Q1n = ((fmaf_t(-s.x1h, s.Q1, s.Q1) - hf01c) - hfr) + side;
-    const R Q2n = fmaf_t(s.Q2, c.a_12 - s.x2h, t);
+    const R Q2n = fmaf_t(s.Q2, fmaf_t(-c.hb2, s.x2s, c.a_12), t);
     const R GIn = fmaf_t(s.GIs, c.a_c, s.Q1);
     const R D2n = fmaf_t(s.D2, c.a_g, s.D1s);
     const R D1n = fmaf_t(s.D1s, c.a_g, dd);
@@ -159,10 +161,10 @@ __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R du
     const R S1n = fmaf_t(s.S1s, c.a_i, du);
     const R In = fmaf_t(s.I, c.a_e, s.S2s);
     const R x1n = fmaf_t(s.x1h, c.a1, s.I * c.hb1);
-    const R x2n = fmaf_t(s.x2h, c.a2, s.I * c.hb2);
+    const R x2n = fmaf_t(s.x2s, c.a2, s.I);
     const R e3n = fmaf_t(s.e3, c.a3, fmaf_t(-c.b3e, s.I, c.c3));
     s.D1s = D1n; s.D2 = D2n; s.S1s = S1n; s.S2s = S2n; s.I = In;
-    s.x1h = x1n; s.x2h = x2n; s.e3 = e3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
+    s.x1h = x1n; s.x2s = x2n; s.e3 = e3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
 }
 
 }  // namespace vct
