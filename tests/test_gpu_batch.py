@@ -160,3 +160,38 @@ def test_trial_a_vs_b_arms(T, orc):
             assert np.array_equal(g[k][ok], o[k][ok]), k
         assert np.allclose(g["sum_u"], o["sum_u"], rtol=1e-9)
     assert got[1]["sum_u"].sum() < got[0]["sum_u"].sum()
+
+
+def test_scenarios_full_size_sampled(T, orc):
+    """Trial A vs trial B at the benchmark's size and launch (two arms of 1,000,000 patients x
+    364 days, Northern-European protocol, FP32, one autotuned batched launch): sampled patients
+    of each arm against the oracle one by one; trial B delivers less insulin to every sampled
+    patient and to the population."""
+    a = W.nordic_year()
+    arms = [a, W.with_(a, basal_scale=0.5)]
+    _say("[gpu] trial A vs B at 2 x 1,000,000 x 364 d, one batched launch")
+    bt = T.Batch(arms)
+    try:
+        bt.run()
+        sums = bt.summaries()
+        got = [T.to_host(b) for b in bt.bufs]
+    finally:
+        bt.close()
+    n = a["n_patients"]
+    idx = np.linspace(0, n - 1, 10).astype(int)
+    for t, s, g in zip(arms, sums, got):
+        K = s["n_samples"]
+        assert s["n_patients"] == n and sum(s["bins"]) == n * K
+        dt, du = [], []
+        for i in idx:
+            o = orc.simulate(t, first=int(i), count=1, threads=1)
+            assert g["status"][i] == o["status"][0]
+            dt.append((int(g["bins"][i, 2]) - int(o["bins"][0, 2])) / K)
+            du.append(g["sum_u"][i] / o["sum_u"][0] - 1.0)
+        dt, du = np.array(dt), np.array(du)
+        _say("scenario arm", t.get("basal_scale", 1.0), "sampled |dTIR| max", np.abs(dt).max(),
+             "insulin rel. diff. max", np.abs(du).max())
+        assert np.abs(dt).max() < 5e-3 and abs(dt.mean()) < 2e-3
+        assert np.abs(du).max() < 2e-2
+    assert np.all(got[1]["sum_u"][idx] < got[0]["sum_u"][idx])
+    assert sums[1]["mean_insulin"] < sums[0]["mean_insulin"] and sums[1]["mean_tir"] < sums[0]["mean_tir"]

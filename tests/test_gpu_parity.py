@@ -247,6 +247,37 @@ def test_nordic_fp32_stochastic(gpu, orc):
     assert np.array_equal(g["status"], o["status"])
 
 
+def test_nordic_full_size_sampled(gpu, orc):
+    """The Northern-European year at the benchmark's size and launch (1,000,000 patients x 364
+    days, FP32, PID): patients spread over the index range are recomputed by the oracle one by
+    one. The same launch with the population BG per sample on gives the same per-patient
+    records, counts every sample once in its pooled bins, its mean curve averages to the
+    summary's mean BG, and the upper curve of the span ends at K."""
+    t = W.nordic_year()
+    s, g = run_gpu(gpu, t)
+    n, K = t["n_patients"], g["K"]
+    assert K == 104_832 and s["n_patients"] == n and sum(s["bins"]) == n * K
+    dt = []
+    for i in np.linspace(0, n - 1, 16).astype(int):
+        o = orc.simulate(t, first=int(i), count=1, threads=1)
+        assert g["status"][i] == o["status"][0]
+        dt.append((int(g["bins"][i, 2]) - int(o["bins"][0, 2])) / K)
+    dt = np.array(dt)
+    _say("Nordic full-size sampled |dTIR| max", np.abs(dt).max(), "mean", dt.mean())
+    assert np.abs(dt).max() < 5e-3 and abs(dt.mean()) < 2e-3
+    _say("[gpu] the same launch with the population BG per sample")
+    b = gpu.TrialBuffers(t, popbg=True)
+    gpu.run(t, bufs=b)
+    p = gpu.to_host(b)
+    for k in ("bins", "events", "sum_g", "min_g", "argmin_k", "sum_u", "status"):
+        assert np.array_equal(p[k], g[k]), k
+    assert int(p["pop_hist"].sum()) == n * K
+    assert p["pop_mean"].mean() == pytest.approx(s["mean_bg"], rel=1e-9)
+    assert np.all(p["pop_min"] <= p["pop_mean"]) and np.all(p["pop_mean"] <= p["pop_max"])
+    assert p["pop_min"].min() == pytest.approx(float(np.nanmin(g["min_g"])), rel=1e-12)
+    assert p["span_max"][-1] == K and np.all(np.diff(p["span_min"]) >= 0) and np.all(p["span_min"] <= p["span_max"])
+
+
 def test_nordic_rejects_bad_settings(gpu):
     """Invalid protocol settings are refused before any device work."""
     from paper_2202_13927_amd import vct
