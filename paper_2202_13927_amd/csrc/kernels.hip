@@ -103,22 +103,78 @@ __device__ __forceinline__ unsigned long long order_key(double g)
     const unsigned long long b = (unsigned long long)__double_as_longlong(g);
     return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
 }
-
-__device__ __forceinline__ void pop_accumulate(const SimArgs &a, int32_t k, double g, bool live)
+// The same order on FP32 values (a float and its FP64 conversion have the same rank).
+__device__ __forceinline__ uint32_t order_key32(float g)
 {
-    long long q = live ? __double2ll_rn(g * 4294967296.0) : 0ll;
-    unsigned long long mn = live ? order_key(g) : ~0ull, mx = live ? order_key(g) : 0ull;
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
-        q += __shfl_xor(q, off);
-        const unsigned long long omn = __shfl_xor(mn, off), omx = __shfl_xor(mx, off);
-        mn = omn < mn ? omn : mn;
-        mx = omx > mx ? omx : mx;
+    const uint32_t b = __float_as_uint(g);
+    return (b >> 31) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float order_key32_inv(uint32_t key)
+{
+    return __uint_as_float((key >> 31) ? (key & 0x7FFFFFFFu) : ~key);
+}
+
+// Wave reductions without LDS: two quad exchanges, the half-row and the row mirror leave
+// every lane of a 16-lane row with the row's result (DPP moves, all source lanes inside the
+// row); the four rows are read into scalar registers and combined there. All 64 lanes must
+// be active. The result is the same on every lane.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL>
+__device__ __forceinline__ unsigned long long dpp64(unsigned long long v)
+{
+    const uint32_t lo = dpp32<CTRL>((uint32_t)v), hi = dpp32<CTRL>((uint32_t)(v >> 32));
+    return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ uint32_t rows32(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ unsigned long long rows64(unsigned long long v, int l)
+{
+    return ((unsigned long long)rows32((uint32_t)(v >> 32), l) << 32) | rows32((uint32_t)v, l);
+}
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T x, Op op)
+{
+    if constexpr (sizeof(T) == 4) {
+        x = op(x, dpp32<0xB1>(x));    // quad_perm [1,0,3,2]
+        x = op(x, dpp32<0x4E>(x));    // quad_perm [2,3,0,1]
+        x = op(x, dpp32<0x141>(x));   // row_half_mirror
+        x = op(x, dpp32<0x140>(x));   // row_mirror
+        return op(op(rows32(x, 0), rows32(x, 16)), op(rows32(x, 32), rows32(x, 48)));
+    } else {
+        x = op(x, dpp64<0xB1>(x));
+        x = op(x, dpp64<0x4E>(x));
+        x = op(x, dpp64<0x141>(x));
+        x = op(x, dpp64<0x140>(x));
+        return op(op(rows64(x, 0), rows64(x, 16)), op(rows64(x, 32), rows64(x, 48)));
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void pop_accumulate(const SimArgs &a, int32_t k, R G, bool live)
+{
+    using u64 = unsigned long long;
+    const double g = (double)G;
+    const u64 q = live ? (u64)__double2ll_rn(g * 4294967296.0) : 0ull;
+    const u64 sum = wave_reduce(q, [](u64 x, u64 y) { return x + y; });
+    u64 mn, mx;
+    if constexpr (sizeof(R) == 4) {   // FP32 keys; the extremes converted once
+        const uint32_t key = order_key32(G);
+        const uint32_t kmn = wave_reduce(live ? key : ~0u, [](uint32_t x, uint32_t y) { return x < y ? x : y; });
+        const uint32_t kmx = wave_reduce(live ? key : 0u, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
+        mn = kmn == ~0u ? ~0ull : order_key((double)order_key32_inv(kmn));
+        mx = kmx == 0u ? 0ull : order_key((double)order_key32_inv(kmx));
+    } else {
+        const u64 key = order_key(g);
+        mn = wave_reduce(live ? key : ~0ull, [](u64 x, u64 y) { return x < y ? x : y; });
+        mx = wave_reduce(live ? key : 0ull, [](u64 x, u64 y) { return x > y ? x : y; });
     }
     if ((threadIdx.x & 63) == 0) {
-        atomicAdd((unsigned long long *)&a.pop_sum[k], (unsigned long long)q);
-        atomicMin((unsigned long long *)&a.pop_min[k], mn);
-        atomicMax((unsigned long long *)&a.pop_max[k], mx);
+        atomicAdd((u64 *)&a.pop_sum[k], sum);
+        atomicMin((u64 *)&a.pop_min[k], mn);
+        atomicMax((u64 *)&a.pop_max[k], mx);
     }
 }
 
@@ -643,7 +699,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
     if (OUT & kOutPop) {
-        pop_accumulate(a, k, (double)G, live);
+        pop_accumulate<R>(a, k, G, live);
         if (live)
             atomicAdd(&ps.hist[pop_bin((double)G)], 1u);
         atomicAdd(&ps.span[span_bin((double)G) * 64 + ps.lane], 1u);   // this lane's own counters
