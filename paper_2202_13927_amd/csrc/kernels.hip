@@ -995,6 +995,14 @@ constexpr int sim_waves_per_simd()
     return (sizeof(R) == 4 && CTRL <= kCtrlPid && OUT == 0) ? 4 : 1;
 }
 
+// Workgroup size of simulate_kernel: one wave with the population curves on (its 14.4 KB of
+// LDS counters per wave then limit occupancy per wave, not per 4-wave group), else 256.
+template <int OUT>
+constexpr int sim_block()
+{
+    return (OUT & kOutPop) ? 64 : 256;
+}
+
 template <typename R, int CTRL, bool NOISY, int OUT>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sim_waves_per_simd<R, CTRL, OUT>())))
 void simulate_kernel(const SimArgs a)
@@ -1003,8 +1011,8 @@ void simulate_kernel(const SimArgs a)
     if constexpr ((OUT & kOutPop) != 0) {
         // the population reduction needs every lane of a wave: lanes past the last patient
         // replay it and write nothing; a wave wholly past it exits
-        __shared__ uint32_t hist[4][kPopBins];
-        __shared__ uint32_t span[4][kSpanBins * 64];
+        __shared__ uint32_t hist[sim_block<OUT>() / 64][kPopBins];
+        __shared__ uint32_t span[sim_block<OUT>() / 64][kSpanBins * 64];
         if ((j & ~(int64_t)63) >= a.n)
             return;
         const bool live = j < a.n;
@@ -1326,8 +1334,9 @@ static void launch_sim_o(const SimArgs &a, hipStream_t s)
         hipLaunchKernelGGL((simulate_policy_kernel<R, NOISY, OUT>), dim3(blocks), dim3(kPolicyBlock), 0, s, a,
                            (const int32_t *)counts, (int32_t)nb, (uint32_t *)(counts + nb + 1));
     } else {
-        const unsigned blocks = (unsigned)((a.n + 255) / 256);
-        hipLaunchKernelGGL((simulate_kernel<R, CTRL, NOISY, OUT>), dim3(blocks), dim3(256), 0, s, a);
+        constexpr int B = sim_block<OUT>();
+        const unsigned blocks = (unsigned)((a.n + B - 1) / B);
+        hipLaunchKernelGGL((simulate_kernel<R, CTRL, NOISY, OUT>), dim3(blocks), dim3(B), 0, s, a);
     }
 }
 
