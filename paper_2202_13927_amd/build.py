@@ -24,9 +24,16 @@ FLAGS = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-Wall",
          "-I", os.path.join(ROOT, "include")]
 
 
+# Per-source code-generation options: MFMA accumulators in VGPRs for the sources with MFMA
+# (the network kernels convert every accumulator with vector instructions, which cannot
+# read AGPRs; with AGPR accumulators each value needs a v_accvgpr_read first).
+VGPR_MFMA = ["-mllvm", "-amdgpu-mfma-vgpr-form"]
+EXTRA = {"kernels.hip": VGPR_MFMA, "mlp.hip": VGPR_MFMA}
+
+
 def _compile(src: str, verbose: bool) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [HIPCC, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *FLAGS, *EXTRA.get(src, []), "-c", os.path.join(CSRC, src), "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
