@@ -36,6 +36,7 @@ FLOP_PER_PATIENT_DAY = 1440 * 64 + 288 * (6 * 4.5 + 15)   # EM steps + normals +
 PEAK_FP32 = 157.3e12
 PEAK_FP32_NONPACKED = 78.6e12
 ORACLE_SAMPLE = (10000, 364)  # patients 0..9999 of the same trial, full horizon
+ORACLE_SAMPLE_1THREAD = 200   # the oracle's single-thread rate: patients 0..199, full horizon
 
 
 PROFILE = os.path.join(ROOT, "profiles", "simulate_kernel_paper_scale_1M_x_364d.md")
@@ -73,8 +74,20 @@ def cpu_baseline(trial: dict) -> dict:
     t0 = time.perf_counter()
     oracle.simulate(t, 0, n, threads=threads)
     dt = time.perf_counter() - t0
+    n1 = ORACLE_SAMPLE_1THREAD
+    t0 = time.perf_counter()
+    oracle.simulate(W.with_(trial, n_patients=n1, n_days=d), 0, n1, threads=1)
+    dt1 = time.perf_counter() - t0
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next(line.split(":", 1)[1].strip() for line in f if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": n * d / dt, "unit": "patient-days/s", "cores": threads, "kind": "oracle",
-            "sample": f"patients 0..{n - 1} of the trial, full {d}-day horizon, FP64 oracle ({dt:.1f} s)"}
+            "sample": f"patients 0..{n - 1} of the trial, full {d}-day horizon, FP64 oracle ({dt:.1f} s)",
+            "single_thread": {"value": n1 * d / dt1, "sample": f"patients 0..{n1 - 1}, {d} days, 1 thread ({dt1:.1f} s)"},
+            "cpu_model": cpu}
 
 
 def batched(stream) -> dict:
