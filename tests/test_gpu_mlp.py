@@ -370,6 +370,29 @@ def test_closed_loop_matches_oracle(G, orc, precision):
     assert np.allclose(u0_g, u0_o, rtol=2e-2)
 
 
+def test_learned_full_size_sampled(G, orc):
+    """The learned controller at the benchmark's evaluation size and launch (1,000,000 patients
+    x 28 days, FP32, the persistent queue of out-of-box waves and 64-patient tiles): patients
+    spread over the index range against the oracle one by one, with the same network."""
+    t = _mlp_trial(precision=W.FP32, n_patients=1_000_000, n_days=28)
+    _say("[gpu] learned controller, 1,000,000 x 28 d FP32")
+    g, ref_net = _run_mlp(G, t, W.synthetic_policy_net(71))
+    K = g["K"]
+    assert K == 28 * 288 and len(g["fallback"]) == t["n_patients"]
+    dt, fb_g, fb_o = [], 0, 0
+    for i in np.linspace(0, t["n_patients"] - 1, 12).astype(int):
+        o = orc.simulate(t, first=int(i), count=1, threads=1, mlp=ref_net)
+        assert (g["fallback"][i] == K) == (o["fallback"][0] == K), i     # outside the box: the MPC throughout
+        assert g["status"][i] == o["status"][0]
+        fb_g += int(g["fallback"][i])
+        fb_o += int(o["fallback"][0])
+        dt.append((int(g["bins"][i, 2]) - int(o["bins"][0, 2])) / K)
+    dt = np.array(dt)
+    _say("   sampled |dTIR| max", np.abs(dt).max(), "mean", dt.mean(), "fallbacks gpu", fb_g, "oracle", fb_o)
+    assert np.abs(dt).max() < 5e-2 and abs(dt.mean()) < 1e-2
+    assert abs(fb_g - fb_o) <= 0.05 * fb_o + 50
+
+
 def test_training_reduces_loss_and_is_deterministic(G):
     """Adam on a smooth synthetic target: the minibatch loss falls by 10x; two runs from the
     same initial weights and seed give bitwise equal weights (fixed-order reductions)."""
