@@ -229,6 +229,7 @@ def learned_leg(full: bool) -> dict:
     train_s = time.perf_counter() - t0
     n, days, slices = (1_000_000, 364, 2) if full else (1_000_000, 28, 1)
     tot = {"mpc": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}, "mlp": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}}
+    setup_s = 0.0
     fb = 0.0
     always = 0
     for i in range(slices):
@@ -239,6 +240,7 @@ def learned_leg(full: bool) -> dict:
             tot[arm]["bins"] = [a + b for a, b in zip(tot[arm]["bins"], r[arm]["bins"])]
             tot[arm]["events"] = [a + b for a, b in zip(tot[arm]["events"], r[arm]["events"])]
         fb += r["mlp"]["fallback_rate"] / slices
+        setup_s += r["mpc"]["setup_s"]
         always += r["mlp"]["patients_always_fallback"]
         log(f"[bench] learned: slice {i + 1}/{slices} done (MPC {r['mpc']['sim_s']:.1f} s, "
             f"network {r['mlp']['sim_s']:.1f} s)")
@@ -251,6 +253,9 @@ def learned_leg(full: bool) -> dict:
             "speedup": tot["mpc"]["s"] / tot["mlp"]["s"],
             "mpc_patient_days_per_s": pd / tot["mpc"]["s"], "mlp_patient_days_per_s": pd / tot["mlp"]["s"],
             "mpc_sim_s": tot["mpc"]["s"], "mlp_sim_s": tot["mlp"]["s"], "fallback_rate": fb,
+            # the FP64 per-patient MPC setup, once per population (both arms need it; not in
+            # the simulation times above)
+            "mpc_setup_s": setup_s,
             "patients_always_fallback": always, "bins_mpc": tot["mpc"]["bins"], "bins_mlp": tot["mlp"]["bins"],
             "train_rows": rep["rounds"][-1]["rows"], "train_s": train_s,
             "train_mse": rep["rounds"][-1]["mse_full"]}

@@ -90,18 +90,19 @@ def train_policy(train_trial: dict, epochs: float = 10.0, batch: int = 4096, lr:
 
 def evaluate(pol: PL.Policy, mpc_trial: dict, log=print) -> dict:
     """Step 3 on the evaluation population; each arm is one simulation launch, timed with
-    HIP events (MPC setup and the reduction are outside the timed region)."""
+    HIP events. The MPC setup (both arms need it: the learned arm for its fallback and
+    inputs) is timed separately; the reduction is outside the timed region."""
     mlp_trial = W.with_(mpc_trial, ctrl_kind=W.CTRL_MLP)
     out = {}
     for name, t in (("mpc", mpc_trial), ("mlp", mlp_trial)):
         bufs = T.TrialBuffers(t)
         pop = T.create_population(t, bufs)
-        T.mpc_setup(t, pop, bufs)
         torch.cuda.synchronize()
+        _, setup_s = _timed(lambda: T.mpc_setup(t, pop, bufs))
         _, sim_s = _timed(lambda: T.simulate(t, pop, bufs, mlp_blob=pol.blob if name == "mlp" else None))
         summ = T.read_metrics(bufs)
         vct.vct_destroy_population(pop)
-        r = {"sim_s": sim_s, "tir": summ["mean_tir"], "bins": summ["bins"], "events": summ["events"],
+        r = {"sim_s": sim_s, "setup_s": setup_s, "tir": summ["mean_tir"], "bins": summ["bins"], "events": summ["events"],
              "mean_bg": summ["mean_bg"], "q_frac": summ["q_frac"], "worst_min_g": summ["worst_min_g"]}
         if name == "mlp":
             fb = bufs.fallback.double().sum().item()
