@@ -356,9 +356,19 @@ vct_status vct_mpc_setup(const vct_population *pop, const vct_controller *ctrl, 
     a.umax_rel = ctrl->umax_rel;
     a.riccati_iters = 500;
     a.power_iters = 100;
-    hipError_t e = vct::launch_mpc_setup(a, sim->precision, mpc_dev, (hipStream_t)stream);
+    // FP64 hand-over of A between the setup kernel and the Riccati kernel (stream-ordered,
+    // freed after the launches)
+    hipStream_t s = (hipStream_t)stream;
+    const size_t a64_bytes = (size_t)vct::kNx * vct::kNx * sizeof(double) * (size_t)pop->n;
+    hipError_t e = hipMallocAsync((void **)&a.a64, a64_bytes, s);
+    if (e != hipSuccess)
+        return fail(VCT_ENOMEM, "vct_mpc_setup: scratch of %zu bytes: %s", a64_bytes, hipGetErrorString(e));
+    e = vct::launch_mpc_setup(a, sim->precision, mpc_dev, s);
+    const hipError_t e2 = hipFreeAsync(a.a64, s);
     if (e != hipSuccess)
         return hip_fail(e, "vct_mpc_setup: launch");
+    if (e2 != hipSuccess)
+        return hip_fail(e2, "vct_mpc_setup: free");
     return VCT_OK;
 }
 

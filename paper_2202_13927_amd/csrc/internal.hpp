@@ -90,6 +90,7 @@ struct MpcSetupArgs {
     double sigma_q1, cgm_var;
     double rho, umax_rel;
     int32_t riccati_iters, power_iters;
+    double *a64;           // FP64 scratch [kNx * kNx][n]: A, from the setup kernel to the Riccati kernel
 };
 
 struct MlpTrain {            // views into the caller's training buffer + the inference blob
@@ -101,6 +102,8 @@ struct MlpTrain {            // views into the caller's training buffer + the in
 hipError_t launch_population(const PopArgs &a, hipStream_t s);
 hipError_t launch_simulate(const SimArgs &a, int precision, hipStream_t s);
 hipError_t launch_batch(const BatchLaunch &b, hipStream_t s);
+// Two launches: the per-lane setup (everything but the Kalman gain; writes A in FP64 to
+// a.a64), then the Riccati iteration with one 16-lane row per patient (writes the gain).
 hipError_t launch_mpc_setup(const MpcSetupArgs &a, int precision, void *out, hipStream_t s);
 hipError_t launch_mlp_init(const MlpTrain &t, uint32_t k0, uint32_t k1, hipStream_t s);
 size_t mlp_stats_scratch_bytes();

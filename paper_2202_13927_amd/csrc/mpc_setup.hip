@@ -7,7 +7,12 @@
 // the prediction of G = Q1/VG over 24 samples (Markov parameters h, free response F,
 // intake response w) condensed into Gamma^T F, Gamma^T w, Gamma^T 1; and the projected-
 // gradient step 1/(lambda_max(Gamma^T Gamma) + rho/u_b^2) with lambda from power
-// iteration; and the horizon means of the prediction rows and of the intake response. The matrices live in per-lane private arrays: this kernel runs once per trial.
+// iteration; and the horizon means of the prediction rows and of the intake response.
+// mpc_setup_kernel does all of it except the Kalman gain, one patient per lane with the
+// matrices in private arrays, and hands A over in FP64. The Riccati iteration, 500 steps of
+// two 11x11 products, runs in mpc_riccati_kernel with one patient per 16-lane row: lane r
+// holds row r of A and of P, and the rows another lane needs are broadcast inside the row
+// with DPP (row_newbcast), so the matrices stay in registers.
 #include "internal.hpp"
 #include "mpc.hpp"
 
@@ -48,6 +53,8 @@ __global__ __launch_bounds__(64) void mpc_setup_kernel(const MpcSetupArgs a, R *
     if (!(ub > 0.0)) {   // no basal state: a controller that holds nothing (the plant is NaN anyway)
         for (int r = 0; r < kMRows; ++r)
             out[(int64_t)r * n + j] = R(0);
+        for (int i = 0; i < NX * NX; ++i)
+            a.a64[(int64_t)i * n + j] = 0.0;
         return;
     }
     const double bw = p[kBW];
@@ -111,31 +118,9 @@ __global__ __launch_bounds__(64) void mpc_setup_kernel(const MpcSetupArgs a, R *
         mat_mul(A, M, A);
     }
 
-    // Kalman: prior covariance P <- A (P - P c c^T P / (c P c^T + R)) A^T + Q with c = e_GI
-    const double Rk = a.cgm_var > 1e-4 ? a.cgm_var : 1e-4;
-    const double qq1 = a.sigma_q1 * a.sigma_q1 * h * a.em_per_ctrl;
-    double P[NX * NX], T[NX * NX];
+    // A for the Kalman gain (mpc_riccati_kernel)
     for (int i = 0; i < NX * NX; ++i)
-        P[i] = 0.0;
-    for (int i = 0; i < NX; ++i)
-        P[i * NX + i] = 1e-6;
-    P[kXQ1 * NX + kXQ1] += qq1;
-    for (int it = 0; it < a.riccati_iters; ++it) {
-        const double s = P[kXGI * NX + kXGI] + Rk;
-        for (int r = 0; r < NX; ++r)
-            for (int c = 0; c < NX; ++c)
-                T[r * NX + c] = P[r * NX + c] - P[r * NX + kXGI] * P[kXGI * NX + c] / s;
-        mat_mul(A, T, T);
-        // P = T A^T + Q
-        for (int r = 0; r < NX; ++r)
-            for (int c = 0; c < NX; ++c) {
-                double acc = 0.0;
-                for (int q = 0; q < NX; ++q)
-                    acc = fma(T[r * NX + q], A[c * NX + q], acc);
-                P[r * NX + c] = acc + (r == c ? 1e-6 : 0.0) + (r == kXQ1 && c == kXQ1 ? qq1 : 0.0);
-            }
-    }
-    const double sk = P[kXGI * NX + kXGI] + Rk;
+        a.a64[(int64_t)i * n + j] = A[i];
 
     // prediction rows c_G A^(j+1); Markov parameters h_(j+1) = c_G A^j B; intake response c_G A^j E
     double row[NX], hm[kMpcN], wm[kMpcN];
@@ -196,7 +181,6 @@ __global__ __launch_bounds__(64) void mpc_setup_kernel(const MpcSetupArgs a, R *
     for (int i = 0; i < NX; ++i) {
         W(kMB + i, Bv[i]);
         W(kME + i, Ev[i]);
-        W(kMK + i, P[i * NX + kXGI] / sk);
     }
     for (int i = 0; i < kMpcN; ++i) {
         double gd = 0.0, g1 = 0.0;
@@ -235,13 +219,102 @@ __global__ __launch_bounds__(64) void mpc_setup_kernel(const MpcSetupArgs a, R *
     W(kMwbar, wacc / kMpcN);
 }
 
+// Lane Q's value of v, for every lane of its 16-lane row (DPP row_newbcast).
+template <int Q>
+__device__ __forceinline__ double row_bcast(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + Q, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + Q, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+// out[c] = row q of the matrix whose rows the lanes 0..10 of this row hold in v
+template <int Q>
+__device__ __forceinline__ void row_of(const double v[NX], double out[NX])
+{
+#pragma unroll
+    for (int c = 0; c < NX; ++c)
+        out[c] = row_bcast<Q>(v[c]);
+}
+
+// Kalman prior covariance P <- A (P - P c c^T P / (c P c^T + R)) A^T + Q with c = e_GI, from
+// P0 = Q, a fixed number of steps; gain K = P c / (c P c^T + R). One patient per 16-lane row,
+// lane r < 11 holding row r of A and of P (lanes 11..15 and rows past n carry zeros and write
+// nothing; every lane takes part in the broadcasts). Per step: T = P - P c c^T P / s (row
+// GI broadcast), U = A T (lane r combines the broadcast rows of T along its row of A), and
+// P = U A^T + Q computed by columns (lane r combines the broadcast rows of U with its row of
+// A, giving column r of P). P is symmetric, so column r serves as row r of the next step;
+// every product sums its terms in the same order as the plain row-by-row products.
+template <typename R>
+__global__ __launch_bounds__(256) void mpc_riccati_kernel(const MpcSetupArgs a, R *__restrict__ out)
+{
+    const int64_t n = a.n;
+    const int64_t j = (int64_t)blockIdx.x * 16 + (threadIdx.x >> 4);
+    const int r = threadIdx.x & 15;
+    const bool in = j < n && r < NX;
+    const double ub = j < n ? a.params[(int64_t)kUb * n + j] : 0.0;
+    double Ar[NX], Pr[NX];
+    const double h = a.h;
+    const double Rk = a.cgm_var > 1e-4 ? a.cgm_var : 1e-4;
+    const double qq1 = a.sigma_q1 * a.sigma_q1 * h * a.em_per_ctrl;
+#pragma unroll
+    for (int c = 0; c < NX; ++c) {
+        Ar[c] = in ? a.a64[(int64_t)(r * NX + c) * n + j] : 0.0;
+        Pr[c] = (in && r == c ? 1e-6 : 0.0) + (in && r == kXQ1 && c == kXQ1 ? qq1 : 0.0);
+    }
+    for (int it = 0; it < a.riccati_iters; ++it) {
+        double g[NX], Tr[NX], Ur[NX];
+        row_of<kXGI>(Pr, g);   // row GI of P
+        const double s = g[kXGI] + Rk;
+#pragma unroll
+        for (int c = 0; c < NX; ++c) {
+            Tr[c] = Pr[c] - Pr[kXGI] * g[c] / s;
+            Ur[c] = 0.0;
+        }
+        // U = A T
+#define VCT_U_STEP(Q)                                  \
+        {                                              \
+            double t[NX];                              \
+            row_of<Q>(Tr, t);                          \
+            _Pragma("unroll") for (int c = 0; c < NX; ++c) \
+                Ur[c] = fma(Ar[Q], t[c], Ur[c]);       \
+        }
+        VCT_U_STEP(0) VCT_U_STEP(1) VCT_U_STEP(2) VCT_U_STEP(3) VCT_U_STEP(4) VCT_U_STEP(5)
+        VCT_U_STEP(6) VCT_U_STEP(7) VCT_U_STEP(8) VCT_U_STEP(9) VCT_U_STEP(10)
+#undef VCT_U_STEP
+        // column r of P = U A^T + Q: entry (q0, r) from row q0 of U and row r of A
+#define VCT_P_STEP(Q)                                                                              \
+        {                                                                                          \
+            double u[NX];                                                                          \
+            row_of<Q>(Ur, u);                                                                      \
+            double acc = 0.0;                                                                      \
+            _Pragma("unroll") for (int q = 0; q < NX; ++q)                                         \
+                acc = fma(u[q], Ar[q], acc);                                                       \
+            Pr[Q] = acc + (in && Q == r ? 1e-6 : 0.0) + (in && Q == kXQ1 && r == kXQ1 ? qq1 : 0.0); \
+        }
+        VCT_P_STEP(0) VCT_P_STEP(1) VCT_P_STEP(2) VCT_P_STEP(3) VCT_P_STEP(4) VCT_P_STEP(5)
+        VCT_P_STEP(6) VCT_P_STEP(7) VCT_P_STEP(8) VCT_P_STEP(9) VCT_P_STEP(10)
+#undef VCT_P_STEP
+    }
+    // K = P e_GI / (P[GI][GI] + R): column GI of P, which lane GI holds
+    if (in && r == kXGI && ub > 0.0) {
+        const double sk = Pr[kXGI] + Rk;
+#pragma unroll
+        for (int i = 0; i < NX; ++i)
+            out[(int64_t)(kMK + i) * n + j] = R(Pr[i] / sk);
+    }
+}
+
 hipError_t launch_mpc_setup(const MpcSetupArgs &a, int precision, void *out, hipStream_t s)
 {
     const unsigned blocks = (unsigned)((a.n + 63) / 64);
-    if (precision == 1)
+    const unsigned rblocks = (unsigned)((a.n + 15) / 16);
+    if (precision == 1) {
         hipLaunchKernelGGL(mpc_setup_kernel<float>, dim3(blocks), dim3(64), 0, s, a, (float *)out);
-    else
+        hipLaunchKernelGGL(mpc_riccati_kernel<float>, dim3(rblocks), dim3(256), 0, s, a, (float *)out);
+    } else {
         hipLaunchKernelGGL(mpc_setup_kernel<double>, dim3(blocks), dim3(64), 0, s, a, (double *)out);
+        hipLaunchKernelGGL(mpc_riccati_kernel<double>, dim3(rblocks), dim3(256), 0, s, a, (double *)out);
+    }
     return hipGetLastError();
 }
 
