@@ -13,6 +13,8 @@
 // two 11x11 products, runs in mpc_riccati_kernel with one patient per 16-lane row: lane r
 // holds row r of A and of P, and the rows another lane needs are broadcast inside the row
 // with DPP (row_newbcast), so the matrices stay in registers.
+#include <utility>
+
 #include "internal.hpp"
 #include "mpc.hpp"
 
@@ -227,7 +229,7 @@ __device__ __forceinline__ double row_bcast(double v)
     const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + Q, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
-// out[c] = row q of the matrix whose rows the lanes 0..10 of this row hold in v
+// out[c] = row Q of the matrix whose rows the lanes 0..10 of this row hold in v
 template <int Q>
 __device__ __forceinline__ void row_of(const double v[NX], double out[NX])
 {
@@ -236,14 +238,51 @@ __device__ __forceinline__ void row_of(const double v[NX], double out[NX])
         out[c] = row_bcast<Q>(v[c]);
 }
 
+// U += A[r][Q] T[Q][:] (row Q of T broadcast); called for Q = 0, 1, ..., 10 in order
+template <int Q>
+__device__ __forceinline__ void u_term(const double Ar[NX], const double Tr[NX], double Ur[NX])
+{
+    double t[NX];
+    row_of<Q>(Tr, t);
+#pragma unroll
+    for (int c = 0; c < NX; ++c)
+        Ur[c] = fma(Ar[Q], t[c], Ur[c]);
+}
+template <int... Q>
+__device__ __forceinline__ void u_product(std::integer_sequence<int, Q...>, const double Ar[NX], const double Tr[NX],
+                                          double Ur[NX])
+{
+    (u_term<Q>(Ar, Tr, Ur), ...);
+}
+
+// (U A^T)[Q][r]: row Q of U (broadcast) with this lane's row r of A
+template <int Q>
+__device__ __forceinline__ void p_entry(const double Ur[NX], const double Ar[NX], double Pc[NX])
+{
+    double u[NX];
+    row_of<Q>(Ur, u);
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < NX; ++q)
+        acc = fma(u[q], Ar[q], acc);
+    Pc[Q] = acc;
+}
+template <int... Q>
+__device__ __forceinline__ void p_column(std::integer_sequence<int, Q...>, const double Ur[NX], const double Ar[NX],
+                                         double Pc[NX])
+{
+    (p_entry<Q>(Ur, Ar, Pc), ...);
+}
+
 // Kalman prior covariance P <- A (P - P c c^T P / (c P c^T + R)) A^T + Q with c = e_GI, from
 // P0 = Q, a fixed number of steps; gain K = P c / (c P c^T + R). One patient per 16-lane row,
 // lane r < 11 holding row r of A and of P (lanes 11..15 and rows past n carry zeros and write
 // nothing; every lane takes part in the broadcasts). Per step: T = P - P c c^T P / s (row
 // GI broadcast), U = A T (lane r combines the broadcast rows of T along its row of A), and
 // P = U A^T + Q computed by columns (lane r combines the broadcast rows of U with its row of
-// A, giving column r of P). P is symmetric, so column r serves as row r of the next step;
-// every product sums its terms in the same order as the plain row-by-row products.
+// A, giving column r of P). P is symmetric up to rounding, so column r serves as row r of
+// the next step; every product sums its terms in the same order as the plain row-by-row
+// products.
 template <typename R>
 __global__ __launch_bounds__(256) void mpc_riccati_kernel(const MpcSetupArgs a, R *__restrict__ out)
 {
@@ -270,30 +309,12 @@ __global__ __launch_bounds__(256) void mpc_riccati_kernel(const MpcSetupArgs a, 
             Tr[c] = Pr[c] - Pr[kXGI] * g[c] / s;
             Ur[c] = 0.0;
         }
-        // U = A T
-#define VCT_U_STEP(Q)                                  \
-        {                                              \
-            double t[NX];                              \
-            row_of<Q>(Tr, t);                          \
-            _Pragma("unroll") for (int c = 0; c < NX; ++c) \
-                Ur[c] = fma(Ar[Q], t[c], Ur[c]);       \
-        }
-        VCT_U_STEP(0) VCT_U_STEP(1) VCT_U_STEP(2) VCT_U_STEP(3) VCT_U_STEP(4) VCT_U_STEP(5)
-        VCT_U_STEP(6) VCT_U_STEP(7) VCT_U_STEP(8) VCT_U_STEP(9) VCT_U_STEP(10)
-#undef VCT_U_STEP
-        // column r of P = U A^T + Q: entry (q0, r) from row q0 of U and row r of A
-#define VCT_P_STEP(Q)                                                                              \
-        {                                                                                          \
-            double u[NX];                                                                          \
-            row_of<Q>(Ur, u);                                                                      \
-            double acc = 0.0;                                                                      \
-            _Pragma("unroll") for (int q = 0; q < NX; ++q)                                         \
-                acc = fma(u[q], Ar[q], acc);                                                       \
-            Pr[Q] = acc + (in && Q == r ? 1e-6 : 0.0) + (in && Q == kXQ1 && r == kXQ1 ? qq1 : 0.0); \
-        }
-        VCT_P_STEP(0) VCT_P_STEP(1) VCT_P_STEP(2) VCT_P_STEP(3) VCT_P_STEP(4) VCT_P_STEP(5)
-        VCT_P_STEP(6) VCT_P_STEP(7) VCT_P_STEP(8) VCT_P_STEP(9) VCT_P_STEP(10)
-#undef VCT_P_STEP
+        // U = A T, then column r of P = U A^T + Q
+        u_product(std::make_integer_sequence<int, NX>{}, Ar, Tr, Ur);
+        p_column(std::make_integer_sequence<int, NX>{}, Ur, Ar, Pr);
+#pragma unroll
+        for (int q = 0; q < NX; ++q)
+            Pr[q] = Pr[q] + (in && q == r ? 1e-6 : 0.0) + (in && q == kXQ1 && r == kXQ1 ? qq1 : 0.0);
     }
     // K = P e_GI / (P[GI][GI] + R): column GI of P, which lane GI holds
     if (in && r == kXGI && ub > 0.0) {
