@@ -243,3 +243,49 @@ def test_labels_along_own_loop(orc):
     c = orc.simulate(t, threads=4, record=True, n_traj=10, mlp=W.constant_policy_net(2.0))
     applied = c["traj_u"].T / c["params"][:, 15]
     assert np.any(np.abs(c["record"][:, :, 12] - applied) > 1e-3)
+
+
+def test_insulin_and_meal_inputs_are_the_predicted_mean_glucose_change(orc):
+    """The learned controller's inputs 6 and 7 on every sample of a noisy, meal-bearing MPC
+    run, recomputed from the recorded plant states: the insulin input is the mean over the
+    next 24 samples of the glucose deviation that the insulin states' deviation from basal
+    causes, and the meal input the same for the gut states plus the intake announced for the
+    current interval. Here the horizon is walked sample by sample with the discrete model
+    (x_(j+1) = A x_j, the intake entering through E on the first step), not through the
+    oracle's horizon means. Insulin above basal lowers glucose and meals raise it."""
+    t = W.with_(W.c5_mpc(), n_patients=6, n_days=2, precision=W.FP64)
+    r = orc.simulate(t, n_traj=6, threads=4, record=True, record_x=True)
+    rec, X, K = r["record"], r["traj_x"], r["K"]
+    SX = {n: i for i, n in enumerate(W.STATE_NAMES)}
+    ins = [SX[s] for s in ("S1", "S2", "I", "x1", "x2", "x3")]
+    gut = [SX["D1"], SX["D2"]]
+    for j in range(6):
+        prm = r["params"][j]
+        m = orc.mpc_setup(t, prm)
+        N, A, E = m["N"], m["A"], m["E"]
+        vg = prm[W.PARAM_NAMES.index("VG")] * prm[W.PARAM_NAMES.index("BW")]
+        d = np.zeros(K)
+        for day in range(2):
+            for kd, _c, rate in orc.day_meals(t, j, day):
+                d[day * 288 + int(kd)] += rate
+        # the walk is linear: propagate all samples' start vectors together (columns)
+        dx_ins = np.zeros((11, K))
+        dx_ins[ins] = (X[j][:, ins] - m["xss"][ins]).T
+        dx_gut = np.zeros((11, K))
+        dx_gut[gut] = X[j][:, gut].T
+        acc_i, acc_g = np.zeros(K), np.zeros(K)
+        xi, xg = dx_ins, dx_gut
+        for step in range(N):
+            xi = A @ xi
+            xg = A @ xg + (np.outer(E, d) if step == 0 else 0.0)
+            acc_i += xi[SX["Q1"]] / vg
+            acc_g += xg[SX["Q1"]] / vg
+        iob, meal = acc_i / N, acc_g / N
+        scale_i, scale_g = np.abs(iob).max(), np.abs(meal).max()
+        assert scale_i > 0.1 and scale_g > 0.1
+        assert np.allclose(rec[:, j, 6], iob, rtol=1e-9, atol=1e-12 * scale_i)
+        assert np.allclose(rec[:, j, 7], meal, rtol=1e-9, atol=1e-12 * scale_g)
+        above = (X[j][:, SX["S1"]] + X[j][:, SX["S2"]]) > 1.5 * (m["xss"][SX["S1"]] + m["xss"][SX["S2"]])
+        above &= X[j][:, SX["I"]] > 1.2 * m["xss"][SX["I"]]
+        assert above.sum() > 10 and np.all(rec[above, j, 6] < 0)
+        assert np.all(rec[d > 0, j, 7] > 0)

@@ -9,7 +9,13 @@
 * projected gradient: monotone objective, converges to the unconstrained minimiser
   (numpy.linalg.solve) when the box is inactive, satisfies the KKT conditions when it is
   active, and matches brute force over all 3^N active sets for N = 4;
-* closed loop: at the set point without meals or noise the plan is u = u_b forever.
+* closed loop: at the set point without meals or noise the plan is u = u_b forever;
+* online step: on a noisy, meal-bearing run every applied input equals the one that a
+  textbook Kalman measurement/time update and an exact bounded least-squares solve of the
+  box QP (scipy BVLS) give from the recorded sensor values, announcements and inputs; with
+  two projected-gradient steps, the textbook warm start (previous plan moved one sample on)
+  reproduces the inputs and the reversed shift does not; from high glucose the loop doses
+  above basal and brings glucose down to the set point.
 """
 import itertools
 
@@ -198,3 +204,123 @@ def test_closed_loop_at_setpoint(orc):
     ub = r["params"][:4, 15]
     assert np.max(np.abs(r["traj_u"] - ub[:, None]) / ub[:, None]) < 1e-12
     assert np.max(np.abs(r["traj_g"] - 6.0)) < 1e-10
+
+
+# ------------------------------------------------------------------ online step
+# The controller sample written out in textbook form (Sec. III-B: the controller state is the
+# estimate and the plan, the action is the plan's first input), independently of the oracle's
+# code: measurement update x+ = x- + K (y - x*_GI - x-_GI); prediction matrices rebuilt here
+# from (A, B, E) and c_G = e_Q1 / V_G; the box QP over the input deviations solved exactly as
+# a bounded least-squares problem (scipy's BVLS); time update x- = A x+ + B (u - u_b) + E d.
+# Only (A, B, E, K), pinned by the tests above, are taken from the oracle's setup.
+
+def textbook_prediction(m, prm):
+    N = m["N"]
+    vg = prm[W.PARAM_NAMES.index("VG")] * prm[W.PARAM_NAMES.index("BW")]
+    cg = np.zeros(NX)
+    cg[SX["Q1"]] = 1.0 / vg
+    F, h, w = np.zeros((N, NX)), np.zeros(N), np.zeros(N)
+    Ap = np.eye(NX)
+    for j in range(N):               # G_(k+j+1) - G* = F_j x + sum_i h_(j-i) du_i + w_j d
+        h[j] = cg @ Ap @ m["B"]
+        w[j] = cg @ Ap @ m["E"]
+        Ap = m["A"] @ Ap
+        F[j] = cg @ Ap
+    return F, h, w
+
+
+def announced(orc, t, patient, K):
+    d = np.zeros(K)
+    for day in range(int(t["n_days"])):
+        for kd, _carbs, rate in orc.day_meals(t, patient, day):
+            d[day * 288 + int(kd)] += rate
+    return d
+
+
+def test_online_step_is_the_textbook_filter_and_exact_qp(orc):
+    """A noisy, meal-bearing MPC run: every applied input equals u_b plus the first entry of
+    the exact solution of the box QP built from the textbook filter's estimate, on samples
+    with an active bound as well (the 50 projected-gradient steps converge: the QP's
+    condition number is ~1.3 because rho/u_b^2 dominates Gamma^T Gamma)."""
+    from scipy.optimize import lsq_linear
+    t = W.with_(mpc_trial(), n_patients=3, n_days=2)
+    r = orc.simulate(t, n_traj=3, threads=3)
+    K = r["K"]
+    n_active = 0
+    for j in range(3):
+        prm = r["params"][j]
+        m = orc.mpc_setup(t, prm)
+        F, h, w = textbook_prediction(m, prm)
+        N, ub, umax = m["N"], m["ub"], m["umax"]
+        Gam = gamma(h)
+        rho = t["mpc_rho"] / ub ** 2
+        A_ls = np.vstack([Gam, np.sqrt(rho) * np.eye(N)])
+        d = announced(orc, t, j, K)
+        assert np.count_nonzero(d) >= 6
+        xh = np.zeros(NX)
+        for k in range(K):
+            y, u = r["traj_y"][j, k], r["traj_u"][j, k]
+            xh = xh + m["K"] * ((y - m["xss"][SX["GI"]]) - xh[SX["GI"]])
+            resid = F @ xh + w * d[k] + (t["g_target"] - t["setpoint"])
+            sol = lsq_linear(A_ls, -np.concatenate([resid, np.zeros(N)]),
+                             bounds=(np.full(N, -ub), np.full(N, umax - ub)), method="bvls", tol=1e-14)
+            n_active += int(np.any(sol.active_mask != 0))
+            assert abs(ub + sol.x[0] - u) <= 1e-10 * ub, (j, k)
+            xh = m["A"] @ xh + m["B"] * (u - ub) + m["E"] * d[k]
+    assert n_active > 50
+
+
+def test_online_step_warm_start_is_the_shifted_plan(orc):
+    """With only two projected-gradient steps the warm start decides the action: it is the
+    previous plan moved one sample on (its last entry repeated). The reversed shift misses
+    by > 1 % of u_b; the textbook loop matches to rounding."""
+    t = W.with_(mpc_trial(), n_patients=2, n_days=1, mpc_iters=2)
+    r = orc.simulate(t, n_traj=2, threads=2)
+    K = r["K"]
+    for j in range(2):
+        prm = r["params"][j]
+        m = orc.mpc_setup(t, prm)
+        F, h, w = textbook_prediction(m, prm)
+        N, ub, umax = m["N"], m["ub"], m["umax"]
+        Gam = gamma(h)
+        H = Gam.T @ Gam + t["mpc_rho"] / ub ** 2 * np.eye(N)
+        step = 1.0 / np.linalg.eigvalsh(H).max()
+        d = announced(orc, t, j, K)
+        xh, U, Urev = np.zeros(NX), np.zeros(N), np.zeros(N)
+        worst_rev = 0.0
+        for k in range(K):
+            y, u = r["traj_y"][j, k], r["traj_u"][j, k]
+            xh = xh + m["K"] * ((y - m["xss"][SX["GI"]]) - xh[SX["GI"]])
+            g = Gam.T @ (F @ xh + w * d[k] + (t["g_target"] - t["setpoint"]))
+            U = np.concatenate([U[1:], U[-1:]])
+            Urev = np.concatenate([Urev[:1], Urev[:-1]])
+            for _ in range(2):
+                U = np.clip(U - step * (H @ U + g), -ub, umax - ub)
+                Urev = np.clip(Urev - step * (H @ Urev + g), -ub, umax - ub)
+            assert abs(ub + U[0] - u) <= 1e-12 * ub, (j, k)
+            worst_rev = max(worst_rev, abs(ub + Urev[0] - u) / ub)
+            xh = m["A"] @ xh + m["B"] * (u - ub) + m["E"] * d[k]
+        assert worst_rev > 1e-2
+
+
+def test_mpc_brings_high_glucose_down(orc):
+    """Sign of the loop: started at G = G_I = 10 mmol/L (basal insulin states), without meals
+    or noise, the first inputs are above u_b (at the bound), glucose falls monotonically for
+    the first hour, reaches the set point within four hours, stays above 5 mmol/L and settles
+    at 6."""
+    t = W.noise_free(mpc_trial(n_patients=3, n_days=1, n_slots=0))
+    pop = orc.sample_population(t)
+    for j in range(3):
+        vg = pop[j][W.PARAM_NAMES.index("VG")] * pop[j][W.PARAM_NAMES.index("BW")]
+        off = np.zeros(NX)
+        off[SX["Q1"]] = 4.0 * vg
+        off[SX["GI"]] = 4.0
+        r = orc.simulate(W.with_(t, n_patients=1, first_patient=j), n_traj=1, threads=1, x0_offset=off)
+        u, g = r["traj_u"][0], r["traj_g"][0]
+        ub = r["params"][0, 15]
+        assert g[0] == pytest.approx(10.0, rel=1e-12)
+        assert np.all(u[:2] > 2.9 * ub)
+        assert np.all(np.diff(g[:12]) < 0)
+        assert np.min(np.abs(g[:48] - 6.0)) < 0.3
+        assert g.min() > 5.0
+        assert abs(g[-1] - 6.0) < 1e-2
