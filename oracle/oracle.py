@@ -78,7 +78,8 @@ class OrcSummary(C.Structure):
         ("n", C.c_int64), ("k", C.c_int64), ("bins", C.c_uint64 * 5), ("events", C.c_uint64 * 3),
         ("q_count", C.c_int64 * 5), ("mean_tir", C.c_double), ("mean_bg", C.c_double),
         ("worst_patient", C.c_int64), ("worst_min_g", C.c_double), ("worst_k", C.c_int32),
-        ("status_count", C.c_int64 * 3),
+        ("status_count", C.c_int64 * 3), ("n_clean", C.c_int64), ("bins_clean", C.c_uint64 * 5),
+        ("q_count_clean", C.c_int64 * 5), ("mean_tir_clean", C.c_double), ("mean_bg_clean", C.c_double),
     ]
 
 
@@ -440,4 +441,6 @@ def reduce(r: dict) -> dict:
         "n": s.n, "k": s.k, "bins": list(s.bins), "events": list(s.events), "q_count": list(s.q_count),
         "mean_tir": s.mean_tir, "mean_bg": s.mean_bg, "worst_patient": s.worst_patient,
         "worst_min_g": s.worst_min_g, "worst_k": s.worst_k, "status_count": list(s.status_count),
+        "n_clean": s.n_clean, "bins_clean": list(s.bins_clean), "q_count_clean": list(s.q_count_clean),
+        "mean_tir_clean": s.mean_tir_clean, "mean_bg_clean": s.mean_bg_clean,
     }

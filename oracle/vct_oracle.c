@@ -1366,7 +1366,8 @@ static int cmp_i32(const void *a, const void *b)
 
 /* Population summary. Quantile p (percent) is the nearest rank: the value at
  * position ceil(p n / 100) of the sorted per-patient in-range counts. The worst
- * patient is the lexicographic minimum of (min G, patient index). */
+ * patient is the lexicographic minimum of (min G, patient index). The same totals,
+ * quantiles and means are repeated over the unflagged patients (status == 0). */
 void orc_reduce(int64_t n, int64_t k, const int32_t *bins, const int32_t *events, const double *sum_g,
                 const double *min_g, const int32_t *argmin_k, const uint32_t *status, orc_summary *s)
 {
@@ -1375,8 +1376,9 @@ void orc_reduce(int64_t n, int64_t k, const int32_t *bins, const int32_t *events
     s->k = k;
     s->worst_patient = -1;
     s->worst_min_g = INFINITY;
-    double total_g = 0.0;
+    double total_g = 0.0, total_g_clean = 0.0;
     int32_t *tir = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
+    int32_t *tir_clean = (int32_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int32_t));
     for (int64_t i = 0; i < n; ++i) {
         for (int b = 0; b < 5; ++b) s->bins[b] += (uint64_t)bins[i * 5 + b];
         for (int e = 0; e < 3; ++e) s->events[e] += (uint64_t)events[i * 3 + e];
@@ -1389,14 +1391,26 @@ void orc_reduce(int64_t n, int64_t k, const int32_t *bins, const int32_t *events
         }
         for (int t = 0; t < 3; ++t)
             if (status[i] & (1u << t)) s->status_count[t] += 1;
+        if (status[i] == 0) {
+            for (int b = 0; b < 5; ++b) s->bins_clean[b] += (uint64_t)bins[i * 5 + b];
+            total_g_clean += sum_g[i];
+            tir_clean[s->n_clean++] = bins[i * 5 + 2];
+        }
     }
     qsort(tir, (size_t)n, sizeof(int32_t), cmp_i32);
+    qsort(tir_clean, (size_t)s->n_clean, sizeof(int32_t), cmp_i32);
     static const int64_t pct[5] = {5, 25, 50, 75, 95};
+    const int64_t nc = s->n_clean;
     for (int q = 0; q < 5; ++q) {
         int64_t r = (pct[q] * n + 99) / 100;
         s->q_count[q] = n > 0 ? tir[r - 1] : 0;
+        int64_t rc = (pct[q] * nc + 99) / 100;
+        s->q_count_clean[q] = nc > 0 ? tir_clean[rc - 1] : 0;
     }
     s->mean_tir = (n > 0 && k > 0) ? (double)s->bins[2] / ((double)n * (double)k) : 0.0;
     s->mean_bg = (n > 0 && k > 0) ? total_g / ((double)n * (double)k) : 0.0;
+    s->mean_tir_clean = (nc > 0 && k > 0) ? (double)s->bins_clean[2] / ((double)nc * (double)k) : 0.0;
+    s->mean_bg_clean = (nc > 0 && k > 0) ? total_g_clean / ((double)nc * (double)k) : 0.0;
     free(tir);
+    free(tir_clean);
 }

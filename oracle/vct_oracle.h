@@ -212,7 +212,9 @@ int      orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n
 void     orc_em_ou(double theta, double s, double x0, double h, int32_t n_steps, int64_t n_paths,
                    uint64_t seed, double *x_final);
 
-/* Population summary: exact integer totals, nearest-rank quantiles of per-patient in-range counts. */
+/* Population summary: exact integer totals, nearest-rank quantiles of per-patient in-range counts.
+   The *_clean fields repeat the totals, quantiles and means over the unflagged patients only
+   (status == 0: finite state, Q1 never negative, parameters not the resampling fallback). */
 typedef struct {
     int64_t  n, k;
     uint64_t bins[5];
@@ -224,6 +226,11 @@ typedef struct {
     double   worst_min_g;
     int32_t  worst_k;
     int64_t  status_count[3];
+    int64_t  n_clean;             /* patients with status == 0 */
+    uint64_t bins_clean[5];
+    int64_t  q_count_clean[5];    /* nearest rank over the n_clean patients (0 if none) */
+    double   mean_tir_clean;      /* bins_clean[2] / (n_clean k), 0 if none */
+    double   mean_bg_clean;
 } orc_summary;
 void     orc_reduce(int64_t n, int64_t k, const int32_t *bins, const int32_t *events, const double *sum_g,
                     const double *min_g, const int32_t *argmin_k, const uint32_t *status, orc_summary *s);

@@ -143,3 +143,14 @@ def test_reduce_quantiles_and_totals(orc):
         assert s["mean_bg"] == pytest.approx(r["sum_g"].sum() / (n * K), rel=1e-12)
         for b in range(3):
             assert s["status_count"][b] == np.sum((r["status"] >> b) & 1)
+        # the same summary over the unflagged patients (status == 0) only
+        ok = r["status"] == 0
+        assert s["n_clean"] == ok.sum()
+        assert s["bins_clean"] == list(bins[ok].sum(0))
+        if ok.any():
+            for q, pct in zip(s["q_count_clean"], (5, 25, 50, 75, 95)):
+                assert q == np.percentile(bins[ok, 2], pct, method="inverted_cdf")
+            assert s["mean_tir_clean"] == pytest.approx(bins[ok, 2].sum() / (ok.sum() * K), rel=1e-15)
+            assert s["mean_bg_clean"] == pytest.approx(r["sum_g"][ok].sum() / (ok.sum() * K), rel=1e-12)
+        else:
+            assert s["q_count_clean"] == [0] * 5 and s["mean_tir_clean"] == 0.0
