@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VCT_ABI_VERSION 2
+#define VCT_ABI_VERSION 3
 #define VCT_NP 15          /* sampled parameters per patient                         */
 #define VCT_NX 11          /* model states per patient                               */
 #define VCT_NPARAM_ROWS 19 /* rows of the population buffer: 15 parameters, u_b, I*, attempts, status */
@@ -213,6 +213,15 @@ typedef struct {
     int32_t  worst_k;
     int32_t  _pad;
     int64_t  status_count[3];
+    /* The same over the unflagged patients only (status == 0: finite state, Q1 never
+     * negative, parameters not the resampling fallback); every field above still counts
+     * all patients. Quantiles and means are 0 if no patient is unflagged. */
+    int64_t  n_clean;
+    uint64_t bins_clean[5];
+    int64_t  q_count_clean[5];
+    double   q_frac_clean[5];
+    double   mean_tir_clean;   /* bins_clean[2] / (n_clean K)                      */
+    double   mean_bg_clean;
 } vct_summary;
 
 typedef struct vct_population vct_population;   /* opaque, owned by the library */

@@ -491,36 +491,9 @@ vct_status vct_mlp_forward(const float *x_dev, int64_t n, const void *blob_dev, 
     return VCT_OK;
 }
 
-vct_status vct_read_metrics(const void *metrics_dev, int64_t n, int64_t K, vct_summary *out, void *stream)
+// Copies a device-side reduction result into the caller's summary.
+static void fill_summary(const vct::ReduceOut &h, int64_t n, int64_t K, vct_summary *out)
 {
-    g_err.clear();
-    if (!metrics_dev || !out)
-        return fail(VCT_EINVAL, "vct_read_metrics: null argument");
-    if (n < 1 || n >= kMaxPatients || K < 1 || K >= ((int64_t)1 << 31))
-        return fail(VCT_EINVAL, "vct_read_metrics: n %lld or K %lld out of range", (long long)n, (long long)K);
-    hipStream_t s = (hipStream_t)stream;
-    const size_t ws_bytes = vct::reduce_workspace_bytes(n, K) + sizeof(vct::ReduceOut);
-    void *ws = nullptr;
-    hipError_t e = hipMallocAsync(&ws, ws_bytes, s);
-    if (e != hipSuccess)
-        return fail(VCT_ENOMEM, "vct_read_metrics: workspace of %zu bytes: %s", ws_bytes, hipGetErrorString(e));
-    vct::ReduceOut *dres = (vct::ReduceOut *)((char *)ws + vct::reduce_workspace_bytes(n, K));
-    const char *m = (const char *)metrics_dev;
-    e = vct::launch_reduce((const double *)m, (const double *)(m + 8 * n), (const double *)(m + 16 * n),
-                           (const int32_t *)(m + 24 * n), (const int32_t *)(m + 44 * n),
-                           (const int32_t *)(m + 56 * n), (const uint32_t *)(m + 60 * n), n, K, ws, dres, s);
-    vct::ReduceOut h{};
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(&h, dres, sizeof h, hipMemcpyDeviceToHost, s);
-    hipError_t e2 = hipFreeAsync(ws, s);
-    hipError_t e3 = hipStreamSynchronize(s);
-    if (e != hipSuccess)
-        return hip_fail(e, "vct_read_metrics: reduction");
-    if (e2 != hipSuccess)
-        return hip_fail(e2, "vct_read_metrics: free");
-    if (e3 != hipSuccess)
-        return hip_fail(e3, "vct_read_metrics: synchronize");
-
     std::memset(out, 0, sizeof *out);
     out->n_patients = n;
     out->n_samples = K;
@@ -537,6 +510,56 @@ vct_status vct_read_metrics(const void *metrics_dev, int64_t n, int64_t K, vct_s
     out->worst_min_g = h.worst_min_g;
     out->worst_k = h.worst_k;
     for (int q = 0; q < 3; ++q) out->status_count[q] = h.status_count[q];
+    const int64_t nc = h.n_clean;
+    out->n_clean = nc;
+    for (int q = 0; q < 5; ++q) {
+        out->bins_clean[q] = h.bins_clean[q];
+        out->q_count_clean[q] = h.q_count_clean[q];
+        out->q_frac_clean[q] = (double)h.q_count_clean[q] / (double)K;
+    }
+    out->mean_tir_clean = nc > 0 ? (double)h.bins_clean[2] / ((double)nc * (double)K) : 0.0;
+    out->mean_bg_clean = nc > 0 ? h.sum_g_clean / ((double)nc * (double)K) : 0.0;
+}
+
+// Launches the reduction into `ws`, copies the result to the host and synchronises.
+static hipError_t reduce_to_host(const void *metrics_dev, int64_t n, int64_t K, void *ws, vct::ReduceOut *h,
+                                 hipStream_t s)
+{
+    const char *m = (const char *)metrics_dev;
+    vct::ReduceOut *dres = nullptr;
+    hipError_t e = vct::launch_reduce((const double *)m, (const double *)(m + 8 * n), (const double *)(m + 16 * n),
+                                      (const int32_t *)(m + 24 * n), (const int32_t *)(m + 44 * n),
+                                      (const int32_t *)(m + 56 * n), (const uint32_t *)(m + 60 * n), n, K, ws, &dres,
+                                      s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(h, dres, sizeof *h, hipMemcpyDeviceToHost, s);
+    return e;
+}
+
+vct_status vct_read_metrics(const void *metrics_dev, int64_t n, int64_t K, vct_summary *out, void *stream)
+{
+    g_err.clear();
+    if (!metrics_dev || !out)
+        return fail(VCT_EINVAL, "vct_read_metrics: null argument");
+    if (n < 1 || n >= kMaxPatients || K < 1 || K >= ((int64_t)1 << 31))
+        return fail(VCT_EINVAL, "vct_read_metrics: n %lld or K %lld out of range", (long long)n, (long long)K);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t ws_bytes = vct::reduce_workspace_bytes(n, K);
+    void *ws = nullptr;
+    hipError_t e = hipMallocAsync(&ws, ws_bytes, s);
+    if (e != hipSuccess)
+        return fail(VCT_ENOMEM, "vct_read_metrics: workspace of %zu bytes: %s", ws_bytes, hipGetErrorString(e));
+    vct::ReduceOut h{};
+    e = reduce_to_host(metrics_dev, n, K, ws, &h, s);
+    hipError_t e2 = hipFreeAsync(ws, s);
+    hipError_t e3 = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_read_metrics: reduction");
+    if (e2 != hipSuccess)
+        return hip_fail(e2, "vct_read_metrics: free");
+    if (e3 != hipSuccess)
+        return hip_fail(e3, "vct_read_metrics: synchronize");
+    fill_summary(h, n, K, out);
     return VCT_OK;
 }
 

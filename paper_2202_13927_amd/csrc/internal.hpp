@@ -130,12 +130,17 @@ struct ReduceOut {
     int32_t worst_k;
     int32_t pad;
     int64_t status_count[3];
+    int64_t n_clean;            // unflagged patients (status == 0) and their totals
+    uint64_t bins_clean[5];
+    int64_t q_count_clean[5];
+    double sum_g_clean;
 };
 
-// Reduce metrics; writes one ReduceOut to dev_out. Workspace: see reduce_workspace_bytes.
+// Reduce metrics (four launches on s). The workspace (reduce_workspace_bytes, 256-byte
+// aligned, no initialisation needed) also holds the result: *dev_out points into it.
 size_t reduce_workspace_bytes(int64_t n, int64_t K);
 hipError_t launch_reduce(const double *sum_g, const double *min_g, const double *sum_u, const int32_t *bins,
                          const int32_t *events, const int32_t *argmin_k, const uint32_t *status, int64_t n,
-                         int64_t K, void *workspace, ReduceOut *dev_out, hipStream_t s);
+                         int64_t K, void *workspace, ReduceOut **dev_out, hipStream_t s);
 
 }  // namespace vct

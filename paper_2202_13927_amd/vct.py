@@ -67,7 +67,9 @@ class vct_summary(C.Structure):
                 ("events", C.c_uint64 * 3), ("q_count", C.c_int64 * 5), ("q_frac", C.c_double * 5),
                 ("mean_tir", C.c_double), ("mean_bg", C.c_double), ("mean_insulin", C.c_double),
                 ("worst_patient", C.c_int64), ("worst_min_g", C.c_double), ("worst_k", C.c_int32),
-                ("_pad", C.c_int32), ("status_count", C.c_int64 * 3)]
+                ("_pad", C.c_int32), ("status_count", C.c_int64 * 3), ("n_clean", C.c_int64),
+                ("bins_clean", C.c_uint64 * 5), ("q_count_clean", C.c_int64 * 5), ("q_frac_clean", C.c_double * 5),
+                ("mean_tir_clean", C.c_double), ("mean_bg_clean", C.c_double)]
 
     def as_dict(self) -> dict:
         return {
@@ -75,7 +77,10 @@ class vct_summary(C.Structure):
             "events": list(self.events), "q_count": list(self.q_count), "q_frac": list(self.q_frac),
             "mean_tir": self.mean_tir, "mean_bg": self.mean_bg, "mean_insulin": self.mean_insulin,
             "worst_patient": self.worst_patient, "worst_min_g": self.worst_min_g, "worst_k": self.worst_k,
-            "status_count": list(self.status_count),
+            "status_count": list(self.status_count), "n_clean": self.n_clean,
+            "bins_clean": list(self.bins_clean), "q_count_clean": list(self.q_count_clean),
+            "q_frac_clean": list(self.q_frac_clean), "mean_tir_clean": self.mean_tir_clean,
+            "mean_bg_clean": self.mean_bg_clean,
         }
 
 
