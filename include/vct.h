@@ -341,6 +341,18 @@ vct_status  vct_mlp_forward(const float *x_dev, int64_t n, const void *blob_dev,
 /* Reduce the per-patient metrics of n patients with K samples each into *host_out. */
 vct_status  vct_read_metrics(const void *metrics_dev, int64_t n_patients, int64_t n_samples,
                              vct_summary *host_out, void *stream);
+/* Allocation-free variant of vct_read_metrics, for callers that cannot allocate device
+ * memory (serving loops, harnesses that forbid hipMalloc). Same arguments, result and
+ * synchronisation; n_samples <= VCT_NOALLOC_MAX_SAMPLES, else VCT_EINVAL. Its workspace
+ * is a static device array of VCT_NOALLOC_SCRATCH_BYTES on each GPU the library runs on,
+ * held until the process ends and looked up at the first call on that GPU; the current
+ * device must be the stream's. Every call on a GPU shares that GPU's array (each call
+ * clears what it needs): calls that overlap on one GPU (several streams or threads) race,
+ * and the caller must serialise them. */
+#define VCT_NOALLOC_MAX_SAMPLES 210240        /* two years of 5-min samples */
+#define VCT_NOALLOC_SCRATCH_BYTES 2097152     /* 2 MiB per GPU              */
+vct_status  vct_read_metrics_noalloc(const void *metrics_dev, int64_t n_patients, int64_t n_samples,
+                                     vct_summary *host_out, void *stream);
 void        vct_destroy_population(vct_population *pop);
 
 /* Batched heterogeneous trial (many arms of uneven size and horizon) in ONE persistent

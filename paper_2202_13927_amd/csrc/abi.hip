@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -52,6 +53,36 @@ void split_key(uint64_t seed, uint32_t arm, uint32_t &k0, uint32_t &k1)
 }
 
 const int64_t kMaxPatients = (int64_t)1 << 31;
+
+// Workspace of vct_read_metrics_noalloc: one static array per GPU, held until the process
+// ends. Host code never passes `scratch` itself to a kernel (on the host it names a
+// stand-in, not device memory); it uses the device address found once per device.
+static __device__ __align__(256) unsigned char scratch[VCT_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up at the first call there).
+hipError_t scratch_address(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess)
+        return e;
+    if (dev < 0 || dev >= kMaxDevices)
+        return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess)
+            return e;
+        g_scratch_dev[dev] = p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 }  // namespace
 
@@ -559,6 +590,34 @@ vct_status vct_read_metrics(const void *metrics_dev, int64_t n, int64_t K, vct_s
         return hip_fail(e2, "vct_read_metrics: free");
     if (e3 != hipSuccess)
         return hip_fail(e3, "vct_read_metrics: synchronize");
+    fill_summary(h, n, K, out);
+    return VCT_OK;
+}
+
+vct_status vct_read_metrics_noalloc(const void *metrics_dev, int64_t n, int64_t K, vct_summary *out, void *stream)
+{
+    g_err.clear();
+    if (!metrics_dev || !out)
+        return fail(VCT_EINVAL, "vct_read_metrics_noalloc: null argument");
+    if (n < 1 || n >= kMaxPatients || K < 1 || K > VCT_NOALLOC_MAX_SAMPLES)
+        return fail(VCT_EINVAL, "vct_read_metrics_noalloc: n %lld or K %lld out of range (K <= %d)", (long long)n,
+                    (long long)K, VCT_NOALLOC_MAX_SAMPLES);
+    const size_t ws_bytes = vct::reduce_workspace_bytes(n, K);
+    if (ws_bytes > sizeof scratch)
+        return fail(VCT_EINVAL, "vct_read_metrics_noalloc: workspace of %zu bytes exceeds the static %zu", ws_bytes,
+                    sizeof scratch);
+    void *ws = nullptr;
+    hipError_t e = scratch_address(&ws);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_read_metrics_noalloc: scratch address");
+    hipStream_t s = (hipStream_t)stream;
+    vct::ReduceOut h{};
+    e = reduce_to_host(metrics_dev, n, K, ws, &h, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    if (e != hipSuccess)
+        return hip_fail(e, "vct_read_metrics_noalloc: reduction");
+    if (e2 != hipSuccess)
+        return hip_fail(e2, "vct_read_metrics_noalloc: synchronize");
     fill_summary(h, n, K, out);
     return VCT_OK;
 }

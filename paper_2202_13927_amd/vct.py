@@ -20,6 +20,7 @@ VCT_CTRL_OPEN, VCT_CTRL_PID, VCT_CTRL_MPC, VCT_CTRL_MLP = 0, 1, 2, 3
 VCT_PROTO_SLOTS, VCT_PROTO_NORDIC = 0, 1
 VCT_FP64, VCT_FP32 = 0, 1
 VCT_POP_MIN_BASAL = 1
+VCT_NOALLOC_MAX_SAMPLES, VCT_NOALLOC_SCRATCH_BYTES = 210240, 2097152
 VCT_MLP_IN, VCT_MLP_PARAMS, VCT_MLP_BLOB_BYTES = 12, 10448, 21568
 # byte offsets inside a learned-controller blob
 MLP_BLOB = {"W1": 0, "W2": 2048, "W3": 10240, "W4": 18432, "b1": 20480, "b2": 20736, "b3": 20992, "b4": 21248,
@@ -106,7 +107,8 @@ class VctError(RuntimeError):
 
 # every symbol include/vct.h declares
 EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_metrics_bytes", "vct_traj_bytes",
-           "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_destroy_population",
+           "vct_create_population", "vct_simulate", "vct_read_metrics", "vct_read_metrics_noalloc",
+           "vct_destroy_population",
            "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy", "vct_mpc_bytes",
            "vct_mpc_setup", "vct_mlp_blob_bytes", "vct_mlp_train_bytes", "vct_mlp_init", "vct_mlp_normalize",
            "vct_mlp_train_step", "vct_mlp_forward", "vct_popbg_bytes")
@@ -138,6 +140,9 @@ def lib() -> C.CDLL:
         L.vct_simulate.restype = C.c_int
         L.vct_read_metrics.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(vct_summary), C.c_void_p]
         L.vct_read_metrics.restype = C.c_int
+        L.vct_read_metrics_noalloc.argtypes = [C.c_void_p, C.c_int64, C.c_int64, C.POINTER(vct_summary),
+                                               C.c_void_p]
+        L.vct_read_metrics_noalloc.restype = C.c_int
         L.vct_destroy_population.argtypes = [C.c_void_p]
         L.vct_destroy_population.restype = None
         L.vct_batch_create.argtypes = [C.POINTER(vct_arm), C.c_int32, C.POINTER(vct_protocol),
@@ -248,6 +253,13 @@ def vct_read_metrics(metrics_dev, n_patients: int, n_samples: int, stream=None) 
     out = vct_summary()
     _check("vct_read_metrics",
            lib().vct_read_metrics(_ptr(metrics_dev), n_patients, n_samples, C.byref(out), _stream(stream)))
+    return out
+
+
+def vct_read_metrics_noalloc(metrics_dev, n_patients: int, n_samples: int, stream=None) -> vct_summary:
+    out = vct_summary()
+    _check("vct_read_metrics_noalloc",
+           lib().vct_read_metrics_noalloc(_ptr(metrics_dev), n_patients, n_samples, C.byref(out), _stream(stream)))
     return out
 
 
