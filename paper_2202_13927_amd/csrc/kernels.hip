@@ -491,12 +491,31 @@ template <typename R> struct CtrlConst {
 // absorption subsystems driven by the delivered doses and the announced meals; both are
 // deterministic and the announcements exact, so the replica equals the plant's states and
 // is read from them (the coefficients below undo the state scaling).
-template <typename R> struct PolicyLane {
+//
+// Rows of the per-lane coefficients: f6 (insulin), f7 (meals), f8..f11; the learned
+// controller also keeps its Kalman gain and the linearised step of the time update there.
+enum : int { kPcIns = 0, kPcIns0 = 6, kPcMealD1 = 7, kPcMealD2 = 8, kPcWbar = 9, kPcSt = 10, kPcFeat = 14,
+             kPcKg = 14, kPcLin = kPcKg + kNx, kPcRows = kPcLin + 11 };
+
+// Coefficients of one lane in registers (the MPC kernel's recording path: the input rows
+// only) or in the wave's LDS block [kPcRows][64] (the learned controller: read when used,
+// so they take no registers across the network's evaluation).
+template <typename R, bool kLds> struct PolicyCoefs {
+    R v[kPcFeat];
+    __device__ __forceinline__ R get(int r) const { return v[r]; }
+    __device__ __forceinline__ void set(int r, R x) { v[r] = x; }
+};
+template <typename R> struct PolicyCoefs<R, true> {
+    R *p;
+    int lane;
+    __device__ __forceinline__ R get(int r) const { return p[r * 64 + lane]; }
+    __device__ __forceinline__ void set(int r, R x) { p[r * 64 + lane] = x; }
+};
+
+template <typename R, bool kLds> struct PolicyLane {
     R yh[5];                 // y_k-1 .. y_k-5
-    R ins[6], ins0;          // f6 = ins . (S1s, S2s, I, x1h, x2s, e3) + ins0
-    R meal_d1, meal_d2, wbar;   // f7 = D1s meal_d1 + D2 meal_d2 + dhat wbar
-    R st[4];
-    R kg[kNx];               // Kalman gain (learned controller: held in registers)
+    PolicyCoefs<R, kLds> co; // f6 = ins . (S1s, S2s, I, x1h, x2s, e3) + ins0,
+                             // f7 = D1s meal_d1 + D2 meal_d2 + dhat wbar, f8..f11 = st
     int32_t fallbacks;       // samples on which the MPC acted instead of the network
 };
 
@@ -526,6 +545,7 @@ struct PolicyShared {
     const float *mean, *istd, *lo, *hi;
     uint32_t *hist;             // population BG bins of this wave (kOutPop)
     uint32_t *span;             // [kSpanBins][64] per-lane BG bins of this wave (kOutPop)
+    void *pc;                   // [kPcRows][64] per-lane coefficients of this wave (working precision)
     int lane;
     bool rest;                  // this wave's patient is outside the box: the MPC acts on every sample
 };
@@ -539,42 +559,76 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename R>
-__device__ __forceinline__ void policy_features(const PolicyLane<R> &P, const State<R> &s, R y, R dr, R f[kMlpIn])
+template <typename R, bool kLds>
+__device__ __forceinline__ void policy_features(const PolicyLane<R, kLds> &P, const State<R> &s, R y, R dr,
+                                                R f[kMlpIn])
 {
     f[0] = y;
 #pragma unroll
     for (int q = 0; q < 5; ++q)
         f[1 + q] = P.yh[q];
-    R a6 = P.ins0;
-    a6 = fmaf_t(P.ins[0], s.S1s, a6);
-    a6 = fmaf_t(P.ins[1], s.S2s, a6);
-    a6 = fmaf_t(P.ins[2], s.I, a6);
-    a6 = fmaf_t(P.ins[3], s.x1h, a6);
-    a6 = fmaf_t(P.ins[4], s.x2s, a6);
-    f[6] = fmaf_t(P.ins[5], s.e3, a6);
-    f[7] = fmaf_t(s.D1s, P.meal_d1, fmaf_t(s.D2, P.meal_d2, dr * P.wbar));
+    R a6 = P.co.get(kPcIns0);
+    a6 = fmaf_t(P.co.get(kPcIns + 0), s.S1s, a6);
+    a6 = fmaf_t(P.co.get(kPcIns + 1), s.S2s, a6);
+    a6 = fmaf_t(P.co.get(kPcIns + 2), s.I, a6);
+    a6 = fmaf_t(P.co.get(kPcIns + 3), s.x1h, a6);
+    a6 = fmaf_t(P.co.get(kPcIns + 4), s.x2s, a6);
+    f[6] = fmaf_t(P.co.get(kPcIns + 5), s.e3, a6);
+    f[7] = fmaf_t(s.D1s, P.co.get(kPcMealD1), fmaf_t(s.D2, P.co.get(kPcMealD2), dr * P.co.get(kPcWbar)));
 #pragma unroll
     for (int q = 0; q < 4; ++q)
-        f[8 + q] = P.st[q];
+        f[8 + q] = P.co.get(kPcSt + q);
 }
 
-// Network output o_k for the 64 lanes of the wave (all lanes must be active): normalise,
-// round to BF16, stage row `lane` of the input tile, run the MFMA chain.
+// The linearised time-update constants of the learned controller, from its LDS block.
+template <typename R>
+__device__ __forceinline__ LinStep<R> lin_from(const PolicyCoefs<R, true> &co)
+{
+    LinStep<R> m;
+    m.s2s1 = co.get(kPcLin + 0);
+    m.is2 = co.get(kPcLin + 1);
+    m.x1i = co.get(kPcLin + 2);
+    m.x2i = co.get(kPcLin + 3);
+    m.x3i = co.get(kPcLin + 4);
+    m.hq1 = co.get(kPcLin + 5);
+    m.q1x3 = co.get(kPcLin + 6);
+    m.q1q1 = co.get(kPcLin + 7);
+    m.q2x2 = co.get(kPcLin + 8);
+    m.q2q1 = co.get(kPcLin + 9);
+    m.q2q2 = co.get(kPcLin + 10);
+    return m;
+}
+
+// Writes the lane's normalised fixed inputs f8..f11 (BF16, columns 8..11 of its row of the
+// input tile) and zeros in the padding columns 12..15, once per patient; each sample then
+// writes columns 0..7 only.
+template <typename R>
+__device__ __forceinline__ void policy_fixed_inputs(const PolicyShared &ps, const R st[4])
+{
+    uint32_t w[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+        w[q] = pack_bf16(((float)st[2 * q] - ps.mean[8 + 2 * q]) * ps.istd[8 + 2 * q],
+                         ((float)st[2 * q + 1] - ps.mean[9 + 2 * q]) * ps.istd[9 + 2 * q]);
+    uint4 *dst = (uint4 *)(ps.xs + ps.lane * PaddedLayout::ldi);
+    dst[1] = uint4{w[0], w[1], 0u, 0u};
+}
+
+// Network output o_k for the 64 lanes of the wave (all lanes must be active): normalise the
+// time-varying inputs f0..f7, round them to BF16, stage them in row `lane` of the input tile
+// (columns 8..15 hold the patient's fixed inputs), run the MFMA chain.
 template <typename R>
 __device__ __forceinline__ float policy_forward(const PolicyShared &ps, const R f[kMlpIn])
 {
-    uint32_t w[8];
+    uint32_t w[4];
 #pragma unroll
-    for (int q = 0; q < 8; ++q)
-        w[q] = 2 * q < kMlpIn ? pack_bf16(((float)f[2 * q] - ps.mean[2 * q]) * ps.istd[2 * q],
-                                          ((float)f[2 * q + 1] - ps.mean[2 * q + 1]) * ps.istd[2 * q + 1])
-                              : 0u;
+    for (int q = 0; q < 4; ++q)
+        w[q] = pack_bf16(((float)f[2 * q] - ps.mean[2 * q]) * ps.istd[2 * q],
+                         ((float)f[2 * q + 1] - ps.mean[2 * q + 1]) * ps.istd[2 * q + 1]);
     uint4 *dst = (uint4 *)(ps.xs + ps.lane * PaddedLayout::ldi);
     dst[0] = uint4{w[0], w[1], w[2], w[3]};
-    dst[1] = uint4{w[4], w[5], w[6], w[7]};
     wave_lds_sync();
-    return mlp_forward_rf<PaddedLayout>(ps.img, ps.xs, ps.o, ps.lane, wave_lds_sync);
+    return mlp_forward_lean<PaddedLayout>(ps.img, ps.xs, ps.o, ps.lane, wave_lds_sync);
 }
 
 // ------------------------------------------------------ wave-cooperative QP ----
@@ -621,8 +675,11 @@ __device__ __forceinline__ int lane_read(int v, int l) { return __builtin_amdgcn
 
 // Solve the QP of the patient of lane L (all lanes must be active). Returns u_0 - u_b of
 // that patient, uniform across the wave; stores its plan when it is a live lane.
+// A real call (not inlined): falling back is rare on a tile wave, and its ~100 registers
+// would otherwise add to the network's and the plant's at every sample; the caller saves
+// its live registers around the call instead.
 template <typename R>
-__device__ __forceinline__ R coop_qp(const SimArgs &a, const R *__restrict__ M, int64_t j, bool live, int32_t k,
+__device__ __attribute__((noinline)) R coop_qp(const SimArgs &a, const R *__restrict__ M, int64_t j, bool live, int32_t k,
                                      const MpcState<R> &ms, R dhat, int L, int lane)
 {
     const uint32_t jL = (uint32_t)lane_read((int)j, L);
@@ -631,8 +688,10 @@ __device__ __forceinline__ R coop_qp(const SimArgs &a, const R *__restrict__ M, 
 #pragma unroll
     for (int c = 0; c < kNx; ++c)
         xh[c] = lane_read(ms.xh[c], L);
-    const R dh = lane_read(dhat, L), step = lane_read(ms.step, L), rho = lane_read(ms.rho_p, L);
-    const R lo = lane_read(ms.lo, L), hi = lane_read(ms.hi, L);
+    const R dh = lane_read(dhat, L);
+    // step, rho and bounds as mpc_load_state forms them
+    const R step = soa<R>(M, a.n, jL, kMstep), rho = soa<R>(M, a.n, jL, kMrho), ubL = soa<R>(M, a.n, jL, kMub);
+    const R lo = -ubL, hi = soa<R>(M, a.n, jL, kMumax) - ubL;
     const bool act = lane < kMpcN;
     const int i = act ? lane : 0;
     // linear term g_i (the order of mpc_linear_term)
@@ -694,7 +753,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
                                             const R *z, State<R> &s, const StepConst<R> &c,
                                             const CtrlConst<R> &cc, Lane<R> &L, MpcState<R> &ms,
                                             MpcPlan<R> &mplan, const LinStep<R> &lin,
-                                            PolicyLane<R> &pl, const PolicyShared &ps)
+                                            PolicyLane<R, CTRL == kCtrlMlp> &pl, const PolicyShared &ps)
 {
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
@@ -736,11 +795,11 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
             for (int q = 0; q < 5; ++q)
                 pl.yh[q] = y;
         }
-        policy_features<R>(pl, s, y, dr, f);
+        policy_features<R, CTRL == kCtrlMlp>(pl, s, y, dr, f);
     }
 
     R u, label = R(0);
-    if (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
+    if constexpr (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
         // u = u_b + kp e_k + ki sum_{i<k} ts e_i + kd (y_k - y_k-1)/ts with e = y - sp,
         // clamped to [0, umax]; the integral grows only while u is not clamped. Regrouped
         // as pid_b + (kp + kd/ts) y_k - (kd/ts) y_k-1 with pid_b = u_b - kp sp + ki sum ts e_i.
@@ -751,10 +810,10 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         if (u == u_unc)   // not clamped (a NaN u_unc is clamped to 0 and never integrates)
             L.pid_b = fmaf_t(cc.kits, y, L.pid_b - cc.kits_sp);
         L.y_prev = y;
-    } else if (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
+    } else if constexpr (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
         u = mpc_step<R>((const R *)a.mpc, a.n, j, ms, mplan, c, lin, R(a.h), R(a.h * a.ag), a.em_per_ctrl, y, dr,
                         R(a.g_target - a.setpoint), a.mpc_iters);
-    } else if (CTRL == kCtrlMlp) {
+    } else if constexpr (CTRL == kCtrlMlp) {
         // control state (CGM history, Kalman estimate, input plan): the network acts unless
         // an input leaves the box it was trained on, or the sensor reads low (y < mlp_safe_g)
         // while the network asks for more than mlp_safe_out u_b; then the MPC solves its QP.
@@ -762,7 +821,13 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         // the MPC's QP is solved on every sample and its action recorded as the label of
         // the network's inputs (data aggregation along the network's own closed loop).
         const R *M = (const R *)a.mpc;
-        mpc_measure_gain<R>(pl.kg, ms, y);
+        {
+            R kg[kNx];
+#pragma unroll
+            for (int q = 0; q < kNx; ++q)
+                kg[q] = pl.co.get(kPcKg + q);
+            mpc_measure_gain<R>(kg, ms, y);
+        }
         // The fixed inputs f8..f11 decided the lane order: every patient of a tile wave has
         // them inside the box (the same comparisons), every other patient is alone on a
         // wave and falls back on every sample. Only the time-varying inputs are tested here.
@@ -791,7 +856,7 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
             du = u - cc.ub;
         }
         label = cc.ub + du_mpc;
-        mpc_predict<R>(ms, c, lin, du, dr, R(a.h), R(a.h * a.ag), a.em_per_ctrl);
+        mpc_predict<R>(ms, c, lin_from<R>(pl.co), du, dr, R(a.h), R(a.h * a.ag), a.em_per_ctrl);
     } else {
         u = cc.u_open;
     }
@@ -868,7 +933,11 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
             P[(int64_t)i * a.n + j] = R(0);
         a.kplan[j] = -1;
     }
-    PolicyLane<R> pl;
+    PolicyLane<R, CTRL == kCtrlMlp> pl;
+    if constexpr (CTRL == kCtrlMlp) {
+        pl.co.p = (R *)ps.pc;
+        pl.co.lane = ps.lane;
+    }
     if (CTRL == kCtrlMlp || (OUT & kOutRecord)) {
         // f6, f7 from the horizon-mean prediction rows (FP64 here, then the working precision)
         const auto M = as_global((const R *)a.mpc);
@@ -880,22 +949,41 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
         const double c_ui = h / (ti * vi), b_i = h / ti;
         // unscaled states: S1 = S1s/(c_ui b_i), S2 = S2s/c_ui, x1 = x1h/h, x2 = x2s h ka2 SID,
         // x3 = 1 - e3/(h EGP0); basal: S1* = S2* = u_b tmaxI, I*, x_j* = S_j I*
-        pl.ins[0] = R(fb[kXS1] / (c_ui * b_i));
-        pl.ins[1] = R(fb[kXS2] / c_ui);
-        pl.ins[2] = R(fb[kXI]);
-        pl.ins[3] = R(fb[kXx1] / h);
-        pl.ins[4] = R(fb[kXx2] * h * p[kKa2] * p[kSID]);
-        pl.ins[5] = R(-fb[kXx3] / (h * egp0));
-        pl.ins0 = R(fb[kXx3] - (fb[kXS1] + fb[kXS2]) * ub_d * ti - fb[kXI] * istar -
-                    (fb[kXx1] * p[kSIT] + fb[kXx2] * p[kSID] + fb[kXx3] * p[kSIE]) * istar);
-        pl.meal_d1 = R(fb[kXD1] * p[kTmaxG] / h);
-        pl.meal_d2 = R(fb[kXD2]);
-        pl.wbar = R((double)M[(int64_t)kMwbar * a.n + j]);
-        patient_inputs<R>(a, j, pl.st);
+        pl.co.set(kPcIns + 0, R(fb[kXS1] / (c_ui * b_i)));
+        pl.co.set(kPcIns + 1, R(fb[kXS2] / c_ui));
+        pl.co.set(kPcIns + 2, R(fb[kXI]));
+        pl.co.set(kPcIns + 3, R(fb[kXx1] / h));
+        pl.co.set(kPcIns + 4, R(fb[kXx2] * h * p[kKa2] * p[kSID]));
+        pl.co.set(kPcIns + 5, R(-fb[kXx3] / (h * egp0)));
+        pl.co.set(kPcIns0, R(fb[kXx3] - (fb[kXS1] + fb[kXS2]) * ub_d * ti - fb[kXI] * istar -
+                             (fb[kXx1] * p[kSIT] + fb[kXx2] * p[kSID] + fb[kXx3] * p[kSIE]) * istar));
+        pl.co.set(kPcMealD1, R(fb[kXD1] * p[kTmaxG] / h));
+        pl.co.set(kPcMealD2, R(fb[kXD2]));
+        pl.co.set(kPcWbar, R((double)M[(int64_t)kMwbar * a.n + j]));
+        R st[4];
+        patient_inputs<R>(a, j, st);
 #pragma unroll
-        for (int q = 0; q < kNx; ++q)
-            pl.kg[q] = M[(int64_t)(kMK + q) * a.n + j];
+        for (int q = 0; q < 4; ++q)
+            pl.co.set(kPcSt + q, st[q]);
         pl.fallbacks = 0;
+        if constexpr (CTRL == kCtrlMlp) {
+#pragma unroll
+            for (int q = 0; q < kNx; ++q)
+                pl.co.set(kPcKg + q, M[(int64_t)(kMK + q) * a.n + j]);
+            pl.co.set(kPcLin + 0, lin.s2s1);
+            pl.co.set(kPcLin + 1, lin.is2);
+            pl.co.set(kPcLin + 2, lin.x1i);
+            pl.co.set(kPcLin + 3, lin.x2i);
+            pl.co.set(kPcLin + 4, lin.x3i);
+            pl.co.set(kPcLin + 5, lin.hq1);
+            pl.co.set(kPcLin + 6, lin.q1x3);
+            pl.co.set(kPcLin + 7, lin.q1q1);
+            pl.co.set(kPcLin + 8, lin.q2x2);
+            pl.co.set(kPcLin + 9, lin.q2q1);
+            pl.co.set(kPcLin + 10, lin.q2q2);
+            if (!ps.rest)
+                policy_fixed_inputs<R>(ps, st);
+        }
     }
 
     CtrlConst<R> cc;   // gains relative to u_b
@@ -1037,28 +1125,41 @@ void simulate_kernel(const SimArgs a)
 // outside the box (the MPC acts on every sample, so the network is skipped) alone on a
 // wave, then tiles of 64 patients. Every lane of a tile wave takes part in the MFMA chain,
 // so the padding lanes of the last tile replay a patient and write nothing.
-constexpr int kPolicyBlock = 256;
+// Workgroup size: four waves; two for FP64 with the population curves (their LDS).
+template <typename R, int OUT> constexpr int policy_block()
+{
+    return (sizeof(R) == 8 && (OUT & kOutPop)) ? 128 : 256;
+}
 using PolicyNet = NetImage<PaddedLayout>;
-// per wave: the input tile [64][24] BF16 and the 64 outputs
-constexpr int kPolicyWaveBytes = 64 * PaddedLayout::ldi * 2 + 64 * 4;
-// Waves per SIMD the kernel is compiled for (the register budget): one wave holds ~370
-// registers without spilling, so two would spill to scratch memory.
-constexpr int kPolicyBlocksPerCu = 1;
+// per wave: the input tile [64][24] BF16, the 64 outputs and the lanes' coefficients
+// [kPcRows][64] in the working precision
+template <typename R> constexpr int policy_wave_bytes()
+{
+    return 64 * PaddedLayout::ldi * 2 + 64 * 4 + kPcRows * 64 * (int)sizeof(R);
+}
+// Workgroups per CU the kernel is compiled for: two (two waves per SIMD, 256 registers
+// each) for FP32 without the population curves; one otherwise (FP64 state needs twice the
+// registers; the curves' LDS counters leave room for one workgroup).
+template <typename R, int OUT> constexpr int policy_blocks_per_cu()
+{
+    return (sizeof(R) == 4 && !(OUT & kOutPop)) ? 2 : 1;
+}
 
 template <typename R, bool NOISY, int OUT>
-__global__ __launch_bounds__(kPolicyBlock, kPolicyBlocksPerCu) void simulate_policy_kernel(const SimArgs a,
-                                                                                           const int32_t *counts,
-                                                                                           int32_t nb, uint32_t *queue)
+__global__ __launch_bounds__((policy_block<R, OUT>()), (policy_blocks_per_cu<R, OUT>())) void simulate_policy_kernel(
+    const SimArgs a, const int32_t *counts, int32_t nb, uint32_t *queue)
 {
-    __shared__ __align__(16) unsigned char lds[PolicyNet::bytes + (kPolicyBlock / 64) * kPolicyWaveBytes];
-    stage_net<PaddedLayout>(a.mlp, lds, threadIdx.x, kPolicyBlock);
+    constexpr int kBlock = policy_block<R, OUT>();
+    __shared__ __align__(16) unsigned char lds[PolicyNet::bytes + (kBlock / 64) * policy_wave_bytes<R>()];
+    stage_net<PaddedLayout>(a.mlp, lds, threadIdx.x, kBlock);
     __syncthreads();
     const int wave = threadIdx.x >> 6;
-    unsigned char *wl = lds + PolicyNet::bytes + wave * kPolicyWaveBytes;
+    unsigned char *wl = lds + PolicyNet::bytes + wave * policy_wave_bytes<R>();
     PolicyShared ps;
     ps.img = lds;
     ps.xs = (uint16_t *)wl;
     ps.o = (float *)(wl + 64 * PaddedLayout::ldi * 2);
+    ps.pc = wl + 64 * PaddedLayout::ldi * 2 + 64 * 4;
     ps.mean = (const float *)(lds + PolicyNet::tail + (kOffMean - kOffB1));
     ps.istd = (const float *)(lds + PolicyNet::tail + (kOffIstd - kOffB1));
     ps.lo = (const float *)(lds + PolicyNet::tail + (kOffLo - kOffB1));
@@ -1067,8 +1168,8 @@ __global__ __launch_bounds__(kPolicyBlock, kPolicyBlocksPerCu) void simulate_pol
     ps.hist = nullptr;
     ps.span = nullptr;
     if constexpr ((OUT & kOutPop) != 0) {
-        __shared__ uint32_t phist[kPolicyBlock / 64][kPopBins];
-        __shared__ uint32_t pspan[kPolicyBlock / 64][kSpanBins * 64];
+        __shared__ uint32_t phist[kBlock / 64][kPopBins];
+        __shared__ uint32_t pspan[kBlock / 64][kSpanBins * 64];
         ps.hist = phist[wave];
         ps.span = pspan[wave];
         for (int b = 0; b < kSpanBins; ++b)
@@ -1326,12 +1427,13 @@ static void launch_sim_o(const SimArgs &a, hipStream_t s)
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 256;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, simulate_policy_kernel<R, NOISY, OUT>, kPolicyBlock,
-                                                         0) != hipSuccess)
+        constexpr int PB = policy_block<R, OUT>();
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, simulate_policy_kernel<R, NOISY, OUT>, PB, 0) !=
+            hipSuccess)
             per_cu = 1;
-        const int64_t need = (a.n + kPolicyBlock / 64 - 1) / (kPolicyBlock / 64);
+        const int64_t need = (a.n + PB / 64 - 1) / (PB / 64);
         const unsigned blocks = (unsigned)std::max<int64_t>(1, std::min<int64_t>(need, (int64_t)cus * std::max(1, per_cu)));
-        hipLaunchKernelGGL((simulate_policy_kernel<R, NOISY, OUT>), dim3(blocks), dim3(kPolicyBlock), 0, s, a,
+        hipLaunchKernelGGL((simulate_policy_kernel<R, NOISY, OUT>), dim3(blocks), dim3(PB), 0, s, a,
                            (const int32_t *)counts, (int32_t)nb, (uint32_t *)(counts + nb + 1));
     } else {
         constexpr int B = sim_block<OUT>();

@@ -432,4 +432,82 @@ __device__ __forceinline__ float mlp_forward_rf(const unsigned char *img, const 
     return o[lane];
 }
 
+// The same forward pass with a smaller register footprint, for kernels that keep much
+// state of their own in registers: one layer's weight fragments are read from LDS just
+// before the layer (not one layer ahead), and each 16-sample tile s goes through all 64
+// units before the next, so its eight input fragments are replaced in place by its outputs
+// (4 accumulator tiles live instead of 8, no second copy of the activations). The
+// products, their order and the roundings are those of mlp_forward_rf: both return the
+// same values bit for bit.
+template <typename L, typename Sync>
+__device__ __forceinline__ float mlp_forward_lean(const unsigned char *img, const uint16_t *xs, float *o, int lane,
+                                                  Sync sync)
+{
+    using I = NetImage<L>;
+    const float *b1 = (const float *)(img + I::tail + (kOffB1 - kOffB1));
+    const float *b4 = (const float *)(img + I::tail + (kOffB4 - kOffB1));
+    bf16x8 h[2][4];
+    {   // input layer, K = 16: B = X^T read from the input tile
+        const uint16_t *W1 = (const uint16_t *)(img + I::w1);
+        bf16x4 a1[4];
+        f32x4 bb1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            a1[mt] = frag_rows(W1, L::ldw1, 16 * mt, 0, lane);
+            bb1[mt] = *(const f32x4 *)(b1 + 16 * mt + 4 * (lane >> 4));
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const bf16x4 x = frag_rows(xs, L::ldi, 16 * s, 0, lane);
+            f32x4 acc[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                acc[mt] = mfma16(a1[mt], x, bb1[mt]);
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                h[t][s] = relu_frag(acc[2 * t], acc[2 * t + 1]);
+        }
+    }
+#pragma unroll
+    for (int layer = 0; layer < 2; ++layer) {   // hidden layers 2 and 3
+        const uint16_t *W = (const uint16_t *)(img + (layer == 0 ? I::w2 : I::w3));
+        const float *bias = (const float *)(img + I::tail + ((layer == 0 ? kOffB2 : kOffB3) - kOffB1));
+        const HiddenFrags f = hidden_frags<L>(W, bias, lane);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            f32x4 acc[4];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                acc[mt] = f.b[mt];
+#pragma unroll
+                for (int kt = 0; kt < 2; ++kt)
+                    acc[mt] = mfma32(f.a[mt][kt], h[kt][s], acc[mt]);
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t)
+                h[t][s] = relu_frag(acc[2 * t], acc[2 * t + 1]);
+        }
+    }
+    bf16x8 a4[2];
+#pragma unroll
+    for (int kt = 0; kt < 2; ++kt)
+        a4[kt] = frag8_rows((const uint16_t *)(img + I::w4), L::ldw, 0, 32 * kt, lane);
+    const float bo = b4[0];
+    f32x4 acc[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        acc[s] = f32x4{bo, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+            acc[s] = mfma32(a4[kt], h[kt][s], acc[s]);
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            o[16 * s + lane] = acc[s][0];
+    }
+    sync();
+    return o[lane];
+}
+
 }  // namespace vct
