@@ -18,8 +18,10 @@ The JSON line also carries
 * scenarios -- the paper's comparison of trial A (correct basal rate) and trial B (basal
   rate underestimated by 50 %) on that protocol, the same 1,000,000 patients each, as two
   arms of one batched launch: TIR and the distribution of the daily insulin per arm;
-* learned -- the learned controller against exact linear MPC on common random numbers
-  (1,000,000 x 28 days by default, 1,000,000 x 364 days with --learned-full).
+* learned -- the learned controller against exact linear MPC on common random numbers,
+  1,000,000 patients x 364 days: TIR of both arms, their simulation times and speedup, and
+  a roofline for each arm (the MPC arm on the FP32 ALUs, the learned arm's network on BF16
+  MFMA beside its FP32 plant work).
 """
 from __future__ import annotations
 
@@ -33,8 +35,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FLOP_PER_PATIENT_DAY = 1440 * 64 + 288 * (6 * 4.5 + 15)   # EM steps + normals + sensor/PID
+# exact MPC arm: the PID's 13 FLOP per sample replaced by the MPC sample (50 projected-gradient
+# steps of two 300-term Toeplitz products + 48, linear term ~530, Kalman ~100)
+FLOP_MPC_SAMPLE = 50 * (2 * 2 * 300 + 48) + 530 + 100
+FLOP_MPC_PER_PATIENT_DAY = FLOP_PER_PATIENT_DAY + 288 * (FLOP_MPC_SAMPLE - 13)
+# learned arm: the network on BF16 MFMA, 2 (12*64 + 64*64 + 64*64 + 64*1) FLOP per sample;
+# FP32 besides the plant: Kalman measurement 22, linearised time update 222, inputs 6 and 7
+# 17, input normalisation 16, less the PID's 13
+FLOP_MLP_BF16_SAMPLE = 2 * (12 * 64 + 64 * 64 + 64 * 64 + 64 * 1)
+FLOP_MLP_FP32_PER_PATIENT_DAY = FLOP_PER_PATIENT_DAY + 288 * (22 + 222 + 17 + 16 - 13)
 PEAK_FP32 = 157.3e12
 PEAK_FP32_NONPACKED = 78.6e12
+PEAK_BF16 = 2.5e15
 ORACLE_SAMPLE = (10000, 364)  # patients 0..9999 of the same trial, full horizon
 ORACLE_SAMPLE_1THREAD = 200   # the oracle's single-thread rate: patients 0..199, full horizon
 
@@ -42,23 +54,25 @@ ORACLE_SAMPLE_1THREAD = 200   # the oracle's single-thread rate: patients 0..199
 PROFILE = os.path.join(ROOT, "profiles", "simulate_kernel_paper_scale_1M_x_364d.md")
 
 
-def measured_traffic():
-    """HBM bytes per simulate launch from the committed counter summary (FETCH_SIZE +
-    WRITE_SIZE, scaled by a 1 GiB copy), or None once the kernel sources have changed
-    since those counters were taken."""
+def profile_counters() -> dict:
+    """Counter figures of one simulate launch from the committed profile summary: HBM bytes
+    (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy) and the FP32 operations the kernel
+    executed (64 (ADD + MUL + TRANS) + 128 FMA per wave instruction); empty once the kernel
+    sources have changed since those counters were taken."""
     import glob
     import hashlib
     try:
         txt = open(PROFILE).read()
     except OSError:
-        return None
-    fields = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith(("traffic_bytes", "kernel_source")))
+        return {}
+    keys = ("traffic_bytes_per_launch", "executed_fp32_flop_per_launch", "kernel_source_sha256")
+    fields = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith(keys))
     h = hashlib.sha256()
     for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_13927_amd", "csrc", "*"))):
         h.update(open(f, "rb").read())
     if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
-        return None
-    return int(fields["traffic_bytes_per_launch"])
+        return {}
+    return {k: float(fields[k]) for k in keys[:2] if k in fields}
 
 
 def log(*a):
@@ -216,49 +230,67 @@ def scenarios_leg(stream) -> dict:
         bt.close()
 
 
-def learned_leg(full: bool) -> dict:
+def learned_leg(days: int, arms=("mpc", "mlp")) -> dict:
     """The learned controller against exact MPC on common random numbers: train on the MPC's
     recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
-    evaluation population with both controllers. full: 1,000,000 patients x 364 days as two
-    slices of 500,000 (each slice keeps the patients' global indices); otherwise 1,000,000 x 28
-    days. Times are the simulation launches only (HIP events); MPC setup and training are
-    reported separately."""
+    evaluation population, 1,000,000 patients x `days`, with both controllers (beyond 28 days
+    as two slices of 500,000 patients; each slice keeps the patients' global indices). Times
+    are the simulation launches only (HIP events); MPC setup and training are reported
+    separately. arms = ("mlp",) runs the learned arm alone (profiling)."""
     from paper_2202_13927_amd import learned as L, workloads as W
     t0 = time.perf_counter()
     pol, rep = L.train_policy(W.mlp_training_population(), epochs=10.0, log=log)
     train_s = time.perf_counter() - t0
-    n, days, slices = (1_000_000, 364, 2) if full else (1_000_000, 28, 1)
-    tot = {"mpc": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}, "mlp": {"s": 0.0, "bins": [0] * 5, "events": [0] * 3}}
+    n, slices = 1_000_000, (2 if days > 28 else 1)
+    tot = {a: {"s": 0.0, "bins": [0] * 5, "events": [0] * 3} for a in arms}
     setup_s = 0.0
     fb = 0.0
     always = 0
     for i in range(slices):
         ev = W.with_(W.c5_mpc(), n_patients=n // slices, first_patient=i * (n // slices), n_days=days)
-        r = L.evaluate(pol, ev, log=log)
-        for arm in ("mpc", "mlp"):
+        r = L.evaluate(pol, ev, log=log, arms=arms)
+        for arm in arms:
             tot[arm]["s"] += r[arm]["sim_s"]
             tot[arm]["bins"] = [a + b for a, b in zip(tot[arm]["bins"], r[arm]["bins"])]
             tot[arm]["events"] = [a + b for a, b in zip(tot[arm]["events"], r[arm]["events"])]
         fb += r["mlp"]["fallback_rate"] / slices
-        setup_s += r["mpc"]["setup_s"]
+        setup_s += r["mlp"]["setup_s"]
         always += r["mlp"]["patients_always_fallback"]
-        log(f"[bench] learned: slice {i + 1}/{slices} done (MPC {r['mpc']['sim_s']:.1f} s, "
-            f"network {r['mlp']['sim_s']:.1f} s)")
-    tir = {a: tot[a]["bins"][2] / sum(tot[a]["bins"]) for a in tot}
+        log(f"[bench] learned: slice {i + 1}/{slices} done (" +
+            ", ".join(f"{a} {r[a]['sim_s']:.2f} s" for a in arms) + ")")
     pd = n * days
-    return {"workload": f"{n} patients x {days} days, FP32, exact linear MPC (24 samples, 50 projected-gradient "
-                        "steps) vs 12-64-64-64-1 BF16 network with MPC fallback, common random numbers",
-            "patients": n, "days": days, "tir_mpc": tir["mpc"], "tir_mlp": tir["mlp"],
-            "delta_tir_pp": 100.0 * (tir["mlp"] - tir["mpc"]),
-            "speedup": tot["mpc"]["s"] / tot["mlp"]["s"],
-            "mpc_patient_days_per_s": pd / tot["mpc"]["s"], "mlp_patient_days_per_s": pd / tot["mlp"]["s"],
-            "mpc_sim_s": tot["mpc"]["s"], "mlp_sim_s": tot["mlp"]["s"], "fallback_rate": fb,
-            # the FP64 per-patient MPC setup, once per population (both arms need it; not in
-            # the simulation times above)
-            "mpc_setup_s": setup_s,
-            "patients_always_fallback": always, "bins_mpc": tot["mpc"]["bins"], "bins_mlp": tot["mlp"]["bins"],
-            "train_rows": rep["rounds"][-1]["rows"], "train_s": train_s,
-            "train_mse": rep["rounds"][-1]["mse_full"]}
+    t_mlp = tot["mlp"]["s"]
+    out = {"workload": f"{n} patients x {days} days, FP32, exact linear MPC (24 samples, 50 projected-gradient "
+                       "steps) vs 12-64-64-64-1 BF16 network with MPC fallback, common random numbers",
+           "patients": n, "days": days, "mlp_sim_s": t_mlp, "mlp_patient_days_per_s": pd / t_mlp,
+           "fallback_rate": fb, "patients_always_fallback": always,
+           # the FP64 per-patient MPC setup, once per population (both arms need it; not in the
+           # simulation times)
+           "mpc_setup_s": setup_s, "bins_mlp": tot["mlp"]["bins"],
+           "train_rows": rep["rounds"][-1]["rows"], "train_s": train_s, "train_mse": rep["rounds"][-1]["mse_full"],
+           # the learned arm's dominant work: the network on BF16 MFMA, and the plant with
+           # the Kalman filter on the FP32 ALUs
+           "roofline_mlp": {"bound": "mfma", "achieved": FLOP_MLP_BF16_SAMPLE * 288 * pd / t_mlp / 1e12,
+                            "peak": PEAK_BF16 / 1e12, "unit": "TFLOP/s",
+                            "frac": FLOP_MLP_BF16_SAMPLE * 288 * pd / t_mlp / PEAK_BF16,
+                            "flop_per_sample": FLOP_MLP_BF16_SAMPLE,
+                            "alu_fp32": {"achieved": FLOP_MLP_FP32_PER_PATIENT_DAY * pd / t_mlp / 1e12,
+                                         "peak": PEAK_FP32 / 1e12,
+                                         "frac": FLOP_MLP_FP32_PER_PATIENT_DAY * pd / t_mlp / PEAK_FP32,
+                                         "flop_per_patient_day": FLOP_MLP_FP32_PER_PATIENT_DAY},
+                            "kernel": "simulate_policy_kernel<float, noisy>"}}
+    if "mpc" in arms:
+        t_mpc = tot["mpc"]["s"]
+        tir = {a: tot[a]["bins"][2] / sum(tot[a]["bins"]) for a in tot}
+        out.update({"tir_mpc": tir["mpc"], "tir_mlp": tir["mlp"], "delta_tir_pp": 100.0 * (tir["mlp"] - tir["mpc"]),
+                    "speedup": t_mpc / t_mlp, "mpc_sim_s": t_mpc, "mpc_patient_days_per_s": pd / t_mpc,
+                    "bins_mpc": tot["mpc"]["bins"],
+                    "roofline_mpc": {"bound": "alu", "achieved": FLOP_MPC_PER_PATIENT_DAY * pd / t_mpc / 1e12,
+                                     "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                                     "frac": FLOP_MPC_PER_PATIENT_DAY * pd / t_mpc / PEAK_FP32,
+                                     "flop_per_patient_day": FLOP_MPC_PER_PATIENT_DAY,
+                                     "kernel": "simulate_kernel<float, MPC, noisy>"}})
+    return out
 
 
 def main() -> int:
@@ -275,8 +307,10 @@ def main() -> int:
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scales HBM byte counters)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-controller comparison")
-    ap.add_argument("--learned-full", action="store_true",
-                    help="run the learned-controller comparison at 1,000,000 x 364 days (minutes)")
+    ap.add_argument("--learned-days", type=int, default=364,
+                    help="horizon of the learned-controller comparison (1,000,000 patients; 364 = the paper's year)")
+    ap.add_argument("--learned-arms", default="mpc,mlp", choices=("mpc,mlp", "mlp"),
+                    help="mlp: the learned arm alone (no speedup or TIR difference; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
@@ -335,7 +369,9 @@ def main() -> int:
     value = pdays * args.steps / dt
     kern_s = sum(sim_ms) / len(sim_ms) / 1e3
     achieved = FLOP_PER_PATIENT_DAY * pdays / kern_s
-    traffic = measured_traffic() if (n, days) == (1_000_000, 364) else None
+    prof = profile_counters() if (n, days) == (1_000_000, 364) else {}
+    traffic = int(prof["traffic_bytes_per_launch"]) if "traffic_bytes_per_launch" in prof else None
+    executed = prof.get("executed_fp32_flop_per_launch")
     out = {
         "metric": "patient-days simulated/s (1 GPU) + %FP32 roofline; MLP vs exact MPC at TIR \u0394\u22640.5pp",
         "value": value,
@@ -358,9 +394,21 @@ def main() -> int:
                      "algorithmic_bytes": 208 * n,
                      "kernel": "simulate_kernel<float, PID, noisy>", "kernel_ms": kern_s * 1e3,
                      "frac_nonpacked_peak": achieved / PEAK_FP32_NONPACKED,
-                     "flop_per_patient_day": FLOP_PER_PATIENT_DAY},
+                     "flop_per_patient_day": FLOP_PER_PATIENT_DAY,
+                     # `achieved` and `frac` count the method's FP32 work (the canonical count per
+                     # patient-day); the counters give what the kernel executed instead (reciprocals
+                     # and folded constants make it less), over the same launch time
+                     "executed_counters": (None if executed is None else
+                                           {"flop_per_launch": executed,
+                                            "achieved": executed / kern_s / 1e12,
+                                            "frac": executed / kern_s / PEAK_FP32,
+                                            "frac_nonpacked_peak": executed / kern_s / PEAK_FP32_NONPACKED})},
         "summary": {"mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"], "mean_bg_mmol": s["mean_bg"],
-                    "worst_min_g": s["worst_min_g"], "status_count": s["status_count"]},
+                    "worst_min_g": s["worst_min_g"], "status_count": s["status_count"],
+                    # the same without the flagged patients (non-finite state, negative Q1 or
+                    # the resampling fallback)
+                    "n_flagged": n - s["n_clean"], "mean_tir_unflagged": s["mean_tir_clean"],
+                    "tir_quantiles_unflagged": s["q_frac_clean"], "mean_bg_mmol_unflagged": s["mean_bg_clean"]},
         "paper_context": {"patient_days_per_s": 3.64e8 / 4920.0,
                           "note": "1M patients x 52 weeks in 1 h 22 min on 2x EPYC 7542, dual-hormone AP, 30 s step"},
     }
@@ -371,7 +419,7 @@ def main() -> int:
         out["nordic"] = nordic_leg(stream)
         out["scenarios"] = scenarios_leg(stream)
     if not args.no_learned:
-        out["learned"] = learned_leg(args.learned_full)
+        out["learned"] = learned_leg(args.learned_days, tuple(args.learned_arms.split(",")))
     if not args.no_cpu_baseline:
         log("[bench] timing the FP64 oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(trial)

@@ -88,13 +88,16 @@ def train_policy(train_trial: dict, epochs: float = 10.0, batch: int = 4096, lr:
     return pol, rep
 
 
-def evaluate(pol: PL.Policy, mpc_trial: dict, log=print) -> dict:
+def evaluate(pol: PL.Policy, mpc_trial: dict, log=print, arms=("mpc", "mlp")) -> dict:
     """Step 3 on the evaluation population; each arm is one simulation launch, timed with
     HIP events. The MPC setup (both arms need it: the learned arm for its fallback and
-    inputs) is timed separately; the reduction is outside the timed region."""
+    inputs) is timed separately; the reduction is outside the timed region. arms selects
+    the arms to run."""
     mlp_trial = W.with_(mpc_trial, ctrl_kind=W.CTRL_MLP)
     out = {}
     for name, t in (("mpc", mpc_trial), ("mlp", mlp_trial)):
+        if name not in arms:
+            continue
         bufs = T.TrialBuffers(t)
         pop = T.create_population(t, bufs)
         torch.cuda.synchronize()
@@ -115,6 +118,7 @@ def evaluate(pol: PL.Policy, mpc_trial: dict, log=print) -> dict:
             (f", fallback {r['fallback_rate']:.4%}" if name == "mlp" else ""))
         del bufs
         torch.cuda.empty_cache()
-    out["delta_tir_pp"] = 100.0 * (out["mlp"]["tir"] - out["mpc"]["tir"])
-    out["speedup"] = out["mpc"]["sim_s"] / out["mlp"]["sim_s"]
+    if "mpc" in out and "mlp" in out:
+        out["delta_tir_pp"] = 100.0 * (out["mlp"]["tir"] - out["mpc"]["tir"])
+        out["speedup"] = out["mpc"]["sim_s"] / out["mlp"]["sim_s"]
     return out
