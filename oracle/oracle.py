@@ -14,6 +14,7 @@ import numpy as np
 from . import build as _build
 
 NP, NX, NPOUT, MAX_SLOTS = 15, 11, 19, 4
+NXE = 5   # extension states: Z1, Z2 (glucagon), E1, E2, E3 (exercise)
 INT_EM, INT_RK4 = 0, 1
 
 
@@ -33,6 +34,13 @@ class OrcConfig(C.Structure):
         ("mpc_horizon", C.c_int32), ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double),
         ("mpc_riccati_iters", C.c_int32), ("mpc_power_iters", C.c_int32), ("mlp", C.c_void_p),
         ("mlp_safe_g", C.c_double), ("mlp_safe_out", C.c_double),
+        ("model_ext", C.c_int32), ("tau_n", C.c_double), ("e_n", C.c_double), ("tau_e1", C.c_double),
+        ("tau_e2", C.c_double), ("tau_e3", C.c_double), ("alpha_e", C.c_double), ("beta_e", C.c_double),
+        ("exercise", C.c_int32), ("exercise_minute", C.c_int32), ("exercise_duration", C.c_int32),
+        ("exercise_hrr", C.c_double), ("hrr_const", C.c_double), ("un_open", C.c_double),
+        ("meal_bolus", C.c_int32), ("icr_rule", C.c_double), ("glu_enter", C.c_double), ("glu_exit", C.c_double),
+        ("glu_target", C.c_double), ("glu_kp", C.c_double), ("glu_max", C.c_double), ("ex_bolus", C.c_double),
+        ("ex_bolus_below", C.c_double),
     ]
 
 
@@ -70,6 +78,7 @@ class OrcOutputs(C.Structure):
         ("n_near", _P(C.c_int32)), ("ctrl_margin", _P(C.c_double)), ("params", _P(C.c_double)),
         ("n_traj", C.c_int32), ("traj_g", _P(C.c_double)), ("traj_y", _P(C.c_double)), ("traj_u", _P(C.c_double)),
         ("traj_x", _P(C.c_double)), ("record", _P(C.c_double)), ("fallback", _P(C.c_int32)),
+        ("doses", _P(C.c_double)), ("traj_xe", _P(C.c_double)),
     ]
 
 
@@ -104,6 +113,13 @@ def lib() -> C.CDLL:
                               _P(C.c_double)]
         L.orc_simulate.argtypes = [_P(OrcConfig), C.c_int64, C.c_int64, C.c_int, _P(OrcOutputs)]
         L.orc_simulate.restype = C.c_int
+        L.orc_rhs_ext.argtypes = [_P(OrcConfig), _P(C.c_double), _P(C.c_double), _P(C.c_double), C.c_double,
+                                  C.c_double, C.c_double, C.c_double, _P(C.c_double), _P(C.c_double)]
+        L.orc_day_exercise.argtypes = [_P(OrcConfig), C.c_uint32, C.c_int32]
+        L.orc_day_exercise.restype = C.c_int32
+        L.orc_dual_run.argtypes = [_P(OrcConfig), C.c_double, C.c_double, C.c_double, C.c_int32, _P(C.c_double),
+                                   _P(C.c_double),
+                                   _P(C.c_int32), _P(C.c_double), _P(C.c_double), _P(C.c_double), _P(C.c_int32)]
         L.orc_em_ou.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double, C.c_int32, C.c_int64,
                                 C.c_uint64, _P(C.c_double)]
         L.orc_reduce.argtypes = [C.c_int64, C.c_int64, _P(C.c_int32), _P(C.c_int32), _P(C.c_double),
@@ -177,6 +193,12 @@ def config(trial: dict, integrator: int = INT_EM, rk4_sub: int = 64, x0_offset=N
     c.mpc_power_iters = int(trial.get("mpc_power_iters", 100))
     c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.0))
     c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
+    for k in ("model_ext", "exercise", "exercise_minute", "exercise_duration", "meal_bolus"):
+        setattr(c, k, int(trial.get(k, 0)))
+    for k in ("tau_n", "e_n", "tau_e1", "tau_e2", "tau_e3", "alpha_e", "beta_e", "exercise_hrr", "hrr_const",
+              "un_open", "icr_rule", "glu_enter", "glu_exit", "glu_target", "glu_kp", "glu_max", "ex_bolus",
+              "ex_bolus_below"):
+        setattr(c, k, float(trial.get(k, 0.0)))
     return c
 
 
@@ -230,6 +252,37 @@ def rhs(trial: dict, p, x, u: float, d: float) -> np.ndarray:
     lib().orc_rhs(C.byref(cfg), _ptr(pa, C.c_double), _ptr(xa, C.c_double), float(u), float(d),
                   _ptr(dx, C.c_double))
     return dx
+
+
+def rhs_ext(trial: dict, p, x, xe, u: float, un: float, d: float, hrr: float) -> tuple[np.ndarray, np.ndarray]:
+    cfg = config(trial)
+    pa = np.ascontiguousarray(p, dtype=np.float64)
+    xa = np.ascontiguousarray(x, dtype=np.float64)
+    xea = np.ascontiguousarray(xe, dtype=np.float64)
+    dx, dxe = np.zeros(NX), np.zeros(NXE)
+    lib().orc_rhs_ext(C.byref(cfg), _ptr(pa, C.c_double), _ptr(xa, C.c_double), _ptr(xea, C.c_double), float(u),
+                      float(un), float(d), float(hrr), _ptr(dx, C.c_double), _ptr(dxe, C.c_double))
+    return dx, dxe
+
+
+def day_exercise(trial: dict, patient: int, day: int) -> int:
+    """Sample index within the day of the patient's exercise onset, -1 if none."""
+    return int(lib().orc_day_exercise(C.byref(config(trial)), int(patient), int(day)))
+
+
+def dual_run(trial: dict, ub: float, y, d, ex, iob: float = 0.0, gob: float = 0.0) -> dict:
+    """Scripted dual-hormone AP: basal and bolus insulin (mU/min), glucagon (ug/min), mode;
+    insulin and glucagon on board held at iob (mU above basal) and gob (ug)."""
+    ya = np.ascontiguousarray(y, dtype=np.float64)
+    da = np.ascontiguousarray(d, dtype=np.float64)
+    ea = np.ascontiguousarray(ex, dtype=np.int32)
+    n = len(ya)
+    out = {"u_basal": np.zeros(n), "u_bolus": np.zeros(n), "un": np.zeros(n), "mode": np.zeros(n, np.int32)}
+    lib().orc_dual_run(C.byref(config(trial)), float(ub), float(iob), float(gob), n, _ptr(ya, C.c_double),
+                       _ptr(da, C.c_double),
+                       _ptr(ea, C.c_int32), _ptr(out["u_basal"], C.c_double), _ptr(out["u_bolus"], C.c_double),
+                       _ptr(out["un"], C.c_double), _ptr(out["mode"], C.c_int32))
+    return out
 
 
 def em_ou(theta: float, s: float, x0: float, h: float, n_steps: int, n_paths: int, seed: int) -> np.ndarray:
@@ -402,6 +455,8 @@ def simulate(trial: dict, first: int | None = None, count: int | None = None, th
         r["traj_u"] = np.zeros((nt, K))
         if record_x:
             r["traj_x"] = np.zeros((nt, K, NX))
+            if int(trial.get("model_ext", 0)):
+                r["traj_xe"] = np.zeros((nt, K, NXE))
     o = OrcOutputs()
     o.bins, o.events = _ptr(r["bins"], C.c_int32), _ptr(r["events"], C.c_int32)
     o.sum_g, o.min_g = _ptr(r["sum_g"], C.c_double), _ptr(r["min_g"], C.c_double)
@@ -413,6 +468,9 @@ def simulate(trial: dict, first: int | None = None, count: int | None = None, th
     o.traj_y = _ptr(r.get("traj_y"), C.c_double)
     o.traj_u = _ptr(r.get("traj_u"), C.c_double)
     o.traj_x = _ptr(r.get("traj_x"), C.c_double)
+    o.traj_xe = _ptr(r.get("traj_xe"), C.c_double)
+    r["doses"] = np.zeros((n, 3))
+    o.doses = _ptr(r["doses"], C.c_double)
     if record:
         r["record"] = np.zeros((K, n, MLP_IN + 1))
     r["fallback"] = np.zeros(n, np.int32)

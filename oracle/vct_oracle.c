@@ -97,6 +97,7 @@ enum { P_EGP0, P_F01, P_K12, P_KA1, P_KA2, P_KA3, P_SIT, P_SID, P_SIE, P_KE, P_V
        P_TMAXI, P_TMAXG, P_BW };
 /* State order. */
 enum { X_D1, X_D2, X_S1, X_S2, X_I, X_X1, X_X2, X_X3, X_Q1, X_Q2, X_GI };
+enum { XE_Z1, XE_Z2, XE_E1, XE_E2, XE_E3 };
 
 /* Hovorka core (glucose absorption, subcutaneous insulin, insulin action on
  * transport, disposal and endogenous production, two glucose compartments) and
@@ -141,6 +142,57 @@ void orc_rhs(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_N
     dx[X_Q1] = -f01c - x[X_X1] * x[X_Q1] + k12 * x[X_Q2] - fr + ug + egp0 * fmax(0.0, 1.0 - x[X_X3]);
     dx[X_Q2] = x[X_X1] * x[X_Q1] - (k12 + x[X_X2]) * x[X_Q2];
     dx[X_GI] = (G - x[X_GI]) / cfg->tau_cgm;
+}
+
+/* The model extensions of Sec. IV-B (this project's reading; the paper cites the models
+ * without their equations, and their parameters are shared by all patients):
+ *  - subcutaneous glucagon, two states with equal time constants tau_n (ug):
+ *      dZ1 = u_N - Z1/tau_n,  dZ2 = (Z1 - Z2)/tau_n,  appearance U_N = Z2/tau_n (ug/min),
+ *    which adds e_n U_N (mmol/min) to the hepatic glucose output, outside the insulin clip:
+ *      EGP = EGP0 max(0, 1 - x3) + e_n U_N;
+ *  - exercise, three states driven by the heart-rate reserve fraction HRR in [0, 1]:
+ *      dE1 = (HRR - E1)/tau_e1  (heart rate),
+ *      dE2 = (E1 - E2)/tau_e2   (insulin-independent glucose uptake, -alpha_e E2 Q1),
+ *      dE3 = (E1 - E3)/tau_e3   (insulin action raised: x1 and x2 act as x1 (1 + beta_e E3),
+ *                                x2 (1 + beta_e E3) on glucose transport and disposal).
+ * With u_N = 0 and HRR = 0 from the basal state the extension states stay 0 and the core
+ * model is unchanged. */
+void orc_rhs_ext(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_NX], const double xe[ORC_NXE],
+                 double u, double un, double d, double hrr, double dx[ORC_NX], double dxe[ORC_NXE])
+{
+    double bw = p[P_BW];
+    double egp0 = p[P_EGP0] * bw, f01 = p[P_F01] * bw;
+    double vi = p[P_VI] * bw, vg = p[P_VG] * bw;
+    double k12 = p[P_K12], ke = p[P_KE];
+    double ka1 = p[P_KA1], ka2 = p[P_KA2], ka3 = p[P_KA3];
+    double sit = p[P_SIT], sid = p[P_SID], sie = p[P_SIE];
+    double tmaxi = p[P_TMAXI], tmaxg = p[P_TMAXG];
+
+    double G = x[X_Q1] / vg;
+    double ug = x[X_D2] / tmaxg;
+    double ui = x[X_S2] / tmaxi;
+    double f01c = f01 * fmin(1.0, G / 4.5);
+    double fr = (G > 9.0) ? 0.003 * (G - 9.0) * vg : 0.0;
+    double gain = 1.0 + cfg->beta_e * xe[XE_E3];
+    double x1e = x[X_X1] * gain, x2e = x[X_X2] * gain;
+    double egp = egp0 * fmax(0.0, 1.0 - x[X_X3]) + cfg->e_n * xe[XE_Z2] / cfg->tau_n;
+
+    dx[X_D1] = cfg->ag * d - x[X_D1] / tmaxg;
+    dx[X_D2] = (x[X_D1] - x[X_D2]) / tmaxg;
+    dx[X_S1] = u - x[X_S1] / tmaxi;
+    dx[X_S2] = (x[X_S1] - x[X_S2]) / tmaxi;
+    dx[X_I]  = ui / vi - ke * x[X_I];
+    dx[X_X1] = -ka1 * x[X_X1] + ka1 * sit * x[X_I];
+    dx[X_X2] = -ka2 * x[X_X2] + ka2 * sid * x[X_I];
+    dx[X_X3] = -ka3 * x[X_X3] + ka3 * sie * x[X_I];
+    dx[X_Q1] = -f01c - x1e * x[X_Q1] + k12 * x[X_Q2] - fr + ug + egp - cfg->alpha_e * xe[XE_E2] * x[X_Q1];
+    dx[X_Q2] = x1e * x[X_Q1] - (k12 + x2e) * x[X_Q2];
+    dx[X_GI] = (G - x[X_GI]) / cfg->tau_cgm;
+    dxe[XE_Z1] = un - xe[XE_Z1] / cfg->tau_n;
+    dxe[XE_Z2] = (xe[XE_Z1] - xe[XE_Z2]) / cfg->tau_n;
+    dxe[XE_E1] = (hrr - xe[XE_E1]) / cfg->tau_e1;
+    dxe[XE_E2] = (xe[XE_E1] - xe[XE_E2]) / cfg->tau_e2;
+    dxe[XE_E3] = (xe[XE_E1] - xe[XE_E3]) / cfg->tau_e3;
 }
 
 /* Basal steady state at G* = g_target with D = 0 (and x3* < 1). Setting dQ1 = dQ2 = 0 and
@@ -418,6 +470,41 @@ int orc_day_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *
     return n;
 }
 
+/* Exercise (Sec. II-B: the active day has an exercise session; this project's reading of
+ * its time and form): on each active day of the Northern-European protocol one session of
+ * exercise_duration minutes at heart-rate reserve fraction exercise_hrr, starting in the
+ * sample that contains exercise_minute + jitter, the jitter drawn like a meal's from word 2
+ * of Philox block (day, patient, EXER, 0); the input is held over whole sampling intervals:
+ * ceil(duration / Ts) samples from the onset. */
+#define TAG_EXER 9u
+static int32_t exercise_onset(const orc_config *cfg, uint32_t patient, int32_t day, const uint32_t key[2])
+{
+    if (!cfg->model_ext || !cfg->exercise || cfg->proto != ORC_PROTO_NORDIC)
+        return -1;
+    int season, wtype, dtype;
+    nordic_day_types(patient, day, key, &season, &wtype, &dtype);
+    if (dtype != 1)
+        return -1;
+    uint32_t ctr[4] = {(uint32_t)day, patient, TAG_EXER, 0u};
+    uint32_t x[4];
+    orc_philox4x32_10(ctr, key, x);
+    uint32_t odd = 2u * (x[2] >> 9) + 1u;
+    int32_t jit = (int32_t)(((uint64_t)odd * (uint64_t)(2 * cfg->jitter + 1)) >> 24) - cfg->jitter;
+    return (cfg->exercise_minute + jit) / cfg->ts_min;
+}
+
+static int32_t exercise_samples(const orc_config *cfg)
+{
+    return (cfg->exercise_duration + cfg->ts_min - 1) / cfg->ts_min;
+}
+
+int32_t orc_day_exercise(const orc_config *cfg, uint32_t patient, int32_t day)
+{
+    uint32_t key[2];
+    make_key(cfg->noise_seed, cfg->arm_id, key);
+    return exercise_onset(cfg, patient, day, key);
+}
+
 /* Meal draws of one (patient, day), for tests: out [n_slots][4] = (present, sample
  * index within the day, carbs in g, jitter in min); absent slots keep their draw. */
 void orc_meals(const orc_config *cfg, uint32_t patient, int32_t day, double *out)
@@ -459,6 +546,29 @@ static void rk4_step(const orc_config *cfg, const double p[ORC_NP], double x[ORC
     orc_rhs(cfg, p, t, u, d, k4);
     for (int i = 0; i < ORC_NX; ++i)
         x[i] = x[i] + h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
+}
+
+/* The same on the extended model's 16 states (X = core states, then the extension's). */
+static void rhs16(const orc_config *cfg, const double p[ORC_NP], const double X[ORC_NX + ORC_NXE], double u,
+                  double un, double d, double hrr, double F[ORC_NX + ORC_NXE])
+{
+    orc_rhs_ext(cfg, p, X, X + ORC_NX, u, un, d, hrr, F, F + ORC_NX);
+}
+
+static void rk4_step_ext(const orc_config *cfg, const double p[ORC_NP], double X[ORC_NX + ORC_NXE], double u,
+                         double un, double d, double hrr, double h)
+{
+    enum { N = ORC_NX + ORC_NXE };
+    double k1[N], k2[N], k3[N], k4[N], t[N];
+    rhs16(cfg, p, X, u, un, d, hrr, k1);
+    for (int i = 0; i < N; ++i) t[i] = X[i] + 0.5 * h * k1[i];
+    rhs16(cfg, p, t, u, un, d, hrr, k2);
+    for (int i = 0; i < N; ++i) t[i] = X[i] + 0.5 * h * k2[i];
+    rhs16(cfg, p, t, u, un, d, hrr, k3);
+    for (int i = 0; i < N; ++i) t[i] = X[i] + h * k3[i];
+    rhs16(cfg, p, t, u, un, d, hrr, k4);
+    for (int i = 0; i < N; ++i)
+        X[i] += h / 6.0 * (k1[i] + 2.0 * k2[i] + 2.0 * k3[i] + k4[i]);
 }
 
 void orc_em_ou(double theta, double s, double x0, double h, int32_t n_steps, int64_t n_paths, uint64_t seed,
@@ -569,6 +679,67 @@ void orc_pid_run(const orc_config *cfg, double ub, int32_t n, const double *y, d
         u[k] = pid_step(cfg, &c, y[k], ub, &margin);
         if (integ)
             integ[k] = c.integ;
+    }
+}
+
+/* ------------------------------------------------- dual-hormone AP ---- */
+/* Sec. IV-C names the parts of the paper's AP; their laws are this project's reading.
+ * Modes: glucagon mode is entered when y_k < glu_enter and left when y_k >= glu_exit.
+ *  - insulin mode: microadjustments of the basal rate by the PID above (the PID runs on
+ *    every sample, its integral with its own conditional rule, but its output is delivered
+ *    only in this mode), plus a meal bolus at each announced meal (meal_bolus = 1): carbs / ICR with
+ *    ICR = icr_rule / TDD (g/U) and TDD = 2 x the daily basal insulin (U/day), less the
+ *    insulin on board above basal (subcutaneous depot S1 + S2 minus its basal 2 u_b tmaxI),
+ *    never negative, delivered over the meal's interval; no glucagon;
+ *  - glucagon mode: no insulin; a glucagon microbolus glu_kp (glu_target - y_k) less the
+ *    glucagon on board (depot Z1 + Z2), clamped to [0, glu_max] ug, over the interval;
+ *  - in either mode, an exercise onset with y_k < ex_bolus_below adds an ex_bolus ug
+ *    glucagon bolus over the interval.
+ * The insulin and glucagon on board are those of a controller-side replica of the depots
+ * driven by the delivered doses; both subsystems are deterministic, so the replica equals
+ * the plant's states and is read from them. Announced carbs: the held intake d (mmol/min)
+ * over Ts minutes, 180.16/1000 g per mmol. */
+typedef struct { pid_t_ pid; int glu; } dual_t;
+
+static void dual_step(const orc_config *cfg, dual_t *st, double y, double ub, double iob, double gob, double d,
+                      int ex_onset, double *u_basal, double *u_bolus, double *un, double *margin)
+{
+    const double ts = (double)cfg->ts_min;
+    if (!st->glu && y < cfg->glu_enter)
+        st->glu = 1;
+    else if (st->glu && y >= cfg->glu_exit)
+        st->glu = 0;
+    double n_ug = 0.0;
+    const double u_pid = pid_step(cfg, &st->pid, y, ub, margin);
+    if (st->glu) {
+        *u_basal = 0.0;
+        *u_bolus = 0.0;
+        n_ug = fmin(cfg->glu_max, fmax(0.0, cfg->glu_kp * (cfg->glu_target - y) - gob));
+    } else {
+        *u_basal = u_pid;
+        double bolus_mu = 0.0;
+        if (cfg->meal_bolus && d > 0.0) {
+            double carbs = d * ts * 180.16 / 1000.0;
+            double tdd = 2.0 * ub * 1440.0 / 1000.0;
+            bolus_mu = fmax(0.0, carbs / (cfg->icr_rule / tdd) * 1000.0 - iob);
+        }
+        *u_bolus = bolus_mu / ts;
+    }
+    if (ex_onset && y < cfg->ex_bolus_below)
+        n_ug += cfg->ex_bolus;
+    *un = n_ug / ts;
+}
+
+/* Scripted run for tests: insulin and glucagon on board held at iob and gob. */
+void orc_dual_run(const orc_config *cfg, double ub, double iob, double gob, int32_t n, const double *y,
+                  const double *d, const int32_t *ex, double *u_basal, double *u_bolus, double *un, int32_t *mode)
+{
+    dual_t st;
+    memset(&st, 0, sizeof st);
+    double margin = INFINITY;
+    for (int32_t k = 0; k < n; ++k) {
+        dual_step(cfg, &st, y[k], ub, iob, gob, d[k], ex[k], &u_basal[k], &u_bolus[k], &un[k], &margin);
+        mode[k] = st.glu;
     }
 }
 
@@ -1162,6 +1333,11 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
     sig[X_Q1] = cfg->sigma_q1;
     const double vg = p[P_VG] * p[P_BW];
     pid_t_ pid = {0.0, 0.0, 0};
+    dual_t dual;
+    memset(&dual, 0, sizeof dual);
+    double xe[ORC_NXE] = {0};           /* extension states (model_ext): 0 at the basal state */
+    double dose_basal = 0.0, dose_bolus = 0.0, dose_glucagon = 0.0;
+    const int32_t n_ex = exercise_samples(cfg);
     int is_traj = j < out->n_traj;
     mpc_state *mpc = NULL;
     int32_t fallbacks = 0;
@@ -1197,6 +1373,7 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
     for (int32_t day = 0; day < cfg->n_days; ++day) {
         meal_t meals[ORC_MAX_DAY_MEALS];
         int nm = meals_for_day(cfg, patient, day, p[14], nkey, meals);
+        const int32_t ex0 = exercise_onset(cfg, patient, day, nkey);
         for (int32_t kd = 0; kd < kday; ++kd) {
             int64_t k = (int64_t)day * kday + kd;
             double G = x[X_Q1] / vg;
@@ -1233,15 +1410,25 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
                     for (int q = 0; q < ORC_MLP_IN; ++q) f[q] = NAN;
             }
 
-            double u;
-            if (cfg->ctrl_kind == ORC_CTRL_PID)
+            /* exercise input of this interval (model extensions) */
+            const int in_session = ex0 >= 0 && kd >= ex0 && kd < ex0 + n_ex;
+            const double hrr = cfg->hrr_const + (in_session ? cfg->exercise_hrr : 0.0);
+            double u, un = 0.0, u_bolus = 0.0, u_basal = NAN;
+            if (cfg->ctrl_kind == ORC_CTRL_DUAL) {
+                const double iob = x[X_S1] + x[X_S2] - 2.0 * ub * p[P_TMAXI];
+                const double gob = xe[XE_Z1] + xe[XE_Z2];
+                dual_step(cfg, &dual, y, ub, iob, gob, d, kd == ex0, &u_basal, &u_bolus, &un, &a.ctrl_margin);
+                u = u_basal + u_bolus;
+            } else if (cfg->ctrl_kind == ORC_CTRL_PID)
                 u = pid_step(cfg, &pid, y, cfg->basal_scale * ub, &a.ctrl_margin);
             else if (cfg->ctrl_kind == ORC_CTRL_MPC)
                 u = mpc ? mpc_step(cfg, mpc, y, d) : NAN;
             else if (cfg->ctrl_kind == ORC_CTRL_MLP)
                 u = mpc ? mlp_step(cfg, mpc, f, y, d, &fallbacks, out->record ? &label : NULL) : NAN;
-            else
+            else {
                 u = cfg->u_rel * (cfg->basal_scale * ub);
+                un = cfg->un_open;
+            }
 
             if (use_inputs) {
                 for (int i = 5; i > 0; --i) yh[i] = yh[i - 1];
@@ -1258,9 +1445,31 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
                 if (out->traj_u) out->traj_u[j * K + k] = u;
                 if (out->traj_x)
                     for (int i = 0; i < ORC_NX; ++i) out->traj_x[(j * K + k) * ORC_NX + i] = x[i];
+                if (out->traj_xe)
+                    for (int i = 0; i < ORC_NXE; ++i) out->traj_xe[(j * K + k) * ORC_NXE + i] = xe[i];
             }
 
-            if (cfg->integrator == ORC_INT_RK4) {
+            if (cfg->model_ext) {   /* the extended model on its 16 states */
+                double X[ORC_NX + ORC_NXE];
+                memcpy(X, x, sizeof x);
+                memcpy(X + ORC_NX, xe, sizeof xe);
+                if (cfg->integrator == ORC_INT_RK4) {
+                    double hr = (double)ts / (double)cfg->rk4_sub;
+                    for (int s = 0; s < cfg->rk4_sub; ++s)
+                        rk4_step_ext(cfg, p, X, u, un, d, hrr, hr);
+                } else {
+                    double sig16[ORC_NX + ORC_NXE] = {0};
+                    sig16[X_Q1] = cfg->sigma_q1;
+                    for (int s = 0; s < M; ++s) {
+                        double F[ORC_NX + ORC_NXE], xi[ORC_NX + ORC_NXE] = {0};
+                        rhs16(cfg, p, X, u, un, d, hrr, F);
+                        xi[X_Q1] = z[s];
+                        em_step(ORC_NX + ORC_NXE, X, F, h, sqrt_h, sig16, xi);
+                    }
+                }
+                memcpy(x, X, sizeof x);
+                memcpy(xe, X + ORC_NX, sizeof xe);
+            } else if (cfg->integrator == ORC_INT_RK4) {
                 double hr = (double)ts / (double)cfg->rk4_sub;
                 for (int s = 0; s < cfg->rk4_sub; ++s)
                     rk4_step(cfg, p, x, u, d, hr);
@@ -1273,10 +1482,21 @@ static void simulate_patient(const orc_config *cfg, int64_t j, int64_t count, ui
                 }
             }
             a.sum_u += u * (double)ts;
+            dose_basal += (cfg->ctrl_kind == ORC_CTRL_DUAL ? u_basal : u) * (double)ts;
+            dose_bolus += u_bolus * (double)ts;
+            dose_glucagon += un * (double)ts;
         }
         for (int i = 0; i < ORC_NX; ++i)
             if (!isfinite(x[i]))
                 a.status |= ORC_ST_NONFINITE;
+        for (int i = 0; i < ORC_NXE; ++i)
+            if (!isfinite(xe[i]))
+                a.status |= ORC_ST_NONFINITE;
+    }
+    if (out->doses) {
+        out->doses[j * 3 + 0] = dose_basal;
+        out->doses[j * 3 + 1] = dose_bolus;
+        out->doses[j * 3 + 2] = dose_glucagon;
     }
     free(mpc);
 

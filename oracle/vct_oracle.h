@@ -38,6 +38,10 @@ extern "C" {
 #define ORC_CTRL_PID  1
 #define ORC_CTRL_MPC  2
 #define ORC_CTRL_MLP  3
+#define ORC_CTRL_DUAL 4    /* dual-hormone AP (insulin mode / glucagon mode), model extensions on */
+
+/* states of the model extensions (Sec. IV-B), after the 11 core states */
+#define ORC_NXE 5          /* Z1, Z2 (subcutaneous glucagon), E1, E2, E3 (exercise) */
 
 /* integrators */
 #define ORC_INT_EM  0      /* Euler-Maruyama with em_per_ctrl substeps          */
@@ -98,6 +102,27 @@ typedef struct {
        the safety hand-over: the MPC acts when y_k < mlp_safe_g and out > mlp_safe_out */
     const struct orc_mlp_s *mlp;
     double   mlp_safe_g, mlp_safe_out;
+    /* model extensions of Sec. IV-B, parameters shared by all patients (model_ext = 0: the
+       core model alone, every other field below unused) */
+    int32_t  model_ext;
+    double   tau_n;             /* subcutaneous glucagon absorption time constant, min       */
+    double   e_n;               /* hepatic glucose output per glucagon appearance, mmol/ug    */
+    double   tau_e1, tau_e2, tau_e3;   /* exercise: heart rate, uptake, sensitivity; min      */
+    double   alpha_e;           /* insulin-independent uptake at full effect, 1/min           */
+    double   beta_e;            /* relative rise of insulin action at full effect             */
+    /* exercise sessions on the Northern-European protocol's active days (Sec. II-B) */
+    int32_t  exercise;          /* 0/1 */
+    int32_t  exercise_minute;   /* clock minute of the onset before its jitter                */
+    int32_t  exercise_duration; /* minutes                                                    */
+    double   exercise_hrr;      /* heart-rate reserve fraction during a session               */
+    double   hrr_const;         /* tests: heart-rate reserve fraction held at every sample    */
+    double   un_open;           /* open-loop mode: glucagon infusion, ug/min                  */
+    /* dual-hormone AP (ORC_CTRL_DUAL, Sec. IV-C) */
+    int32_t  meal_bolus;        /* 0/1: meal bolus calculator in insulin mode                 */
+    double   icr_rule;          /* ICR = icr_rule / TDD g/U, TDD = 2 x daily basal insulin     */
+    double   glu_enter, glu_exit;   /* glucagon mode when y < glu_enter, insulin mode again at y >= glu_exit */
+    double   glu_target, glu_kp, glu_max;   /* microbolus min(glu_max, glu_kp (glu_target - y)) ug */
+    double   ex_bolus, ex_bolus_below;      /* ug at an exercise onset when y < ex_bolus_below   */
 } orc_config;
 
 /* Learned controller: 12 inputs -> 64 -> 64 -> 64 -> 1, ReLU hidden layers. The inputs are
@@ -148,6 +173,8 @@ typedef struct {
     double   *record;      /* [K][count][13] controller inputs, then the MPC's action / u_b
                               (MPC; MLP: the QP is then solved on every sample) or NULL */
     int32_t  *fallback;    /* [count] samples on which the MPC acted for the MLP, or NULL */
+    double   *doses;       /* [count][3] basal insulin mU, bolus insulin mU, glucagon ug, or NULL */
+    double   *traj_xe;     /* [n_traj][K][ORC_NXE] extension states at each sample, or NULL */
 } orc_outputs;
 
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11). */
@@ -203,6 +230,22 @@ void     orc_mlp_batch_rows(uint64_t seed, int32_t step, int64_t B, int64_t n_ro
 void     orc_mlp_stats(const double *rows, int64_t n, double box_q, orc_mlp *net);
 /* Adam step t (1-based) with beta 0.9 / 0.999, eps 1e-8 on n parameters. */
 void     orc_adam(int64_t n, double *w, double *m, double *v, const double *g, double lr, int64_t t);
+
+/* The extended model (Sec. IV-B, model_ext = 1): the core drift plus subcutaneous glucagon
+ * and the effect of exercise; xe = (Z1, Z2, E1, E2, E3), un glucagon ug/min, hrr the
+ * heart-rate reserve fraction. */
+void     orc_rhs_ext(const orc_config *cfg, const double p[ORC_NP], const double x[ORC_NX],
+                     const double xe[ORC_NXE], double u, double un, double d, double hrr, double dx[ORC_NX],
+                     double dxe[ORC_NXE]);
+/* Sample index within the day of patient's exercise onset on that day, -1 if none. */
+int32_t  orc_day_exercise(const orc_config *cfg, uint32_t patient, int32_t day);
+/* Scripted dual-hormone AP run for tests: inputs y[k], announced intake d[k] (mmol/min) and
+ * exercise onsets ex[k] (0/1), insulin on board above basal iob (mU) and glucagon on board
+ * gob (ug) held fixed; outputs basal and bolus insulin rates (mU/min), glucagon rate
+ * (ug/min) and the mode (1 = glucagon) after each decision. */
+void     orc_dual_run(const orc_config *cfg, double ub, double iob, double gob, int32_t n, const double *y,
+                      const double *d, const int32_t *ex, double *u_basal, double *u_bolus, double *un,
+                      int32_t *mode);
 
 /* Closed-loop Monte Carlo for patients [first, first+count) on n_threads threads. */
 int      orc_simulate(const orc_config *cfg, int64_t first, int64_t count, int n_threads, const orc_outputs *out);

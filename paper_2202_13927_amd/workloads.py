@@ -25,7 +25,7 @@ NOMINAL = (0.0161, 0.0097, 0.066, 0.006, 0.06, 0.03, 51.2e-4, 8.2e-4, 520e-4,
 # State order of the model (documentation for users of trajectory dumps).
 STATE_NAMES = ("D1", "D2", "S1", "S2", "I", "x1", "x2", "x3", "Q1", "Q2", "GI")
 
-CTRL_OPEN, CTRL_PID, CTRL_MPC, CTRL_MLP = 0, 1, 2, 3
+CTRL_OPEN, CTRL_PID, CTRL_MPC, CTRL_MLP, CTRL_DUAL = 0, 1, 2, 3, 4
 PROTO_SLOTS, PROTO_NORDIC = 0, 1
 FP64, FP32 = 0, 1
 
@@ -75,6 +75,39 @@ def base_trial() -> dict:
         "mlp_safe_out": 1.0,
         # the controller's basal rate relative to the patient's (Sec. IV-E trial B: 0.5)
         "basal_scale": 1.0,
+        # dual-hormone AP (CTRL_DUAL): the PID above in insulin mode plus a meal bolus
+        # (ICR = icr_rule / TDD, TDD = twice the daily basal insulin); glucagon mode below
+        # glu_enter until glu_exit, microboli min(glu_max, glu_kp (glu_target - y)) ug; a
+        # glucagon bolus of ex_bolus ug at an exercise onset while y < ex_bolus_below
+        "meal_bolus": 1,
+        "icr_rule": 1000.0,
+        "glu_enter": 3.5,
+        "glu_exit": 5.0,
+        "glu_target": 5.0,
+        "glu_kp": 5.0,
+        "glu_max": 10.0,
+        "ex_bolus": 100.0,
+        "ex_bolus_below": 7.0,
+        # (3) model extensions of Sec. IV-B, parameters shared by all patients; off by default:
+        # subcutaneous glucagon (two states, time constant tau_n min, hepatic output e_n
+        # mmol per ug appearing) and exercise (three states driven by the heart-rate reserve:
+        # time constants tau_e1..3 min, uptake alpha_e 1/min, insulin action gain beta_e)
+        "model_ext": 0,
+        "tau_n": 20.0,
+        "e_n": 0.3,
+        "tau_e1": 5.0,
+        "tau_e2": 20.0,
+        "tau_e3": 300.0,
+        "alpha_e": 0.015,
+        "beta_e": 1.0,
+        # exercise sessions on the Northern-European protocol's active days (model_ext only)
+        "exercise": 0,
+        "exercise_minute": 960,
+        "exercise_duration": 45,
+        "exercise_hrr": 0.5,
+        # test inputs (model_ext only): heart-rate reserve held at every sample; open-loop glucagon
+        "hrr_const": 0.0,
+        "un_open": 0.0,
         # (3) model + simulation settings
         "n_days": 7,
         "em_per_ctrl": 5,
@@ -123,6 +156,15 @@ def nordic_year(seed: int = 6) -> dict:
     +-30 min onset jitter."""
     return with_(base_trial(), n_patients=1_000_000, n_days=364, pop_seed=seed, noise_seed=seed, precision=FP32,
                  proto=PROTO_NORDIC, meal_cv=0.1)
+
+
+def dual_hormone_year(seed: int = 7) -> dict:
+    """The paper's own kind of trial (Sec. IV): the Northern-European year with an exercise
+    session on every active day, the model extended with subcutaneous glucagon and exercise,
+    and the dual-hormone AP (insulin mode: PID microadjustments with doubled gains and a
+    meal bolus; glucagon mode below 3.5 mmol/L; 100 ug at an exercise onset below 7 mmol/L),
+    1,000,000 patients x 364 days, FP32."""
+    return with_(nordic_year(seed), model_ext=1, exercise=1, ctrl_kind=CTRL_DUAL, kp=1.0, ki=1.0 / 600.0, kd=60.0)
 
 
 def c5_mpc(seed: int = 5) -> dict:
