@@ -379,9 +379,12 @@ def test_learned_full_size_sampled(G, orc):
     g, ref_net = _run_mlp(G, t, W.synthetic_policy_net(71))
     K = g["K"]
     assert K == 28 * 288 and len(g["fallback"]) == t["n_patients"]
+    import concurrent.futures as cf
+    idx = np.linspace(0, t["n_patients"] - 1, 64).astype(int)
+    with cf.ThreadPoolExecutor(THREADS) as ex:     # one patient per oracle call, in parallel
+        res = list(ex.map(lambda i: orc.simulate(t, first=int(i), count=1, threads=1, mlp=ref_net), idx))
     dt, fb_g, fb_o = [], 0, 0
-    for i in np.linspace(0, t["n_patients"] - 1, 12).astype(int):
-        o = orc.simulate(t, first=int(i), count=1, threads=1, mlp=ref_net)
+    for i, o in zip(idx, res):
         assert (g["fallback"][i] == K) == (o["fallback"][0] == K), i     # outside the box: the MPC throughout
         assert g["status"][i] == o["status"][0]
         fb_g += int(g["fallback"][i])
@@ -389,7 +392,8 @@ def test_learned_full_size_sampled(G, orc):
         dt.append((int(g["bins"][i, 2]) - int(o["bins"][0, 2])) / K)
     dt = np.array(dt)
     _say("   sampled |dTIR| max", np.abs(dt).max(), "mean", dt.mean(), "fallbacks gpu", fb_g, "oracle", fb_o)
-    assert np.abs(dt).max() < 5e-2 and abs(dt.mean()) < 1e-2
+    # FP32 against FP64 on the same noise: 0.5 pp per patient, 0.1 pp on the sample's mean
+    assert np.abs(dt).max() < 5e-3 and abs(dt.mean()) < 1e-3
     assert abs(fb_g - fb_o) <= 0.05 * fb_o + 50
 
 
