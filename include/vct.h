@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VCT_ABI_VERSION 3
+#define VCT_ABI_VERSION 4
 #define VCT_NP 15          /* sampled parameters per patient                         */
 #define VCT_NX 11          /* model states per patient                               */
 #define VCT_NPARAM_ROWS 19 /* rows of the population buffer: 15 parameters, u_b, I*, attempts, status */
@@ -50,8 +50,9 @@ typedef enum {
     VCT_ENOTSUP = -5   /* valid but not supported by this build              */
 } vct_status;
 
-/* Controllers (Sec. III-B): constant open-loop rate (tests), PID, linear MPC, learned MLP. */
-enum { VCT_CTRL_OPEN = 0, VCT_CTRL_PID = 1, VCT_CTRL_MPC = 2, VCT_CTRL_MLP = 3 };
+/* Controllers (Sec. III-B): constant open-loop rate (tests), PID, linear MPC, learned MLP,
+ * and the dual-hormone AP of Sec. IV-C (needs the model extensions, vct_sim.model_ext). */
+enum { VCT_CTRL_OPEN = 0, VCT_CTRL_PID = 1, VCT_CTRL_MPC = 2, VCT_CTRL_MLP = 3, VCT_CTRL_DUAL = 4 };
 /* Working precision of the patient state; accumulators are always FP64. */
 enum { VCT_FP64 = 0, VCT_FP32 = 1 };
 /* Population flags. */
@@ -111,6 +112,16 @@ typedef struct {
     int32_t jitter_min;                     /* 0..120 (VCT_PROTO_NORDIC: 0..40)    */
     int32_t kind;                           /* VCT_PROTO_SLOTS or VCT_PROTO_NORDIC */
     double  meal_cv;                        /* VCT_PROTO_NORDIC: relative SD of each meal, 0..1 */
+    /* Exercise (Sec. II-B: the active day has an exercise session), VCT_PROTO_NORDIC with the
+     * model extensions only: exercise = 1 gives each active day one session of
+     * exercise_duration minutes at heart-rate reserve fraction exercise_hrr, held over
+     * ceil(exercise_duration / ts_min) sampling intervals from the one that contains
+     * exercise_minute + a jitter on the integers [-jitter_min, jitter_min] (word 2 of Philox
+     * block (day, patient, 9, 0), simulation key). */
+    int32_t exercise;                       /* 0 or 1                              */
+    int32_t exercise_minute;                /* 0..1439                             */
+    int32_t exercise_duration;              /* minutes, 1..240                     */
+    double  exercise_hrr;                   /* in [0, 1]                           */
 } vct_protocol;
 
 /* (5) controller -- Sec. III-B (x^c_{k+1} = kappa(x^c_k, y_k, ...), u_k = lambda(...)).
@@ -154,6 +165,20 @@ typedef struct {
     double  basal_scale;   /* > 0: the controller's basal rate is basal_scale u_b (1 = correct;
                               Sec. IV-E trial B: 0.5). It replaces u_b in the PID law and bound
                               and in the open-loop rate; other values than 1 need PID or open loop */
+    /* Dual-hormone AP (VCT_CTRL_DUAL, Sec. IV-C; needs vct_sim.model_ext): glucagon mode when
+     * y_k < glu_enter, insulin mode again when y_k >= glu_exit. The PID above runs on every
+     * sample (its conditional integral included) and is delivered in insulin mode only, with
+     * (meal_bolus = 1) a bolus at each announced meal: carbs TDD / icr_rule U (carbs = the held
+     * intake d Ts 180.16/1000 g, TDD = 2 x 1440 u_b / 1000 U/day) less the insulin on board
+     * above basal (S1 + S2 - 2 u_b tmaxI, mU), never negative. Glucagon mode: no insulin; a
+     * microbolus min(glu_max, max(0, glu_kp (glu_target - y_k) - (Z1 + Z2))) ug. Either mode:
+     * ex_bolus ug at an exercise onset while y_k < ex_bolus_below. Every dose is delivered as a
+     * constant rate over its sampling interval. */
+    int32_t meal_bolus;    /* 0 or 1                                                 */
+    double  icr_rule;      /* > 0, g U/day / U (500 is the clinical rule of thumb)   */
+    double  glu_enter, glu_exit;      /* mmol/L, glu_enter <= glu_exit                */
+    double  glu_target, glu_kp, glu_max;   /* mmol/L, ug/(mmol/L) >= 0, ug >= 0        */
+    double  ex_bolus, ex_bolus_below;      /* ug >= 0, mmol/L                          */
 } vct_controller;
 
 /* (3) model + simulation settings -- Sec. III-A. Euler-Maruyama with em_per_ctrl
@@ -193,6 +218,22 @@ typedef struct {
     void    *popbg_dev;       /* optional (NULL = off): the population's BG as a function of
                                  time, Sec. III-C, vct_popbg_bytes(n_days, ts_min) bytes; see
                                  vct_popbg_bytes. Not with traj_dev or record_dev. */
+    /* Model extensions (Sec. IV-B; parameters shared by all patients). model_ext = 1 adds a
+     * subcutaneous glucagon depot dZ1 = u_N - Z1/tau_n, dZ2 = (Z1 - Z2)/tau_n (ug, u_N ug/min)
+     * whose appearance Z2/tau_n adds e_n Z2/tau_n (mmol/min) to the hepatic glucose output,
+     * EGP = EGP0 max(0, 1 - x3) + e_n Z2/tau_n, and exercise states driven by the heart-rate
+     * reserve fraction HRR: dE1 = (HRR - E1)/tau_e1, dE2 = (E1 - E2)/tau_e2, dE3 = (E1 - E3)/
+     * tau_e3, with the uptake -alpha_e E2 Q1 and x1, x2 acting as x_j (1 + beta_e E3). All
+     * five states start at 0 (the basal state). Needed by VCT_CTRL_DUAL and by exercise;
+     * supported with VCT_CTRL_OPEN, VCT_CTRL_PID and VCT_CTRL_DUAL, not with popbg_dev or
+     * the batched launch (VCT_ENOTSUP). */
+    int32_t  model_ext;       /* 0 or 1                                              */
+    double   tau_n, e_n;      /* min > 0; mmol/ug >= 0                               */
+    double   tau_e1, tau_e2, tau_e3;   /* min > 0                                    */
+    double   alpha_e, beta_e; /* 1/min >= 0; >= 0                                    */
+    double  *doses_dev;       /* optional (model_ext only, NULL = off): double [3][n], per patient
+                                 the basal insulin (mU), bolus insulin (mU) and glucagon (ug)
+                                 delivered over the horizon (PID / open loop: all basal) */
 } vct_sim;
 
 /* Population summary (Sec. III-C indicators, Sec. IV-A ranges). Quantiles are nearest

@@ -229,8 +229,46 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     if (K >= ((int64_t)1 << 31))
         return fail(VCT_EINVAL, "horizon too long");
     if (ctrl->kind != VCT_CTRL_OPEN && ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_MPC &&
-        ctrl->kind != VCT_CTRL_MLP)
+        ctrl->kind != VCT_CTRL_MLP && ctrl->kind != VCT_CTRL_DUAL)
         return fail(VCT_EINVAL, "controller kind %d", ctrl->kind);
+    // model extensions, exercise and the dual-hormone AP
+    if (sim->model_ext != 0 && sim->model_ext != 1)
+        return fail(VCT_EINVAL, "model_ext %d (0 or 1)", sim->model_ext);
+    if (sim->model_ext) {
+        if (!(finite_pos(sim->tau_n) && finite_pos(sim->tau_e1) && finite_pos(sim->tau_e2) &&
+              finite_pos(sim->tau_e3)))
+            return fail(VCT_EINVAL, "model extensions: time constants must be finite and > 0");
+        if (!(std::isfinite(sim->e_n) && sim->e_n >= 0.0 && std::isfinite(sim->alpha_e) && sim->alpha_e >= 0.0 &&
+              std::isfinite(sim->beta_e) && sim->beta_e >= 0.0))
+            return fail(VCT_EINVAL, "model extensions: e_n, alpha_e and beta_e must be finite and >= 0");
+        if (ctrl->kind == VCT_CTRL_MPC || ctrl->kind == VCT_CTRL_MLP)
+            return fail(VCT_ENOTSUP, "model extensions with the MPC or learned controller");
+        if (sim->popbg_dev)
+            return fail(VCT_ENOTSUP, "model extensions with popbg_dev");
+    }
+    if (sim->doses_dev && (!sim->model_ext || (uintptr_t)sim->doses_dev % 8 != 0))
+        return fail(VCT_EINVAL, "doses_dev needs model_ext and 8-byte alignment");
+    if (ctrl->kind == VCT_CTRL_DUAL) {
+        if (!sim->model_ext)
+            return fail(VCT_EINVAL, "the dual-hormone AP needs the model extensions (model_ext = 1)");
+        if (ctrl->meal_bolus != 0 && ctrl->meal_bolus != 1)
+            return fail(VCT_EINVAL, "meal_bolus %d (0 or 1)", ctrl->meal_bolus);
+        if (!(finite_pos(ctrl->icr_rule) && std::isfinite(ctrl->glu_enter) && std::isfinite(ctrl->glu_exit) &&
+              ctrl->glu_enter <= ctrl->glu_exit && std::isfinite(ctrl->glu_target) && std::isfinite(ctrl->glu_kp) &&
+              ctrl->glu_kp >= 0.0 && std::isfinite(ctrl->glu_max) && ctrl->glu_max >= 0.0 &&
+              std::isfinite(ctrl->ex_bolus) && ctrl->ex_bolus >= 0.0 && std::isfinite(ctrl->ex_bolus_below)))
+            return fail(VCT_EINVAL, "dual-hormone AP settings invalid (icr_rule > 0, glu_enter <= glu_exit, "
+                                    "glu_kp, glu_max, ex_bolus >= 0, all finite)");
+    }
+    if (pr->exercise != 0 && pr->exercise != 1)
+        return fail(VCT_EINVAL, "protocol: exercise %d (0 or 1)", pr->exercise);
+    if (pr->exercise) {
+        if (pr->kind != VCT_PROTO_NORDIC || !sim->model_ext)
+            return fail(VCT_EINVAL, "exercise needs the Northern-European protocol and the model extensions");
+        if (pr->exercise_minute < 0 || pr->exercise_minute > 1439 || pr->exercise_duration < 1 ||
+            pr->exercise_duration > 240 || !(pr->exercise_hrr >= 0.0 && pr->exercise_hrr <= 1.0))
+            return fail(VCT_EINVAL, "protocol: exercise minute, duration or intensity out of range");
+    }
     const bool uses_mpc = ctrl->kind == VCT_CTRL_MPC || ctrl->kind == VCT_CTRL_MLP;
     if (sim->record_dev && !uses_mpc)
         return fail(VCT_EINVAL, "record_dev needs the MPC or the learned controller");
@@ -318,6 +356,28 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.pop_hist = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K : nullptr;
     a.span_min = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K + 402 : nullptr;
     a.span_max = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K + 452 : nullptr;
+    a.ext = sim->model_ext;
+    a.tau_n = sim->tau_n;
+    a.e_n = sim->e_n;
+    a.tau_e1 = sim->tau_e1;
+    a.tau_e2 = sim->tau_e2;
+    a.tau_e3 = sim->tau_e3;
+    a.alpha_e = sim->alpha_e;
+    a.beta_e = sim->beta_e;
+    a.exercise = pr->exercise;
+    a.ex_minute = pr->exercise_minute;
+    a.ex_samples = (pr->exercise_duration + sim->ts_min - 1) / sim->ts_min;
+    a.ex_hrr = pr->exercise_hrr;
+    a.meal_bolus = ctrl->meal_bolus;
+    a.icr_rule = ctrl->icr_rule;
+    a.glu_enter = ctrl->glu_enter;
+    a.glu_exit = ctrl->glu_exit;
+    a.glu_target = ctrl->glu_target;
+    a.glu_kp = ctrl->glu_kp;
+    a.glu_max = ctrl->glu_max;
+    a.ex_bolus = ctrl->ex_bolus;
+    a.ex_bolus_below = ctrl->ex_bolus_below;
+    a.doses = (double *)sim->doses_dev;
     return VCT_OK;
 }
 
@@ -722,6 +782,8 @@ vct_status vct_batch_create(const vct_arm *arms, int32_t n_arms, const vct_proto
         return fail(VCT_EINVAL, "vct_batch_create: null argument");
     if (ctrl->kind != VCT_CTRL_PID && ctrl->kind != VCT_CTRL_OPEN)
         return fail(VCT_ENOTSUP, "vct_batch_create: batched arms run the PID or open-loop controller");
+    if (sim->model_ext || sim->doses_dev)
+        return fail(VCT_ENOTSUP, "vct_batch_create: batched arms run the core model");
     if (sim->record_dev || sim->fallback_dev || sim->popbg_dev)
         return fail(VCT_EINVAL, "vct_batch_create: record_dev / fallback_dev / popbg_dev are per-population outputs");
     std::vector<vct::SimArgs> hargs(n_arms);

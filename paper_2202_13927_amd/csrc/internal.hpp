@@ -64,6 +64,16 @@ struct SimArgs {
     uint64_t *pop_hist;   // [402] pooled BG bins of 0.1 mmol/L
     uint64_t *span_min, *span_max;   // [50] min / max over patients of the cumulative 0.5 mmol/L bins
     int64_t K;
+    // model extensions (Sec. IV-B): subcutaneous glucagon and exercise states
+    int32_t ext;          // 1: the extended model
+    double tau_n, e_n, tau_e1, tau_e2, tau_e3, alpha_e, beta_e;
+    // exercise sessions on the Northern-European protocol's active days (Sec. II-B)
+    int32_t exercise, ex_minute, ex_samples;
+    double ex_hrr;
+    // dual-hormone AP (Sec. IV-C)
+    int32_t meal_bolus;
+    double icr_rule, glu_enter, glu_exit, glu_target, glu_kp, glu_max, ex_bolus, ex_bolus_below;
+    double *doses;        // [3][n] basal insulin (mU), bolus insulin (mU), glucagon (ug), or null
 };
 
 // One work item of a batched launch: a tile of consecutive patients of one arm.

@@ -90,7 +90,14 @@ hipError_t launch_population(const PopArgs &a, hipStream_t s)
 }
 
 // ---------------------------------------------------------------- simulation ----
-enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2, kCtrlMlp = 3 };
+// Controller codes of the kernels: those of vct.h (open loop, PID, MPC, learned, dual-hormone),
+// and the PID and open loop on the extended model (glucagon and exercise states).
+enum { kCtrlOpen = 0, kCtrlPid = 1, kCtrlMpc = 2, kCtrlMlp = 3, kCtrlDual = 4, kCtrlPidExt = 5, kCtrlOpenExt = 6 };
+template <int CTRL> constexpr bool ctrl_ext() { return CTRL >= kCtrlDual; }
+template <int CTRL> constexpr int ctrl_base()
+{
+    return CTRL == kCtrlPidExt ? kCtrlPid : (CTRL == kCtrlOpenExt ? kCtrlOpen : CTRL);
+}
 enum { kOutTraj = 1, kOutRecord = 2, kOutPop = 4 };   // optional per-sample outputs (template bits)
 
 // Population BG as a function of time (Sec. III-C: mean, minimum and maximum BG over the
@@ -449,6 +456,23 @@ __device__ __forceinline__ DayMeals<R> draw_meals(const SimArgs &a, uint32_t pid
     return d;
 }
 
+// Sec. II-B: each active day of the Northern-European protocol has one exercise session, from
+// the sampling interval that contains ex_minute + a jitter (word 2 of Philox block (day,
+// patient, EXER, 0), as for a meal) for ex_samples intervals. Returns the onset's sample
+// index within the day, or -1 (other days, or no sessions).
+enum : uint32_t { kTagExer = 9u };
+__device__ __forceinline__ int32_t exercise_onset(const SimArgs &a, uint32_t pid, int32_t day)
+{
+    if (!a.exercise)
+        return -1;
+    int season, wtype, dtype;
+    nordic_day(a, pid, day, season, wtype, dtype);
+    if (dtype != 1)
+        return -1;
+    const U4 r = philox4x32_10((uint32_t)day, pid, kTagExer, 0u, a.key0, a.key1);
+    return (a.ex_minute + meal_jitter(r.z, a.jitter)) / a.ts_min;
+}
+
 template <typename R>
 __device__ __forceinline__ bool all_finite(const State<R> &s)
 {
@@ -475,6 +499,18 @@ template <typename R> struct CtrlConst {
     R k_sig;          // Box-Muller constant giving normals scaled by sqrt(h) sigma
     R sig_sqh, sqrt_r;
     double ts_d;
+};
+
+// Loop-carried state of the extended model (glucagon depot, exercise) and of the
+// dual-hormone AP, per lane.
+template <typename R> struct ExtLane {
+    ExtState<R> x;
+    ExtConst<R> c;
+    int32_t ex_k;            // this day's exercise onset (sample within the day), -1 if none
+    int32_t glu;             // dual-hormone AP: 1 in glucagon mode
+    R bolus_per_rate;        // meal bolus (mU) per unit of announced intake (mmol/min)
+    R iob_s1, iob_s2, iob0;  // insulin on board above basal = S1s iob_s1 + S2s iob_s2 - iob0 (mU)
+    double basal, bolus, glucagon;   // delivered over the horizon: mU, mU, ug
 };
 
 // Inputs of the learned controller (and of the recorded behaviour-cloning rows), per lane:
@@ -749,12 +785,14 @@ __device__ __attribute__((noinline)) R coop_qp(const SimArgs &a, const R *__rest
 // (sqrt(h) sigma xi), z[5] the sensor noise (sqrt(R) v). `live` is false for the padding
 // lanes of the learned controller's last wave, which compute but write nothing.
 template <typename R, int CTRL, int OUT>
-__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool live, int32_t k, R dr,
+__device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool live, int32_t k, int32_t kd, R dr,
                                             const R *z, State<R> &s, const StepConst<R> &c,
                                             const CtrlConst<R> &cc, Lane<R> &L, MpcState<R> &ms,
                                             MpcPlan<R> &mplan, const LinStep<R> &lin,
-                                            PolicyLane<R, CTRL == kCtrlMlp> &pl, const PolicyShared &ps)
+                                            PolicyLane<R, CTRL == kCtrlMlp> &pl, const PolicyShared &ps,
+                                            ExtLane<R> &xl)
 {
+    constexpr int kBase = ctrl_base<CTRL>();
     // indicators (Sec. IV-A ranges) on G(t_k)
     const R G = s.Q1 * c.inv_vg;
     if (OUT & kOutPop) {
@@ -799,7 +837,8 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
     }
 
     R u, label = R(0);
-    if constexpr (CTRL == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
+    R u_bol = R(0), un = R(0);   // dual-hormone AP: bolus insulin (mU/min), glucagon (ug/min)
+    if constexpr (kBase == kCtrlPid) {   // control state (integral, previous y), Sec. III-B form
         // u = u_b + kp e_k + ki sum_{i<k} ts e_i + kd (y_k - y_k-1)/ts with e = y - sp,
         // clamped to [0, umax]; the integral grows only while u is not clamped. Regrouped
         // as pid_b + (kp + kd/ts) y_k - (kd/ts) y_k-1 with pid_b = u_b - kp sp + ki sum ts e_i.
@@ -810,10 +849,10 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         if (u == u_unc)   // not clamped (a NaN u_unc is clamped to 0 and never integrates)
             L.pid_b = fmaf_t(cc.kits, y, L.pid_b - cc.kits_sp);
         L.y_prev = y;
-    } else if constexpr (CTRL == kCtrlMpc) {   // control state (Kalman estimate, input plan)
+    } else if constexpr (kBase == kCtrlMpc) {   // control state (Kalman estimate, input plan)
         u = mpc_step<R>((const R *)a.mpc, a.n, j, ms, mplan, c, lin, R(a.h), R(a.h * a.ag), a.em_per_ctrl, y, dr,
                         R(a.g_target - a.setpoint), a.mpc_iters);
-    } else if constexpr (CTRL == kCtrlMlp) {
+    } else if constexpr (kBase == kCtrlMlp) {
         // control state (CGM history, Kalman estimate, input plan): the network acts unless
         // an input leaves the box it was trained on, or the sensor reads low (y < mlp_safe_g)
         // while the network asks for more than mlp_safe_out u_b; then the MPC solves its QP.
@@ -857,8 +896,42 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
         }
         label = cc.ub + du_mpc;
         mpc_predict<R>(ms, c, lin_from<R>(pl.co), du, dr, R(a.h), R(a.h * a.ag), a.em_per_ctrl);
+    } else if constexpr (kBase == kCtrlDual) {
+        // dual-hormone AP (Sec. IV-C): glucagon mode below glu_enter until y >= glu_exit (a
+        // non-finite reading changes nothing). The PID runs on every sample, as above, and is
+        // delivered in insulin mode only, with the meal bolus less the insulin on board;
+        // glucagon mode gives microboli less the glucagon on board; an exercise onset below
+        // ex_bolus_below adds the exercise bolus in either mode.
+        xl.glu = xl.glu ? !(y >= R(a.glu_exit)) : (y < R(a.glu_enter));
+        if (k == 0)
+            L.y_prev = y;
+        const R u_unc = fmaf_t(cc.kpd, y, fmaf_t(-cc.kd_ts, L.y_prev, L.pid_b));
+        const R u_pid = vclamp(u_unc, R(0), cc.umax);
+        if (u_pid == u_unc)
+            L.pid_b = fmaf_t(cc.kits, y, L.pid_b - cc.kits_sp);
+        L.y_prev = y;
+        R n_ug = R(0);
+        if (xl.glu) {
+            u = R(0);
+            n_ug = vmin(R(a.glu_max), vmax(R(0), fmaf_t(R(a.glu_kp), R(a.glu_target) - y, -(xl.x.z1 + xl.x.z2))));
+        } else {
+            u = u_pid;
+            if (a.meal_bolus && dr > R(0)) {
+                const R iob = fmaf_t(s.S1s, xl.iob_s1, fmaf_t(s.S2s, xl.iob_s2, -xl.iob0));
+                u_bol = vmax(R(0), fmaf_t(dr, xl.bolus_per_rate, -iob)) / R(a.ts_min);
+            }
+        }
+        if (kd == xl.ex_k && y < R(a.ex_bolus_below))
+            n_ug += R(a.ex_bolus);
+        un = n_ug / R(a.ts_min);
     } else {
         u = cc.u_open;
+    }
+    if constexpr (ctrl_ext<CTRL>()) {   // delivered doses: basal and bolus insulin, glucagon
+        xl.basal += (double)u * cc.ts_d;
+        xl.bolus += (double)u_bol * cc.ts_d;
+        xl.glucagon += (double)un * cc.ts_d;
+        u = u + u_bol;
     }
     if (kFeat) {
 #pragma unroll
@@ -880,9 +953,18 @@ __device__ __forceinline__ void sample_step(const SimArgs &a, int64_t j, bool li
     }
 
     const R du = c.u_in * u, dd = c.d_in * dr;
+    if constexpr (ctrl_ext<CTRL>()) {   // the extended model: glucagon into the depot, exercise input
+        const bool session = xl.ex_k >= 0 && kd >= xl.ex_k && kd < xl.ex_k + a.ex_samples;
+        const R dh = session ? xl.c.b_e1 * R(a.ex_hrr) : R(0);
+        const R dn = R(a.h) * un;
 #pragma unroll
-    for (int q = 0; q < 5; ++q)
-        em_step<R>(s, c, du, dd, z[q]);
+        for (int q = 0; q < 5; ++q)
+            em_step_ext<R>(s, xl.x, c, xl.c, du, dd, z[q], dn, dh);
+    } else {
+#pragma unroll
+        for (int q = 0; q < 5; ++q)
+            em_step<R>(s, c, du, dd, z[q]);
+    }
     L.sum_u += (double)u * cc.ts_d;
 }
 
@@ -1005,8 +1087,30 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
     cc.ts_d = (double)a.ts_min;
     const R bw = R(p[kBW]);   // body weight: the Northern-European protocol's meal sizes are per kg
 
+    ExtLane<R> xl{};
+    if constexpr (ctrl_ext<CTRL>()) {
+        ext_constants<R>(a.h, a.tau_n, a.e_n, a.tau_e1, a.tau_e2, a.tau_e3, a.alpha_e, a.beta_e, xl.c);
+        xl.x = ExtState<R>{R(0), R(0), R(0), R(0), R(0)};   // no glucagon, no exercise: the basal state
+        xl.glu = 0;
+        xl.ex_k = -1;
+        // insulin on board above basal from the scaled depot states (S1 = S1s/(c_ui b_i),
+        // S2 = S2s/c_ui, basal S1 = S2 = u_b tmaxI); the bolus per announced intake from
+        // the ICR rule (carbs = intake Ts 180.16/1000 g, ICR = icr_rule / TDD g/U,
+        // TDD = 2 x 1440 u_b / 1000 U)
+        const double ti = p[kTmaxI], vi = p[kVI] * p[kBW];
+        const double c_ui = a.h / (ti * vi), b_i = a.h / ti;
+        xl.iob_s1 = R(1.0 / (c_ui * b_i));
+        xl.iob_s2 = R(1.0 / c_ui);
+        xl.iob0 = R(2.0 * ub_d * ti);
+        const double tdd = 2.0 * ub_d * 1440.0 / 1000.0;
+        xl.bolus_per_rate = R((double)a.ts_min * 180.16 / 1000.0 * tdd / a.icr_rule * 1000.0);
+        xl.basal = xl.bolus = xl.glucagon = 0.0;
+    }
+
     for (int32_t day = 0; day < a.n_days; ++day) {
         DayMeals<R> ml = draw_meals<R>(a, pid, day, bw);
+        if constexpr (ctrl_ext<CTRL>())
+            xl.ex_k = exercise_onset(a, pid, day);
         for (int32_t kk = 0; kk < a.kday; kk += 2) {
             const int32_t k = day * a.kday + kk;
             // normals of the sample pair (k, k+1): blocks (k/2, patient, DIFF, 0..2), normals
@@ -1044,11 +1148,17 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
                 if (ml.k0 == kk + 1)
                     dr1 = pop_front(ml);
             }
-            sample_step<R, CTRL, OUT>(a, j, live, k, dr0, z, s, c, cc, L, ms, mplan, lin, pl, ps);
-            sample_step<R, CTRL, OUT>(a, j, live, k + 1, dr1, z + 6, s, c, cc, L, ms, mplan, lin, pl, ps);
+            sample_step<R, CTRL, OUT>(a, j, live, k, kk, dr0, z, s, c, cc, L, ms, mplan, lin, pl, ps, xl);
+            sample_step<R, CTRL, OUT>(a, j, live, k + 1, kk + 1, dr1, z + 6, s, c, cc, L, ms, mplan, lin, pl, ps,
+                                      xl);
         }
         if (!all_finite(s))
             L.status |= kStNonFinite;
+        if constexpr (ctrl_ext<CTRL>()) {
+            if (!(isfinite(xl.x.z1) && isfinite(xl.x.z2) && isfinite(xl.x.ex1) && isfinite(xl.x.ex2) &&
+                  isfinite(xl.x.ex3)))
+                L.status |= kStNonFinite;
+        }
     }
     if (OUT & kOutPop)
         span_flush(a, ps.span, ps.lane, live);
@@ -1057,6 +1167,13 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
         return;
     if (CTRL == kCtrlMlp && a.fallback)
         a.fallback[j] = pl.fallbacks;
+    if constexpr (ctrl_ext<CTRL>()) {
+        if (a.doses) {
+            a.doses[0 * a.out_stride + j] = xl.basal;
+            a.doses[1 * a.out_stride + j] = xl.bolus;
+            a.doses[2 * a.out_stride + j] = xl.glucagon;
+        }
+    }
     const int64_t st = a.out_stride;
     const int32_t K = (int32_t)a.K;
     a.sum_g[j] = L.sum_g;
@@ -1478,9 +1595,28 @@ static hipError_t launch_sim_t(const SimArgs &a, bool noisy, hipStream_t s)
     return hipGetLastError();
 }
 
+// The extended model (glucagon and exercise states): the noise is always drawn (zero noise
+// scales give the noise-free run exactly); trajectories optional.
+template <typename R, int CTRL>
+static hipError_t launch_sim_ext(const SimArgs &a, hipStream_t s)
+{
+    if (a.traj != nullptr && a.n_traj > 0)
+        launch_sim_o<R, CTRL, true, kOutTraj>(a, s);
+    else
+        launch_sim_o<R, CTRL, true, 0>(a, s);
+    return hipGetLastError();
+}
+
 template <typename R>
 static hipError_t launch_sim_r(const SimArgs &a, bool noisy, hipStream_t s)
 {
+    if (a.ext) {
+        switch (a.ctrl) {
+        case kCtrlDual: return launch_sim_ext<R, kCtrlDual>(a, s);
+        case kCtrlPid: return launch_sim_ext<R, kCtrlPidExt>(a, s);
+        default: return launch_sim_ext<R, kCtrlOpenExt>(a, s);
+        }
+    }
     switch (a.ctrl) {
     case kCtrlPid: return launch_sim_t<R, kCtrlPid>(a, noisy, s);
     case kCtrlMpc: return launch_sim_t<R, kCtrlMpc>(a, noisy, s);

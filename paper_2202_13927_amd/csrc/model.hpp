@@ -167,4 +167,80 @@ __device__ __forceinline__ void em_step(State<R> &s, const StepConst<R> &c, R du
     s.x1h = x1n; s.x2s = x2n; s.e3 = e3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
 }
 
+// ------------------------------------------------------ model extensions ----
+// Sec. IV-B extends the model with a two-state subcutaneous glucagon depot and a three-state
+// effect of exercise (parameters shared by all patients):
+//   dZ1 = u_N - Z1/tau_n,  dZ2 = (Z1 - Z2)/tau_n           (ug; appearance Z2/tau_n ug/min)
+//   EGP = EGP0 max(0, 1 - x3) + e_n Z2/tau_n
+//   dE1 = (HRR - E1)/tau_e1, dE2 = (E1 - E2)/tau_e2, dE3 = (E1 - E3)/tau_e3
+//   Q1 loses alpha_e E2 Q1 (insulin-independent uptake); x1 and x2 act as x_j (1 + beta_e E3).
+// The extension states are carried unscaled; each update is one FMA in decay form.
+template <typename R> struct ExtState {
+    R z1, z2;          // glucagon depot, ug
+    R ex1, ex2, ex3;    // exercise: heart rate, uptake, insulin action
+};
+
+template <typename R> struct ExtConst {
+    R a_n, b_n;          // 1 - h/tau_n, h/tau_n
+    R c_n;               // h e_n / tau_n: Q1 increment per ug in Z2
+    R a_e1, b_e1;        // 1 - h/tau_e1, h/tau_e1 (b_e1 multiplies HRR)
+    R a_e2, b_e2, a_e3, b_e3;
+    R h_alpha;           // h alpha_e
+    R beta;              // beta_e
+};
+
+template <typename R>
+__device__ __forceinline__ void ext_constants(double h, double tau_n, double e_n, double tau_e1, double tau_e2,
+                                              double tau_e3, double alpha_e, double beta_e, ExtConst<R> &e)
+{
+    e.a_n = R(1.0 - h / tau_n);
+    e.b_n = R(h / tau_n);
+    e.c_n = R(h * e_n / tau_n);
+    e.a_e1 = R(1.0 - h / tau_e1);
+    e.b_e1 = R(h / tau_e1);
+    e.a_e2 = R(1.0 - h / tau_e2);
+    e.b_e2 = R(h / tau_e2);
+    e.a_e3 = R(1.0 - h / tau_e3);
+    e.b_e3 = R(h / tau_e3);
+    e.h_alpha = R(h * alpha_e);
+    e.beta = R(beta_e);
+}
+
+// One EM step of the extended model: em_step's update with the glucagon output, the exercise
+// uptake and the raised insulin action in the Q1/Q2 balance, then the extension states.
+// dn = h u_N (ug into Z1), dh = (h/tau_e1) HRR.
+template <typename R>
+__device__ __forceinline__ void em_step_ext(State<R> &s, ExtState<R> &x, const StepConst<R> &c, const ExtConst<R> &e,
+                                            R du, R dd, R dq, R dn, R dh)
+{
+    const R gain = fmaf_t(e.beta, x.ex3, R(1));
+    const R x1g = s.x1h * gain;                                     // h x1 (1 + beta E3)
+    const R t = x1g * s.Q1;
+    R side = fmaf_t(c.hk12, s.Q2, dq);
+    side = fmaf_t(s.D2, c.b_g, side);
+    side = side + vmax(R(0), s.e3);
+    side = fmaf_t(e.c_n, x.z2, side);                               //   + h e_n U_N
+    const R hf01c = vmin(c.f01h, s.Q1 * c.f01h_q);
+    const R hfr = vmax(R(0), fmaf_t(s.Q1, c.fr1, -c.fr0));
+    const R Q1n = ((fmaf_t(-fmaf_t(e.h_alpha, x.ex2, x1g), s.Q1, s.Q1) - hf01c) - hfr) + side;
+    const R Q2n = fmaf_t(s.Q2, fmaf_t(-c.hb2, s.x2s * gain, c.a_12), t);
+    const R GIn = fmaf_t(s.GIs, c.a_c, s.Q1);
+    const R D2n = fmaf_t(s.D2, c.a_g, s.D1s);
+    const R D1n = fmaf_t(s.D1s, c.a_g, dd);
+    const R S2n = fmaf_t(s.S2s, c.a_i, s.S1s);
+    const R S1n = fmaf_t(s.S1s, c.a_i, du);
+    const R In = fmaf_t(s.I, c.a_e, s.S2s);
+    const R x1n = fmaf_t(s.x1h, c.a1, s.I * c.hb1);
+    const R x2n = fmaf_t(s.x2s, c.a2, s.I);
+    const R e3n = fmaf_t(s.e3, c.a3, fmaf_t(-c.b3e, s.I, c.c3));
+    const R z1n = fmaf_t(x.z1, e.a_n, dn);
+    const R z2n = fmaf_t(x.z2, e.a_n, x.z1 * e.b_n);
+    const R f1n = fmaf_t(x.ex1, e.a_e1, dh);
+    const R f2n = fmaf_t(x.ex2, e.a_e2, x.ex1 * e.b_e2);
+    const R f3n = fmaf_t(x.ex3, e.a_e3, x.ex1 * e.b_e3);
+    s.D1s = D1n; s.D2 = D2n; s.S1s = S1n; s.S2s = S2n; s.I = In;
+    s.x1h = x1n; s.x2s = x2n; s.e3 = e3n; s.Q1 = Q1n; s.Q2 = Q2n; s.GIs = GIn;
+    x.z1 = z1n; x.z2 = z2n; x.ex1 = f1n; x.ex2 = f2n; x.ex3 = f3n;
+}
+
 }  // namespace vct

@@ -28,6 +28,9 @@ class TrialBuffers:
         if popbg:
             self.popbg = torch.empty(vct.vct_popbg_bytes(int(trial["n_days"]), int(trial["ts_min"])) // 8,
                                      dtype=torch.int64, device=device)
+        self.doses = None      # optional double [3][n]: basal, bolus insulin (mU), glucagon (ug)
+        if int(trial.get("model_ext", 0)):
+            self.doses = torch.empty(3 * n, dtype=torch.float64, device=device)
         self.record = None     # optional float [K][n][13] (MPC / learned controller)
         self.fallback = None   # optional int32 [n] (learned controller)
         if int(trial["ctrl_kind"]) == vct.VCT_CTRL_MLP:
@@ -45,7 +48,7 @@ def mpc_setup(trial: dict, pop, bufs: TrialBuffers, stream=None) -> None:
 
 def simulate(trial: dict, pop, bufs: TrialBuffers, stream=None, mlp_blob=None) -> None:
     sim = vct.sim_settings(trial, bufs.metrics, bufs.traj_patients, bufs.traj, bufs.record, bufs.fallback,
-                           getattr(bufs, "popbg", None))
+                           getattr(bufs, "popbg", None), getattr(bufs, "doses", None))
     vct.vct_simulate(pop, vct.protocol(trial), vct.controller(trial, bufs.mpc, mlp_blob), sim, stream)
 
 
@@ -98,6 +101,8 @@ def to_host(bufs: TrialBuffers) -> dict:
         out["record"] = bufs.record.view(bufs.K, bufs.n, 13).cpu().numpy()
     if bufs.fallback is not None:
         out["fallback"] = bufs.fallback.cpu().numpy()
+    if getattr(bufs, "doses", None) is not None:
+        out["doses"] = bufs.doses.view(3, bufs.n).cpu().numpy().T.copy()
     if getattr(bufs, "popbg", None) is not None:
         out.update(vct.popbg_decode(bufs.popbg, bufs.n, bufs.K))
     return out

@@ -16,7 +16,7 @@ LIB_PATH = os.path.join(HERE, "libvct.so")
 
 VCT_NP, VCT_NX, VCT_NPARAM_ROWS, VCT_MAX_SLOTS = 15, 11, 19, 4
 VCT_OK, VCT_EINVAL, VCT_ENOMEM, VCT_EHIP, VCT_ESTATE, VCT_ENOTSUP = 0, -1, -2, -3, -4, -5
-VCT_CTRL_OPEN, VCT_CTRL_PID, VCT_CTRL_MPC, VCT_CTRL_MLP = 0, 1, 2, 3
+VCT_CTRL_OPEN, VCT_CTRL_PID, VCT_CTRL_MPC, VCT_CTRL_MLP, VCT_CTRL_DUAL = 0, 1, 2, 3, 4
 VCT_PROTO_SLOTS, VCT_PROTO_NORDIC = 0, 1
 VCT_FP64, VCT_FP32 = 0, 1
 VCT_POP_MIN_BASAL = 1
@@ -45,7 +45,8 @@ class vct_protocol(C.Structure):
     _fields_ = [("n_slots", C.c_int32), ("minute_of_day", C.c_int32 * VCT_MAX_SLOTS),
                 ("carbs_mean_g", C.c_double * VCT_MAX_SLOTS), ("carbs_sd_g", C.c_double * VCT_MAX_SLOTS),
                 ("prob", C.c_double * VCT_MAX_SLOTS), ("jitter_min", C.c_int32), ("kind", C.c_int32),
-                ("meal_cv", C.c_double)]
+                ("meal_cv", C.c_double), ("exercise", C.c_int32), ("exercise_minute", C.c_int32),
+                ("exercise_duration", C.c_int32), ("exercise_hrr", C.c_double)]
 
 
 class vct_controller(C.Structure):
@@ -53,14 +54,20 @@ class vct_controller(C.Structure):
                 ("kd", C.c_double), ("umax_rel", C.c_double), ("u_rel", C.c_double), ("mpc_horizon", C.c_int32),
                 ("mpc_iters", C.c_int32), ("mpc_rho", C.c_double), ("mpc_dev", C.c_void_p),
                 ("mlp_dev", C.c_void_p), ("mlp_safe_g", C.c_double), ("mlp_safe_out", C.c_double),
-                ("basal_scale", C.c_double)]
+                ("basal_scale", C.c_double), ("meal_bolus", C.c_int32), ("icr_rule", C.c_double),
+                ("glu_enter", C.c_double), ("glu_exit", C.c_double), ("glu_target", C.c_double),
+                ("glu_kp", C.c_double), ("glu_max", C.c_double), ("ex_bolus", C.c_double),
+                ("ex_bolus_below", C.c_double)]
 
 
 class vct_sim(C.Structure):
     _fields_ = [("n_days", C.c_int32), ("em_per_ctrl", C.c_int32), ("ts_min", C.c_int32), ("precision", C.c_int32),
                 ("sigma_q1", C.c_double), ("cgm_var", C.c_double), ("noise_seed", C.c_uint64),
                 ("metrics_dev", C.c_void_p), ("traj_patients", C.c_int32), ("traj_dev", C.c_void_p),
-                ("record_dev", C.c_void_p), ("fallback_dev", C.c_void_p), ("popbg_dev", C.c_void_p)]
+                ("record_dev", C.c_void_p), ("fallback_dev", C.c_void_p), ("popbg_dev", C.c_void_p),
+                ("model_ext", C.c_int32), ("tau_n", C.c_double), ("e_n", C.c_double), ("tau_e1", C.c_double),
+                ("tau_e2", C.c_double), ("tau_e3", C.c_double), ("alpha_e", C.c_double), ("beta_e", C.c_double),
+                ("doses_dev", C.c_void_p)]
 
 
 class vct_summary(C.Structure):
@@ -354,6 +361,10 @@ def protocol(trial: dict) -> vct_protocol:
     p.jitter_min = int(trial["jitter"])
     p.kind = int(trial.get("proto", VCT_PROTO_SLOTS))
     p.meal_cv = float(trial.get("meal_cv", 0.0))
+    p.exercise = int(trial.get("exercise", 0))
+    p.exercise_minute = int(trial.get("exercise_minute", 960))
+    p.exercise_duration = int(trial.get("exercise_duration", 45))
+    p.exercise_hrr = float(trial.get("exercise_hrr", 0.5))
     return p
 
 
@@ -368,11 +379,15 @@ def controller(trial: dict, mpc_dev=None, mlp_dev=None) -> vct_controller:
     c.mlp_safe_g = float(trial.get("mlp_safe_g", 3.0))
     c.mlp_safe_out = float(trial.get("mlp_safe_out", 1.0))
     c.basal_scale = float(trial.get("basal_scale", 1.0))
+    c.meal_bolus = int(trial.get("meal_bolus", 1))
+    for k, v in (("icr_rule", 1000.0), ("glu_enter", 3.5), ("glu_exit", 5.0), ("glu_target", 5.0), ("glu_kp", 5.0),
+                 ("glu_max", 10.0), ("ex_bolus", 100.0), ("ex_bolus_below", 7.0)):
+        setattr(c, k, float(trial.get(k, v)))
     return c
 
 
 def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None, record_dev=None,
-                 fallback_dev=None, popbg_dev=None) -> vct_sim:
+                 fallback_dev=None, popbg_dev=None, doses_dev=None) -> vct_sim:
     s = vct_sim()
     s.n_days, s.em_per_ctrl, s.ts_min = int(trial["n_days"]), int(trial["em_per_ctrl"]), int(trial["ts_min"])
     s.precision = int(trial["precision"])
@@ -384,6 +399,11 @@ def sim_settings(trial: dict, metrics_dev, traj_patients: int = 0, traj_dev=None
     s.record_dev = _ptr(record_dev)
     s.fallback_dev = _ptr(fallback_dev)
     s.popbg_dev = _ptr(popbg_dev)
+    s.model_ext = int(trial.get("model_ext", 0))
+    for k, v in (("tau_n", 20.0), ("e_n", 0.3), ("tau_e1", 5.0), ("tau_e2", 20.0), ("tau_e3", 300.0),
+                 ("alpha_e", 0.015), ("beta_e", 1.0)):
+        setattr(s, k, float(trial.get(k, v)))
+    s.doses_dev = _ptr(doses_dev)
     return s
 
 
