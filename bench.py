@@ -18,6 +18,9 @@ The JSON line also carries
 * scenarios -- the paper's comparison of trial A (correct basal rate) and trial B (basal
   rate underestimated by 50 %) on that protocol, the same 1,000,000 patients each, as two
   arms of one batched launch: TIR and the distribution of the daily insulin per arm;
+* dual_hormone -- that year with an exercise session on each active day, the model extended
+  with glucagon and exercise, and the dual-hormone AP (1,000,000 x 364 days, one launch):
+  TIR and the distributions of daily basal insulin, bolus insulin and glucagon;
 * learned -- the learned controller against exact linear MPC on common random numbers,
   1,000,000 patients x 364 days: TIR of both arms, their simulation times and speedup, and
   a roofline for each arm (the MPC arm on the FP32 ALUs, the learned arm's network on BF16
@@ -230,6 +233,44 @@ def scenarios_leg(stream) -> dict:
         bt.close()
 
 
+def dual_hormone_leg(stream) -> dict:
+    """The paper's own kind of trial (Sec. IV): the Northern-European year with an exercise
+    session on each active day, the model with glucagon and exercise, and the dual-hormone AP,
+    1,000,000 patients x 364 days, one launch timed with HIP events on its stream: TIR and the
+    distributions of the daily basal insulin, bolus insulin and glucagon (Fig. 6's quantities)."""
+    import torch
+    from paper_2202_13927_amd import trial as T, vct, workloads as W
+    t = W.dual_hormone_year()
+    bufs = T.TrialBuffers(t)
+    pop = T.create_population(t, bufs, stream)
+    try:
+        T.simulate(t, pop, bufs, stream)
+        stream.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        T.simulate(t, pop, bufs, stream)
+        e1.record(stream)
+        s = T.read_metrics(bufs, stream)
+        ms = e0.elapsed_time(e1)
+    finally:
+        vct.vct_destroy_population(pop)
+    days = t["n_days"]
+    doses = bufs.doses.view(3, bufs.n)
+    qs = torch.tensor([0.05, 0.25, 0.5, 0.75, 0.95], dtype=torch.float64, device=doses.device)
+    pd = t["n_patients"] * days
+    log(f"[bench] dual-hormone: {ms:.1f} ms, mean TIR {s['mean_tir']:.4f}")
+    return {"workload": "Northern-European year with exercise on active days, Hovorka model with glucagon and "
+                        "exercise extensions, dual-hormone AP, 1000000 patients x 364 days, FP32",
+            "patient_days": pd, "ms": ms, "patient_days_per_s": pd / ms * 1e3,
+            "mean_tir": s["mean_tir"], "tir_quantiles": s["q_frac"], "mean_bg_mmol": s["mean_bg"],
+            "bins": s["bins"], "worst_min_g": s["worst_min_g"], "status_count": s["status_count"],
+            "daily_basal_insulin_u_quantiles": torch.quantile(doses[0] / (1000.0 * days), qs).tolist(),
+            "daily_bolus_insulin_u_quantiles": torch.quantile(doses[1] / (1000.0 * days), qs).tolist(),
+            "daily_glucagon_ug_quantiles": torch.quantile(doses[2] / days, qs).tolist(),
+            "mean_daily_glucagon_ug": float(doses[2].mean().item()) / days}
+
+
 def learned_leg(days: int, arms=("mpc", "mlp")) -> dict:
     """The learned controller against exact MPC on common random numbers: train on the MPC's
     recorded closed loop (17,500 patients x 2 days, 10.08 M pairs), then simulate the
@@ -303,7 +344,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-arm batched trial")
     ap.add_argument("--no-nordic", action="store_true",
-                    help="skip the Northern-European protocol run and the trial A vs B scenarios")
+                    help="skip the Northern-European protocol runs (PID, trial A vs B, dual-hormone AP)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one plain device copy of this size first (scales HBM byte counters)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-controller comparison")
@@ -418,6 +459,7 @@ def main() -> int:
     if not args.no_nordic:
         out["nordic"] = nordic_leg(stream)
         out["scenarios"] = scenarios_leg(stream)
+        out["dual_hormone"] = dual_hormone_leg(stream)
     if not args.no_learned:
         out["learned"] = learned_leg(args.learned_days, tuple(args.learned_arms.split(",")))
     if not args.no_cpu_baseline:

@@ -376,6 +376,15 @@ vct_status  vct_mlp_normalize(const float *rows_dev, int64_t n_rows, double box_
 vct_status  vct_mlp_train_step(const float *rows_dev, int64_t n_rows, const int32_t *idx_dev, uint64_t seed,
                                int32_t step, int32_t batch, double lr, int32_t apply, void *train_dev,
                                void *blob_dev, void *stream);
+/* n_steps Adam steps of vct_mlp_train_step (rows drawn by Philox, apply on) with steps
+ * first_step .. first_step + n_steps - 1 and a cosine decay of the learning rate from lr to
+ * lr_min: step i of the call uses lr_min + (lr - lr_min) (1 + cos(pi (sched_offset + i) /
+ * sched_total)) / 2. The loss slot then holds the last step's minibatch loss. Queued on the
+ * stream without host synchronisation; equal, bit for bit, to the same sequence of
+ * vct_mlp_train_step calls. */
+vct_status  vct_mlp_train(const float *rows_dev, int64_t n_rows, uint64_t seed, int32_t first_step, int32_t n_steps,
+                          int32_t sched_offset, int32_t sched_total, int32_t batch, double lr, double lr_min,
+                          void *train_dev, void *blob_dev, void *stream);
 /* Network output for n input rows x_dev [n][12] (raw inputs) -> out_dev [n]. */
 vct_status  vct_mlp_forward(const float *x_dev, int64_t n, const void *blob_dev, float *out_dev, void *stream);
 

@@ -567,6 +567,27 @@ vct_status vct_mlp_train_step(const float *rows_dev, int64_t n_rows, const int32
     return VCT_OK;
 }
 
+vct_status vct_mlp_train(const float *rows_dev, int64_t n_rows, uint64_t seed, int32_t first_step, int32_t n_steps,
+                         int32_t sched_offset, int32_t sched_total, int32_t batch, double lr, double lr_min,
+                         void *train_dev, void *blob_dev, void *stream)
+{
+    g_err.clear();
+    if (n_steps < 0 || sched_offset < 0 || sched_total < 1 || first_step < 0 || first_step > INT32_MAX - n_steps)
+        return fail(VCT_EINVAL, "vct_mlp_train: steps or schedule out of range");
+    if (!(std::isfinite(lr_min) && lr_min >= 0.0 && std::isfinite(lr) && lr >= lr_min))
+        return fail(VCT_EINVAL, "vct_mlp_train: need finite 0 <= lr_min <= lr");
+    for (int32_t i = 0; i < n_steps; ++i) {
+        // cosine decay from lr to lr_min over sched_total steps
+        const double a = lr_min + 0.5 * (lr - lr_min) * (1.0 + std::cos(M_PI * (double)(sched_offset + i) /
+                                                                            (double)sched_total));
+        const vct_status st = vct_mlp_train_step(rows_dev, n_rows, nullptr, seed, first_step + i, batch, a, 1,
+                                                 train_dev, blob_dev, stream);
+        if (st != VCT_OK)
+            return st;
+    }
+    return VCT_OK;
+}
+
 vct_status vct_mlp_forward(const float *x_dev, int64_t n, const void *blob_dev, float *out_dev, void *stream)
 {
     g_err.clear();

@@ -1,11 +1,11 @@
 // mlp.hip -- training of the learned controller (behaviour cloning of the MPC) on BF16 MFMA.
 //
 // One training step over a minibatch of B rows (B a multiple of 64):
-//  1. mlp_grad_kernel: one wave per 64 rows draws its rows (Philox, with replacement, or an
-//     explicit index list), normalises the 12 raw features, runs the forward pass, and
-//     back-propagates the mean squared error sum (o - t)^2 / B through the three hidden
-//     layers with MFMA GEMMs (activations and their gradients in BF16, accumulation FP32),
-//     writing its partial gradient (all parameters) and partial loss;
+//  1. mlp_grad_kernel: one four-wave workgroup per 64 rows draws its rows (Philox, with
+//     replacement, or an explicit index list), normalises the 12 raw features, runs the
+//     forward pass, and back-propagates the mean squared error sum (o - t)^2 / B through the
+//     three hidden layers with MFMA GEMMs (activations and their gradients in BF16,
+//     accumulation FP32), writing its partial gradient (all parameters) and partial loss;
 //  2. mlp_update_kernel: sums the partials in a fixed order (deterministic), then applies
 //     Adam to the FP32 master weights and refreshes the BF16 inference copy.
 // Dataset rows are 13 FP32: the 12 features then the target u/u_b.
@@ -195,166 +195,296 @@ __global__ void mlp_quantile_kernel(const uint32_t *hist, const float *range, in
 }
 
 // -------------------------------------------------------------- forward+backward ----
-// dW[u][v] = sum_s dH[s][u] Hin[s][v]  (64 x NV, K = 64 samples), written to g (row stride NV);
-// db[u] = sum_s dH[s][u]; dHin[s][v] = (sum_u dH[s][u] W[u][v]) [Hin[s][v] > 0] (if dHin).
-template <int NV>
-__device__ __forceinline__ void backprop_layer(const uint16_t *dH, const uint16_t *Hin, const uint16_t *W, float *gW,
-                                               float *gb, uint16_t *dHin, int lane)
+// One workgroup of four waves per 64-row tile of the minibatch; each wave takes a quarter of
+// every layer (16 output units in the forward pass and in the weight gradients, 16 samples in
+// the input gradients), so the 64 tiles of a 4096-row step run as 256 waves. Every MFMA
+// operand is one 16-byte LDS read: activations and gradients are kept both as [sample][unit]
+// and as [unit][sample] (the weight gradient contracts over samples), and the weights both as
+// [out][in] and as [in][out] (the input gradient contracts over output units). Row strides are
+// padded (72 and 24 elements) so the 16 rows a fragment reads fall on distinct banks.
+constexpr int kLd = 72, kLd16 = 24;
+
+struct TrainLds {
+    uint16_t w1[64 * kLd16], w2[64 * kLd], w3[64 * kLd], w4[16 * kLd];   // [out][in]
+    uint16_t w1t[16 * kLd], w2t[64 * kLd], w3t[64 * kLd];                // [in][out]
+    float b1[64], b2[64], b3[64];
+    uint16_t xs[64 * kLd16], xst[16 * kLd];                              // inputs [s][v], [v][s]
+    uint16_t h[3][64 * kLd], ht[3][64 * kLd];                            // activations [s][u], [u][s]
+    uint16_t g[2][64 * kLd], gt[2][64 * kLd];                            // gradients [s][u], [u][s]
+    float o[64], target[64], dout[64], red[4][64];
+};
+
+// Stores the lane's four values (units u0..u0+3 of sample s, or samples s0..s0+3 of unit u)
+// of a C fragment in both layouts.
+__device__ __forceinline__ void store_both(uint16_t *rowmajor, uint16_t *colmajor, int s, int u0, const uint16_t r[4])
 {
-    // weight gradient
+    *(uint2 *)(rowmajor + s * kLd + u0) =
+        uint2{(uint32_t)r[0] | ((uint32_t)r[1] << 16), (uint32_t)r[2] | ((uint32_t)r[3] << 16)};
 #pragma unroll
-    for (int ut = 0; ut < 4; ++ut)
+    for (int e = 0; e < 4; ++e)
+        colmajor[(u0 + e) * kLd + s] = r[e];
+}
+
+// Y^T = relu(W X^T + b) for units 16w..16w+15 and all 64 samples (K = 16 or 64).
+template <int K>
+__device__ __forceinline__ void fwd_quarter(const uint16_t *W, int ldw, const float *bias, const uint16_t *X, int ldx,
+                                            uint16_t *H, uint16_t *HT, int w, int lane)
+{
+    const float4 bb = *(const float4 *)(bias + 16 * w + 4 * (lane >> 4));
+    f32x4 acc[4];
 #pragma unroll
-        for (int vt = 0; vt < NV / 16; ++vt) {
-            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int st = 0; st < 4; ++st)
+        acc[st] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    if (K == 16) {
+        const bf16x4 a = frag_rows(W, ldw, 16 * w, 0, lane);
 #pragma unroll
-            for (int sb = 0; sb < 4; ++sb)
-                acc = mfma16(frag_cols(dH, kMlpH, 16 * sb, 16 * ut, lane), frag_cols(Hin, NV, 16 * sb, 16 * vt, lane),
-                             acc);
+        for (int st = 0; st < 4; ++st)
+            acc[st] = mfma16(a, frag_rows(X, ldx, 16 * st, 0, lane), acc[st]);
+    } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
-                gW[(16 * ut + 4 * (lane >> 4) + e) * NV + 16 * vt + (lane & 15)] = acc[e];
+        for (int kb = 0; kb < K / 32; ++kb) {
+            const bf16x8 a = frag8_rows(W, ldw, 16 * w, 32 * kb, lane);
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+                acc[st] = mfma32(a, frag8_rows(X, ldx, 16 * st, 32 * kb, lane), acc[st]);
         }
-    // bias gradient: lane u
+    }
+#pragma unroll
+    for (int st = 0; st < 4; ++st) {
+        uint16_t r[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            r[e] = f2bf(fmaxf(acc[st][e], 0.f));
+        store_both(H, HT, 16 * st + (lane & 15), 16 * w + 4 * (lane >> 4), r);
+    }
+}
+
+// Gradients of one hidden layer, the wave's quarter: dW rows 16w.. (NV columns), db of units
+// 16w.., and (dHin != null) the input gradient of samples 16w.. through the previous ReLU.
+// dH / dHT: the layer's output gradient in both layouts; HinT: its input [v][s]; WT: its
+// weights [v][u].
+template <int NV>
+__device__ __forceinline__ void bwd_quarter(const uint16_t *dH, const uint16_t *dHT, const uint16_t *HinT,
+                                            const uint16_t *WT, float *gW, float *gb, uint16_t *dHin, uint16_t *dHinT,
+                                            int w, int lane)
+{
+    // dW[u][v] = sum_s dH[s][u] Hin[s][v]: A = dH^T (rows u), B = Hin (K = samples)
+#pragma unroll
+    for (int vt = 0; vt < NV / 16; ++vt) {
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            acc = mfma32(frag8_rows(dHT, kLd, 16 * w, 32 * kb, lane), frag8_rows(HinT, kLd, 16 * vt, 32 * kb, lane),
+                         acc);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+            gW[(16 * w + 4 * (lane >> 4) + e) * NV + 16 * vt + (lane & 15)] = acc[e];
+    }
+    // db[u] = sum_s dH[s][u]: lane l sums samples 16q..16q+15 (q = l / 16) of unit 16w + l % 16,
+    // then the four quarters are added in a fixed order
     {
+        const uint16_t *p = dHT + (16 * w + (lane & 15)) * kLd + 16 * (lane >> 4);
+        const uint4 v0 = *(const uint4 *)p, v1 = *(const uint4 *)(p + 8);
+        const uint32_t wd[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
         float acc = 0.f;
-        for (int s = 0; s < 64; ++s)
-            acc += bf2f(dH[s * kMlpH + lane]);
-        gb[lane] = acc;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            acc += bf2f((uint16_t)(wd[q] & 0xFFFFu));
+            acc += bf2f((uint16_t)(wd[q] >> 16));
+        }
+        acc += __shfl_xor(acc, 16);
+        acc += __shfl_xor(acc, 32);
+        if (lane < 16)
+            gb[16 * w + lane] = acc;
     }
     if (!dHin)
         return;
-    // gradient of the layer input (through the previous ReLU)
+    // dHin[s][v] = sum_u dH[s][u] W[u][v] where Hin[s][v] > 0: A = dH (rows s), B = W (K = units)
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
+    for (int vt = 0; vt < NV / 16; ++vt) {
+        f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int vt = 0; vt < NV / 16; ++vt) {
-            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
+        for (int kb = 0; kb < 2; ++kb)
+            acc = mfma32(frag8_rows(dH, kLd, 16 * w, 32 * kb, lane), frag8_rows(WT, kLd, 16 * vt, 32 * kb, lane), acc);
+        // lane j + 16g holds samples 16w + 4g .. +3 of input unit 16vt + j
+        const int v = 16 * vt + (lane & 15), s0 = 16 * w + 4 * (lane >> 4);
+        const uint2 hin = *(const uint2 *)(HinT + v * kLd + s0);
+        const uint16_t hv[4] = {(uint16_t)(hin.x & 0xFFFFu), (uint16_t)(hin.x >> 16), (uint16_t)(hin.y & 0xFFFFu),
+                                (uint16_t)(hin.y >> 16)};
+        uint16_t r[4];
 #pragma unroll
-            for (int ub = 0; ub < 4; ++ub)
-                acc = mfma16(frag_rows(dH, kMlpH, 16 * st, 16 * ub, lane), frag_cols(W, NV, 16 * ub, 16 * vt, lane),
-                             acc);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int s = 16 * st + 4 * (lane >> 4) + e, v = 16 * vt + (lane & 15);
-                dHin[s * NV + v] = bf2f(Hin[s * NV + v]) > 0.f ? f2bf(acc[e]) : (uint16_t)0;
-            }
-        }
+        for (int e = 0; e < 4; ++e)
+            r[e] = bf2f(hv[e]) > 0.f ? f2bf(acc[e]) : (uint16_t)0;
+        store_both(dHinT, dHin, v, s0, r);   // [v][s] takes the four consecutive samples
+    }
 }
 
-__global__ __launch_bounds__(64) void mlp_grad_kernel(const float *__restrict__ data, int64_t n_rows,
-                                                      const int32_t *__restrict__ idx, uint32_t k0, uint32_t k1,
-                                                      int32_t step, int32_t batch,
-                                                      const unsigned char *__restrict__ blob,
-                                                      float *__restrict__ partial, float *__restrict__ loss_partial)
+__global__ __launch_bounds__(256) void mlp_grad_kernel(const float *__restrict__ data, int64_t n_rows,
+                                                       const int32_t *__restrict__ idx, uint32_t k0, uint32_t k1,
+                                                       int32_t step, int32_t batch,
+                                                       const unsigned char *__restrict__ blob,
+                                                       float *__restrict__ partial, float *__restrict__ loss_partial)
 {
-    __shared__ __align__(16) unsigned char net[kMlpNetBytes];
-    __shared__ __align__(16) uint16_t xs[64 * kMlpInP];
-    __shared__ __align__(16) uint16_t h1[64 * kMlpH], h2[64 * kMlpH], h3[64 * kMlpH], da[64 * kMlpH],
-        db[64 * kMlpH];
-    __shared__ float o[64], dout[64];
-    const int lane = threadIdx.x;
-    for (int i = lane; i < kMlpNetBytes / 16; i += 64)
-        ((uint4 *)net)[i] = ((const uint4 *)blob)[i];
-
-    const int64_t gi = (int64_t)blockIdx.x * 64 + lane;
-    int64_t row;
-    bool valid = true;
-    if (idx) {
-        row = idx[gi];
-        valid = row >= 0 && row < n_rows;
-        row = valid ? row : 0;   // an invalid index poisons the loss instead of reading outside
-    } else {   // uniform with replacement: floor(x n / 2^32) for a Philox word x
-        const U4 r = philox4x32_10((uint32_t)step, (uint32_t)gi, 5u, 0u, k0, k1);
-        row = (int64_t)(((uint64_t)r.x * (uint64_t)n_rows) >> 32);
+    __shared__ __align__(16) TrainLds L;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    // weights in both layouts, biases
+    const uint16_t *W1 = (const uint16_t *)(blob + kOffW1), *W2 = (const uint16_t *)(blob + kOffW2);
+    const uint16_t *W3 = (const uint16_t *)(blob + kOffW3), *W4 = (const uint16_t *)(blob + kOffW4);
+    for (int i = t; i < 64 * 64; i += 256) {
+        const int u = i >> 6, v = i & 63;
+        const uint16_t a = W2[i], b = W3[i];
+        L.w2[u * kLd + v] = a;
+        L.w2t[v * kLd + u] = a;
+        L.w3[u * kLd + v] = b;
+        L.w3t[v * kLd + u] = b;
     }
-    const float *mean = (const float *)(blob + kOffMean), *istd = (const float *)(blob + kOffIstd);
-    for (int f = 0; f < kMlpInP; ++f)
-        xs[lane * kMlpInP + f] = f < kMlpIn ? f2bf((data[row * kRow + f] - mean[f]) * istd[f]) : (uint16_t)0;
-    const float target = valid ? data[row * kRow + kMlpIn] : NAN;
+    for (int i = t; i < 64 * kMlpInP; i += 256) {
+        const int u = i / kMlpInP, v = i % kMlpInP;
+        L.w1[u * kLd16 + v] = W1[i];
+        L.w1t[v * kLd + u] = W1[i];
+    }
+    for (int i = t; i < kMlpOutP * 64; i += 256)
+        L.w4[(i >> 6) * kLd + (i & 63)] = W4[i];
+    if (t < 64) {
+        L.b1[t] = ((const float *)(blob + kOffB1))[t];
+        L.b2[t] = ((const float *)(blob + kOffB2))[t];
+        L.b3[t] = ((const float *)(blob + kOffB3))[t];
+    }
+    // the tile's rows: thread s < 64 takes sample s
+    const int64_t tile = blockIdx.x;
+    if (t < 64) {
+        const int64_t gi = tile * 64 + t;
+        int64_t row;
+        bool valid = true;
+        if (idx) {
+            row = idx[gi];
+            valid = row >= 0 && row < n_rows;
+            row = valid ? row : 0;   // an invalid index poisons the loss instead of reading outside
+        } else {   // uniform with replacement: floor(x n / 2^32) for a Philox word x
+            const U4 r = philox4x32_10((uint32_t)step, (uint32_t)gi, 5u, 0u, k0, k1);
+            row = (int64_t)(((uint64_t)r.x * (uint64_t)n_rows) >> 32);
+        }
+        const float *mean = (const float *)(blob + kOffMean), *istd = (const float *)(blob + kOffIstd);
+        for (int f = 0; f < kMlpInP; ++f) {
+            const uint16_t x = f < kMlpIn ? f2bf((data[row * kRow + f] - mean[f]) * istd[f]) : (uint16_t)0;
+            L.xs[t * kLd16 + f] = x;
+            L.xst[f * kLd + t] = x;
+        }
+        L.target[t] = valid ? data[row * kRow + kMlpIn] : NAN;
+    }
     __syncthreads();
 
-    const MlpNet n = mlp_net(net);
-    mlp_forward<DenseLayout>(n, xs, h1, h2, h3, o, lane, wave_sync);
-
-    float *g = partial + (int64_t)blockIdx.x * kMlpParams;
-    const float r = o[lane] - target;
-    dout[lane] = 2.f * r / (float)batch;
-    // partial loss: sum over the 64 rows of r^2 / B (fixed tree through LDS)
-    o[lane] = r * r / (float)batch;
+    // forward: each wave a quarter of the units of every layer
+    fwd_quarter<kMlpInP>(L.w1, kLd16, L.b1, L.xs, kLd16, L.h[0], L.ht[0], w, lane);
     __syncthreads();
-    for (int w = 32; w > 0; w >>= 1) {
-        if (lane < w)
-            o[lane] += o[lane + w];
-        __syncthreads();
+    fwd_quarter<kMlpH>(L.w2, kLd, L.b2, L.h[0], kLd, L.h[1], L.ht[1], w, lane);
+    __syncthreads();
+    fwd_quarter<kMlpH>(L.w3, kLd, L.b3, L.h[1], kLd, L.h[2], L.ht[2], w, lane);
+    __syncthreads();
+    {   // output unit for samples 16w..16w+15: row 0 of W4 H3^T sits in lanes 0..15
+        const float b4 = ((const float *)(blob + kOffB4))[0];
+        f32x4 acc = f32x4{b4, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            acc = mfma32(frag8_rows(L.w4, kLd, 0, 32 * kb, lane), frag8_rows(L.h[2], kLd, 16 * w, 32 * kb, lane), acc);
+        if (lane < 16)
+            L.o[16 * w + lane] = acc[0];
     }
-    if (lane == 0)
-        loss_partial[blockIdx.x] = o[0];
+    __syncthreads();
 
-    // output layer: lane u
-    {
-        const float w4u = bf2f(n.W4[lane]);
+    float *g = partial + tile * kMlpParams;
+    if (t < 64) {   // loss partial: sum over the 64 rows of r^2 / B (butterfly, fixed order)
+        const float r = L.o[t] - L.target[t];
+        L.dout[t] = 2.f * r / (float)batch;
+        float q = r * r / (float)batch;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            q += __shfl_xor(q, off);
+        if (t == 0)
+            loss_partial[tile] = q;
+    }
+    __syncthreads();
+    {   // output layer: gW4[u] = sum_s dout[s] h3[s][u] over four sample quarters; the gradient
+        // of h3 through the ReLU, in both layouts
+        const int u = t & 63, q = t >> 6;
+        const float w4u = bf2f(L.w4[u]);
         float acc = 0.f;
-        for (int s = 0; s < 64; ++s) {
-            const float hv = bf2f(h3[s * kMlpH + lane]);
-            acc += dout[s] * hv;
-            da[s * kMlpH + lane] = hv > 0.f ? f2bf(dout[s] * w4u) : (uint16_t)0;
+        for (int s = 16 * q; s < 16 * q + 16; ++s) {
+            const float hv = bf2f(L.h[2][s * kLd + u]);
+            acc += L.dout[s] * hv;
+            const uint16_t d = hv > 0.f ? f2bf(L.dout[s] * w4u) : (uint16_t)0;
+            L.g[0][s * kLd + u] = d;
+            L.gt[0][u * kLd + s] = d;
         }
-        g[kPW4 + lane] = acc;
-        for (int q = 1; q < kMlpOutP; ++q)
-            g[kPW4 + q * kMlpH + lane] = 0.f;
-        if (lane < kMlpOutP) {
-            float sb = 0.f;
-            if (lane == 0)
-                for (int s = 0; s < 64; ++s)
-                    sb += dout[s];
-            g[kPB4 + lane] = sb;
-        }
+        L.red[q][u] = acc;
     }
+    for (int i = t; i < (kMlpOutP - 1) * kMlpH; i += 256)   // output rows 1..15: padding
+        g[kPW4 + kMlpH + i] = 0.f;
     __syncthreads();
-    backprop_layer<kMlpH>(da, h2, n.W3, g + kPW3, g + kPB3, db, lane);
+    if (t < 64)
+        g[kPW4 + t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+    else if (t < 64 + kMlpOutP) {
+        float sb = 0.f;
+        if (t == 64)
+            for (int s = 0; s < 64; ++s)
+                sb += L.dout[s];
+        g[kPB4 + (t - 64)] = sb;
+    }
+    bwd_quarter<kMlpH>(L.g[0], L.gt[0], L.ht[1], L.w3t, g + kPW3, g + kPB3, L.g[1], L.gt[1], w, lane);
     __syncthreads();
-    backprop_layer<kMlpH>(db, h1, n.W2, g + kPW2, g + kPB2, da, lane);
+    bwd_quarter<kMlpH>(L.g[1], L.gt[1], L.ht[0], L.w2t, g + kPW2, g + kPB2, L.g[0], L.gt[0], w, lane);
     __syncthreads();
-    backprop_layer<kMlpInP>(da, xs, n.W1, g + kPW1, g + kPB1, nullptr, lane);
+    bwd_quarter<kMlpInP>(L.g[0], L.gt[0], L.xst, L.w1t, g + kPW1, g + kPB1, nullptr, nullptr, w, lane);
 }
 
 // ------------------------------------------------------------------ update ----
-__global__ void mlp_update_kernel(const float *__restrict__ partial, int n_parts, const float *__restrict__ loss_partial,
-                                  float *master, float *m, float *v, float *grad, float *loss, unsigned char *blob,
-                                  float lr, float bc1, float bc2, int apply)
+// Sums the per-tile partials in a fixed order (four threads per parameter each add a quarter
+// of the tiles in sequence, then the quarters are added pairwise), then Adam on the FP32
+// master weights and the BF16 / FP32 inference copy.
+constexpr int kUpdSplit = 4;
+
+__global__ __launch_bounds__(256) void mlp_update_kernel(const float *__restrict__ partial, int n_parts,
+                                                         const float *__restrict__ loss_partial, float *master,
+                                                         float *m, float *v, float *grad, float *loss,
+                                                         unsigned char *blob, float lr, float bc1, float bc2, int apply)
 {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    // sequential sums (fixed order); unrolled so that the loads are issued ahead of the adds
-    if (p == 0) {
+    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = gt / kUpdSplit, part = gt % kUpdSplit;
+    if (gt == 0) {
         float l = 0.f;
-#pragma unroll 16
         for (int b = 0; b < n_parts; ++b)
             l += loss_partial[b];
         *loss = l;
     }
-    if (p >= kMlpParams)
-        return;
+    const int per = (n_parts + kUpdSplit - 1) / kUpdSplit;
+    const int b0 = part * per, b1 = min(n_parts, b0 + per);
     float gs = 0.f;
+    if (p < kMlpParams) {
 #pragma unroll 16
-    for (int b = 0; b < n_parts; ++b)
-        gs += partial[(int64_t)b * kMlpParams + p];
+        for (int b = b0; b < b1; ++b)
+            gs += partial[(int64_t)b * kMlpParams + p];
+    }
+    // (q0 + q1) + (q2 + q3) across the four consecutive lanes of a parameter
+    gs += __shfl_xor(gs, 1);
+    gs += __shfl_xor(gs, 2);
+    if (p >= kMlpParams || part != 0)
+        return;
     if (padded_param(p))
         gs = 0.f;
     grad[p] = gs;
     if (!apply || padded_param(p))
         return;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float mm = b1 * m[p] + (1.f - b1) * gs;
-    const float vv = b2 * v[p] + (1.f - b2) * gs * gs;
+    const float be1 = 0.9f, be2 = 0.999f, eps = 1e-8f;
+    const float mm = be1 * m[p] + (1.f - be1) * gs;
+    const float vv = be2 * v[p] + (1.f - be2) * gs * gs;
     m[p] = mm;
     v[p] = vv;
-    const float w = master[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
-    master[p] = w;
+    const float wn = master[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    master[p] = wn;
     if (p < kPB1)
-        ((uint16_t *)blob)[p] = f2bf(w);
+        ((uint16_t *)blob)[p] = f2bf(wn);
     else
-        ((float *)(blob + kOffB1))[p - kPB1] = w;
+        ((float *)(blob + kOffB1))[p - kPB1] = wn;
 }
 
 // -------------------------------------------------------------- batched forward ----
@@ -414,10 +544,10 @@ hipError_t launch_mlp_step(const MlpTrain &t, const float *data, int64_t n_rows,
                            hipStream_t s)
 {
     const int parts = batch / 64;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(parts), dim3(64), 0, s, data, n_rows, idx, k0, k1, step, batch, t.blob,
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(parts), dim3(256), 0, s, data, n_rows, idx, k0, k1, step, batch, t.blob,
                        t.partial, t.loss_partial);
-    hipLaunchKernelGGL(mlp_update_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, s, t.partial, parts,
-                       t.loss_partial, t.master, t.m, t.v, t.grad, t.loss, t.blob, lr, bc1, bc2, apply);
+    hipLaunchKernelGGL(mlp_update_kernel, dim3((kMlpParams * kUpdSplit + 255) / 256), dim3(256), 0, s, t.partial,
+                       parts, t.loss_partial, t.master, t.m, t.v, t.grad, t.loss, t.blob, lr, bc1, bc2, apply);
     return hipGetLastError();
 }
 

@@ -7,8 +7,6 @@ unpacks the documented blob layout.
 """
 from __future__ import annotations
 
-import math
-
 import numpy as np
 import torch
 
@@ -127,11 +125,15 @@ class Policy:
         """Adam with a cosine learning-rate decay from lr to lr_min over `steps` minibatches
         drawn with replacement. Returns (step, loss) at every log_every steps."""
         log = []
-        for s in range(steps):
-            a = lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * s / max(1, steps)))
-            self.step(rows, seed, a, stream=stream)
-            if log_every and (s % log_every == 0 or s == steps - 1):
-                log.append((s, float(self.loss().item())))
+        marks = sorted({s for s in range(0, steps, log_every)} | {steps - 1}) if log_every else [steps - 1]
+        done = 0
+        for m in marks:   # the library runs the steps up to each logged one in one call
+            vct.vct_mlp_train(rows, rows.numel() // ROW, seed, self.step_count, m + 1 - done, done, max(1, steps),
+                              self.batch, lr, lr_min, self.train_buf, self.blob, stream)
+            self.step_count += m + 1 - done
+            done = m + 1
+            if log_every:
+                log.append((m, float(self.loss().item())))
         return log
 
     def forward(self, x: torch.Tensor, stream=None) -> torch.Tensor:

@@ -118,7 +118,7 @@ EXPORTS = ("vct_abi_version", "vct_last_error", "vct_population_bytes", "vct_met
            "vct_destroy_population",
            "vct_batch_create", "vct_batch_run", "vct_batch_info", "vct_batch_destroy", "vct_mpc_bytes",
            "vct_mpc_setup", "vct_mlp_blob_bytes", "vct_mlp_train_bytes", "vct_mlp_init", "vct_mlp_normalize",
-           "vct_mlp_train_step", "vct_mlp_forward", "vct_popbg_bytes")
+           "vct_mlp_train_step", "vct_mlp_train", "vct_mlp_forward", "vct_popbg_bytes")
 
 _lib = None
 
@@ -177,6 +177,9 @@ def lib() -> C.CDLL:
         L.vct_mlp_train_step.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_uint64, C.c_int32, C.c_int32,
                                          C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p]
         L.vct_mlp_train_step.restype = C.c_int
+        L.vct_mlp_train.argtypes = [C.c_void_p, C.c_int64, C.c_uint64, C.c_int32, C.c_int32, C.c_int32, C.c_int32,
+                                    C.c_int32, C.c_double, C.c_double, C.c_void_p, C.c_void_p, C.c_void_p]
+        L.vct_mlp_train.restype = C.c_int
         L.vct_mlp_forward.argtypes = [C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p]
         L.vct_mlp_forward.restype = C.c_int
         _lib = L
@@ -305,6 +308,13 @@ def vct_mlp_train_step(rows_dev, n_rows: int, idx_dev, seed: int, step: int, bat
     _check("vct_mlp_train_step",
            lib().vct_mlp_train_step(_ptr(rows_dev), int(n_rows), _ptr(idx_dev), int(seed), int(step), int(batch),
                                     float(lr), int(bool(apply)), _ptr(train_dev), _ptr(blob_dev), _stream(stream)))
+
+
+def vct_mlp_train(rows_dev, n_rows: int, seed: int, first_step: int, n_steps: int, sched_offset: int,
+                  sched_total: int, batch: int, lr: float, lr_min: float, train_dev, blob_dev, stream=None) -> None:
+    _check("vct_mlp_train", lib().vct_mlp_train(_ptr(rows_dev), n_rows, seed, first_step, n_steps, sched_offset,
+                                                sched_total, batch, lr, lr_min, _ptr(train_dev), _ptr(blob_dev),
+                                                _stream(stream)))
 
 
 def vct_mlp_forward(x_dev, n: int, blob_dev, out_dev, stream=None) -> None:

@@ -417,6 +417,29 @@ def test_training_reduces_loss_and_is_deterministic(G):
     assert np.array_equal(blobs[0], blobs[1])
 
 
+def test_multi_step_training_equals_single_steps(G):
+    """vct_mlp_train (many steps per call, the cosine schedule computed in the library) gives
+    the same weights, Adam moments and loss bit for bit as the same steps one call each."""
+    import math
+    torch, policy, _ = G
+    rows = torch.tensor(_f32(W.synthetic_policy_rows(82, 50_000)), dtype=torch.float32, device="cuda")
+    steps, lr, lr_min = 120, 2e-3, 1e-4
+    pols = []
+    for multi in (False, True):
+        pol = policy.Policy(batch=512)
+        pol.init(seed=5)
+        pol.normalize(rows, 0.0)
+        if multi:
+            pol.train(rows, steps=steps, seed=11, lr=lr, lr_min=lr_min, log_every=37)
+        else:
+            for s in range(steps):
+                pol.step(rows, 11, lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * s / steps)))
+        pols.append(pol)
+    assert pols[0].step_count == pols[1].step_count == steps
+    assert torch.equal(pols[0].train_buf, pols[1].train_buf)
+    assert torch.equal(pols[0].blob, pols[1].blob)
+
+
 def test_labels_with_empty_box_equal_mpc_rows(G):
     """Data aggregation: recording with the learned controller labels each sample with the
     MPC's action; with an empty box the closed loop is the MPC's, so the rows equal the MPC
