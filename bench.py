@@ -294,12 +294,17 @@ def learned_leg(days: int, arms=("mpc", "mlp")) -> dict:
             tot[arm]["s"] += r[arm]["sim_s"]
             tot[arm]["bins"] = [a + b for a, b in zip(tot[arm]["bins"], r[arm]["bins"])]
             tot[arm]["events"] = [a + b for a, b in zip(tot[arm]["events"], r[arm]["events"])]
-        fb += r["mlp"]["fallback_rate"] / slices
-        setup_s += r["mlp"]["setup_s"]
-        always += r["mlp"]["patients_always_fallback"]
+        if "mlp" in arms:
+            fb += r["mlp"]["fallback_rate"] / slices
+            setup_s += r["mlp"]["setup_s"]
+            always += r["mlp"]["patients_always_fallback"]
         log(f"[bench] learned: slice {i + 1}/{slices} done (" +
             ", ".join(f"{a} {r[a]['sim_s']:.2f} s" for a in arms) + ")")
     pd = n * days
+    if "mlp" not in arms:   # the exact-MPC arm alone (profiling)
+        t_mpc = tot["mpc"]["s"]
+        return {"patients": n, "days": days, "mpc_sim_s": t_mpc, "mpc_patient_days_per_s": pd / t_mpc,
+                "bins_mpc": tot["mpc"]["bins"]}
     t_mlp = tot["mlp"]["s"]
     out = {"workload": f"{n} patients x {days} days, FP32, exact linear MPC (24 samples, 50 projected-gradient "
                        "steps) vs 12-64-64-64-1 BF16 network with MPC fallback, common random numbers",
@@ -350,8 +355,8 @@ def main() -> int:
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-controller comparison")
     ap.add_argument("--learned-days", type=int, default=364,
                     help="horizon of the learned-controller comparison (1,000,000 patients; 364 = the paper's year)")
-    ap.add_argument("--learned-arms", default="mpc,mlp", choices=("mpc,mlp", "mlp"),
-                    help="mlp: the learned arm alone (no speedup or TIR difference; for profiling)")
+    ap.add_argument("--learned-arms", default="mpc,mlp", choices=("mpc,mlp", "mlp", "mpc"),
+                    help="one arm alone (no speedup or TIR difference; for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on exactly one GPU (asked for {args.gpus}); "
