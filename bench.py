@@ -57,12 +57,15 @@ ORACLE_SAMPLE_1THREAD = 200   # the oracle's single-thread rate: patients 0..199
 PROFILE = os.path.join(ROOT, "profiles", "simulate_kernel_paper_scale_1M_x_364d.md")
 
 
+SIM_SOURCES = ("internal.hpp", "kernels.hip", "mlp.hpp", "model.hpp", "mpc.hpp", "rng.hpp")
+
+
 def profile_counters() -> dict:
     """Counter figures of one simulate launch from the committed profile summary: HBM bytes
     (FETCH_SIZE + WRITE_SIZE, scaled by a 1 GiB copy) and the FP32 operations the kernel
-    executed (64 (ADD + MUL + TRANS) + 128 FMA per wave instruction); empty once the kernel
-    sources have changed since those counters were taken."""
-    import glob
+    executed (64 (ADD + MUL + TRANS) + 128 FMA per wave instruction); empty once the sources
+    of the simulate kernel's translation unit (kernels.hip and the headers it includes) have
+    changed since those counters were taken."""
     import hashlib
     try:
         txt = open(PROFILE).read()
@@ -71,8 +74,8 @@ def profile_counters() -> dict:
     keys = ("traffic_bytes_per_launch", "executed_fp32_flop_per_launch", "kernel_source_sha256")
     fields = dict(line.split(": ", 1) for line in txt.splitlines() if line.startswith(keys))
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2202_13927_amd", "csrc", "*"))):
-        h.update(open(f, "rb").read())
+    for f in SIM_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_2202_13927_amd", "csrc", f), "rb").read())
     if fields.get("kernel_source_sha256", "").strip() != h.hexdigest():
         return {}
     return {k: float(fields[k]) for k in keys[:2] if k in fields}

@@ -315,10 +315,12 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
  * ctrl->umax_rel / mpc_rho are baked in. */
 /* Population BG as a function of time (optional output of vct_simulate): for every sample
  * k = 0..K-1, over the patients of the call,
- *   int64  sum[K]  @0      sum of round(G 2^32) (G in mmol/L; exact, order-free integer sum:
- *                          the mean is sum / (n 2^32));
- *   uint64 min[K]  @8K     order-preserving key of the smallest G (as FP64):
- *   uint64 max[K]  @16K    key = bits ^ (sign ? all ones : sign bit); G = the key inverted;
+ *   int64  sum[K]  @0      sum of round(G 2^32) over the patients whose G is finite (G in
+ *                          mmol/L; exact, order-free integer sum: the mean is
+ *                          sum / ((n - nonfinite[k]) 2^32));
+ *   uint64 min[K]  @8K     order-preserving key of the smallest finite G (as FP64):
+ *   uint64 max[K]  @16K    key = bits ^ (sign ? all ones : sign bit); G = the key inverted
+ *                          (all ones / zero, which invert to NaN, when no G is finite);
  *   uint64 hist[402] @24K  the BG of every patient and sample in bins of 0.1 mmol/L: bin 0
  *                          below 0 (and NaN), bin 1 + floor(10 G) for 0 <= G < 40, bin 401
  *                          at or above 40 (the population's BG distribution, Sec. IV-D);
@@ -326,7 +328,10 @@ vct_status  vct_simulate(const vct_population *pop, const vct_protocol *protocol
  *                          and largest number of their samples with G below (b + 1) / 2
  *                          mmol/L, b = 0..48 (b = 49: all samples) -- the span of the
  *                          patients' own BG distributions (Fig. 3);
- * vct_simulate writes all of it (the buffer need not be initialised). Returns 24 K + 4016
+ *   int64  nonfinite[K] @24K+4016: patients whose G at sample k is not finite (their state
+ *                          left the finite range; the status bit says so). They stay in
+ *                          hist (bin 0) and span, and are left out of sum, min and max;
+ * vct_simulate writes all of it (the buffer need not be initialised). Returns 32 K + 4016
  * bytes, or 0 for invalid arguments. */
 size_t      vct_popbg_bytes(int32_t n_days, int32_t ts_min);
 size_t      vct_mpc_bytes(int64_t n_patients, int32_t precision);

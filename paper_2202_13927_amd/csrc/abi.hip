@@ -100,7 +100,7 @@ size_t vct_popbg_bytes(int32_t n_days, int32_t ts_min)
 {
     if (n_days <= 0 || ts_min <= 0 || 1440 % ts_min != 0)
         return 0;
-    return ((size_t)3 * (size_t)n_days * (size_t)(1440 / ts_min) + 502) * sizeof(int64_t);
+    return ((size_t)4 * (size_t)n_days * (size_t)(1440 / ts_min) + 502) * sizeof(int64_t);
 }
 
 size_t vct_traj_bytes(int32_t traj_patients, int32_t n_days, int32_t ts_min)
@@ -356,6 +356,7 @@ static vct_status build_sim_args(const vct_population *pop, const vct_protocol *
     a.pop_hist = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K : nullptr;
     a.span_min = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K + 402 : nullptr;
     a.span_max = sim->popbg_dev ? (uint64_t *)sim->popbg_dev + 3 * K + 452 : nullptr;
+    a.pop_nonfinite = sim->popbg_dev ? (int64_t *)sim->popbg_dev + 3 * K + 502 : nullptr;
     a.ext = sim->model_ext;
     a.tau_n = sim->tau_n;
     a.e_n = sim->e_n;

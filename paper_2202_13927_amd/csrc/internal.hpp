@@ -63,6 +63,7 @@ struct SimArgs {
     uint64_t *pop_min, *pop_max;   // [K] order-preserving keys of min / max G
     uint64_t *pop_hist;   // [402] pooled BG bins of 0.1 mmol/L
     uint64_t *span_min, *span_max;   // [50] min / max over patients of the cumulative 0.5 mmol/L bins
+    int64_t *pop_nonfinite;   // [K] patients whose G is not finite (left out of sum, min, max)
     int64_t K;
     // model extensions (Sec. IV-B): subcutaneous glucagon and exercise states
     int32_t ext;          // 1: the extended model

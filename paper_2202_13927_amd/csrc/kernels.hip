@@ -164,24 +164,30 @@ __device__ __forceinline__ void pop_accumulate(const SimArgs &a, int32_t k, R G,
 {
     using u64 = unsigned long long;
     const double g = (double)G;
-    const u64 q = live ? (u64)__double2ll_rn(g * 4294967296.0) : 0ull;
+    // a patient whose state is no longer finite (its status bit is set) leaves the sum and
+    // the extremes; the count of such patients per sample is kept beside them
+    const bool fin = live && __builtin_isfinite(g);
+    const u64 nonfin = __ballot(live && !fin);
+    const u64 q = fin ? (u64)__double2ll_rn(g * 4294967296.0) : 0ull;
     const u64 sum = wave_reduce(q, [](u64 x, u64 y) { return x + y; });
     u64 mn, mx;
     if constexpr (sizeof(R) == 4) {   // FP32 keys; the extremes converted once
         const uint32_t key = order_key32(G);
-        const uint32_t kmn = wave_reduce(live ? key : ~0u, [](uint32_t x, uint32_t y) { return x < y ? x : y; });
-        const uint32_t kmx = wave_reduce(live ? key : 0u, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
+        const uint32_t kmn = wave_reduce(fin ? key : ~0u, [](uint32_t x, uint32_t y) { return x < y ? x : y; });
+        const uint32_t kmx = wave_reduce(fin ? key : 0u, [](uint32_t x, uint32_t y) { return x > y ? x : y; });
         mn = kmn == ~0u ? ~0ull : order_key((double)order_key32_inv(kmn));
         mx = kmx == 0u ? 0ull : order_key((double)order_key32_inv(kmx));
     } else {
         const u64 key = order_key(g);
-        mn = wave_reduce(live ? key : ~0ull, [](u64 x, u64 y) { return x < y ? x : y; });
-        mx = wave_reduce(live ? key : 0ull, [](u64 x, u64 y) { return x > y ? x : y; });
+        mn = wave_reduce(fin ? key : ~0ull, [](u64 x, u64 y) { return x < y ? x : y; });
+        mx = wave_reduce(fin ? key : 0ull, [](u64 x, u64 y) { return x > y ? x : y; });
     }
     if ((threadIdx.x & 63) == 0) {
         atomicAdd((u64 *)&a.pop_sum[k], sum);
         atomicMin((u64 *)&a.pop_min[k], mn);
         atomicMax((u64 *)&a.pop_max[k], mx);
+        if (nonfin)
+            atomicAdd((u64 *)&a.pop_nonfinite[k], (u64)__popcll(nonfin));
     }
 }
 
@@ -248,12 +254,14 @@ __device__ __forceinline__ void span_flush(const SimArgs &a, uint32_t *cnt, int 
     }
 }
 
-__global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, uint64_t *hist, int64_t K)
+__global__ void popbg_init_kernel(int64_t *sum, uint64_t *mn, uint64_t *mx, uint64_t *hist, int64_t *nonfinite,
+                                  int64_t K)
 {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
         sum[i] = 0;
         mn[i] = ~0ull;
         mx[i] = 0ull;
+        nonfinite[i] = 0;
     }
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < kPopBins; i += (int64_t)gridDim.x * blockDim.x)
         hist[i] = 0ull;
@@ -1566,7 +1574,7 @@ static void launch_sim_n(const SimArgs &a, hipStream_t s)
     const bool rec = a.record != nullptr;
     if (a.pop_sum) {   // not combined with traj / record (checked by the ABI)
         hipLaunchKernelGGL(popbg_init_kernel, dim3(256), dim3(256), 0, s, a.pop_sum, a.pop_min, a.pop_max, a.pop_hist,
-                           a.K);
+                           a.pop_nonfinite, a.K);
         launch_sim_o<R, CTRL, NOISY, kOutPop>(a, s);
         return;
     }

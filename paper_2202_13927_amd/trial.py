@@ -24,7 +24,7 @@ class TrialBuffers:
         self.mpc = None
         if int(trial["ctrl_kind"]) in (vct.VCT_CTRL_MPC, vct.VCT_CTRL_MLP):
             self.mpc = torch.empty(vct.vct_mpc_bytes(n, int(trial["precision"])), dtype=torch.uint8, device=device)
-        self.popbg = None      # optional int64 [3][K]: population BG per sample (sum, min, max keys)
+        self.popbg = None      # optional int64: population BG per sample (sum, min, max keys, counts)
         if popbg:
             self.popbg = torch.empty(vct.vct_popbg_bytes(int(trial["n_days"]), int(trial["ts_min"])) // 8,
                                      dtype=torch.int64, device=device)

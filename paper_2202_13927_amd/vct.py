@@ -234,8 +234,9 @@ def vct_popbg_bytes(n_days: int, ts_min: int) -> int:
 
 
 def popbg_decode(buf, n: int, K: int) -> dict:
-    """Population BG per sample from a vct_popbg_bytes buffer (torch int64 [3K]): mean, min,
-    max in mmol/L as numpy float64 arrays (the layout documented in vct.h)."""
+    """Population BG per sample from a vct_popbg_bytes buffer (torch int64): mean, min, max
+    in mmol/L over the patients with a finite G, as numpy float64 arrays (NaN where no G is
+    finite), and the count of the others (the layout documented in vct.h)."""
     import numpy as np
     full = buf.cpu().numpy()
     a = full[:3 * K].reshape(3, K)
@@ -243,7 +244,11 @@ def popbg_decode(buf, n: int, K: int) -> dict:
     neg = (keys >> np.uint64(63)) == 0
     bits = np.where(neg, ~keys, keys ^ np.uint64(1 << 63))
     mn, mx = bits.view(np.float64)
-    return {"pop_mean": a[0].astype(np.float64) / (n * 4294967296.0), "pop_sum_q32": a[0].copy(),
+    nonfinite = full[3 * K + 502:4 * K + 502].copy()
+    n_fin = n - nonfinite
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = np.where(n_fin > 0, a[0].astype(np.float64) / (np.maximum(n_fin, 1) * 4294967296.0), np.nan)
+    return {"pop_mean": mean, "pop_sum_q32": a[0].copy(), "pop_nonfinite": nonfinite,
             "pop_min": mn.copy(), "pop_max": mx.copy(), "pop_hist": full[3 * K:3 * K + 402].view(np.uint64).copy(),
             "span_min": full[3 * K + 402:3 * K + 452].copy(), "span_max": full[3 * K + 452:3 * K + 502].copy()}
 

@@ -337,6 +337,7 @@ def test_basal_scale_needs_pid_or_open_loop(gpu):
 def _pop_hist(traj_g):
     """Bins of 0.1 mmol/L: 0 below 0, 1 + floor(10 G) for 0 <= G < 40, 401 at or above 40."""
     g = np.asarray(traj_g, np.float64).ravel()
+    g = np.where(np.isnan(g), -1.0, g)          # NaN counts in bin 0
     b = np.where(g >= 0.0, 1 + np.floor(np.minimum(g * 10.0, 400.5)).astype(np.int64), 0)
     return np.bincount(b, minlength=402).astype(np.uint64)
 
@@ -351,8 +352,15 @@ def _span(traj_g):
 
 
 def _pop_from_traj(traj_g):
+    """Sum of round(G 2^32), min and max per sample over the patients whose G is finite
+    (NaN where none is), and the count of the others."""
     g = np.asarray(traj_g, np.float64)
-    return np.rint(g * 4294967296.0).astype(np.int64).sum(0), g.min(0), g.max(0)
+    fin = np.isfinite(g)
+    s = np.rint(np.where(fin, g, 0.0) * 4294967296.0).astype(np.int64).sum(0)
+    any_fin = fin.any(0)
+    mn = np.where(any_fin, np.where(fin, g, np.inf).min(0), np.nan)
+    mx = np.where(any_fin, np.where(fin, g, -np.inf).max(0), np.nan)
+    return s, mn, mx, (~fin).sum(0)
 
 
 @pytest.mark.parametrize("case", ["pid45", "pid64", "mpc45", "mlp45"])
@@ -376,14 +384,67 @@ def test_population_bg_equals_trajectories(gpu, case):
     p = gpu.to_host(b1)
     b2 = gpu.TrialBuffers(t, traj_patients=n)
     gpu.run(t, bufs=b2, mlp_blob=blob)
-    s, mn, mx = _pop_from_traj(gpu.to_host(b2)["traj_g"])
-    assert np.array_equal(p["pop_sum_q32"], s)
+    s, mn, mx, nf = _pop_from_traj(gpu.to_host(b2)["traj_g"])
+    assert np.array_equal(p["pop_sum_q32"], s) and np.array_equal(p["pop_nonfinite"], nf) and not nf.any()
     assert np.array_equal(p["pop_min"], mn) and np.array_equal(p["pop_max"], mx)
     assert np.allclose(p["pop_mean"], s / (n * 4294967296.0), rtol=1e-15)
     tg = gpu.to_host(b2)["traj_g"]
     assert np.array_equal(p["pop_hist"], _pop_hist(tg))
     smin, smax = _span(tg)
     assert np.array_equal(p["span_min"], smin) and np.array_equal(p["span_max"], smax)
+
+
+def test_population_bg_infeasible_fp64(gpu, orc):
+    """A population whose every patient has no finite basal state (the infeasible nominal
+    case): every G is NaN from the first sample, in the oracle and on the GPU. The
+    population curves leave such patients out and count them: the count is n at every
+    sample, the sum 0, mean, min and max NaN; the BG distribution holds them in bin 0."""
+    t = W.with_(W.c1_fp64_pid(), n_patients=64, n_days=2, cv=1e-9,
+                nominal=[W.NOMINAL[0], W.NOMINAL[0] * 1.5, *W.NOMINAL[2:]])
+    _say("[gpu] population BG, infeasible population, 64 x 2 d FP64")
+    b = gpu.TrialBuffers(t, popbg=True)
+    gpu.run(t, bufs=b)
+    p = gpu.to_host(b)
+    o = orc.simulate(t, n_traj=64, threads=THREADS)
+    s, mn, mx, nf = _pop_from_traj(o["traj_g"])
+    assert np.all(nf == 64)
+    assert np.array_equal(p["pop_nonfinite"], nf) and np.array_equal(p["pop_sum_q32"], s)
+    assert np.all(np.isnan(p["pop_mean"])) and np.all(np.isnan(p["pop_min"])) and np.all(np.isnan(p["pop_max"]))
+    assert p["pop_hist"][0] == 64 * o["K"] and int(p["pop_hist"].sum()) == 64 * o["K"]
+    assert np.array_equal(p["status"], o["status"])
+
+
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32])
+def test_population_bg_mixed_nonfinite(gpu, prec):
+    """Patients whose state turns non-finite part-way (their insulin elimination rate k_e
+    replaced by NaN after the population is drawn) beside ordinary ones, in a ragged last wave: the
+    population curves equal what the trajectories give with those patients left out of the
+    sum, min and max at each sample they are not finite, and counted there."""
+    from paper_2202_13927_amd import vct
+    n = 150
+    t = W.with_(W.c1_fp64_pid(), n_patients=n, n_days=1, precision=prec)
+    bad = np.arange(n) % 3 == 0
+    runs = []
+    for popbg in (True, False):
+        b = gpu.TrialBuffers(t, popbg=popbg, traj_patients=0 if popbg else n)
+        pop = gpu.create_population(t, b)
+        try:
+            rows = b.params.view(vct.VCT_NPARAM_ROWS, n)
+            rows[9, bad.nonzero()[0].tolist()] = float("nan")    # k_e: the basal state stays finite
+            _say(f"[gpu] population BG, mixed non-finite, {n} x 1 d, prec {prec}, popbg {popbg}")
+            gpu.simulate(t, pop, b)
+        finally:
+            vct.vct_destroy_population(pop)
+        runs.append(gpu.to_host(b))
+    p, tr = runs
+    s, mn, mx, nf = _pop_from_traj(tr["traj_g"])
+    assert nf.max() == bad.sum() and nf[-1] == bad.sum() and nf.min() < nf.max()   # turns non-finite part-way
+    assert np.array_equal(p["pop_nonfinite"], nf) and np.array_equal(p["pop_sum_q32"], s)
+    assert np.array_equal(p["pop_min"], mn) and np.array_equal(p["pop_max"], mx)
+    assert np.allclose(p["pop_mean"], s / ((n - nf) * 4294967296.0), rtol=1e-15)
+    assert np.all(np.isfinite(p["pop_mean"]))
+    assert np.array_equal(p["pop_hist"], _pop_hist(tr["traj_g"]))
+    assert np.all(p["status"][bad] & 1) and not np.any(p["status"][~bad] & 1)   # the non-finite bit
 
 
 def test_population_bg_matches_oracle(gpu, orc):
@@ -393,7 +454,8 @@ def test_population_bg_matches_oracle(gpu, orc):
     gpu.run(t, bufs=b)
     p = gpu.to_host(b)
     o = orc.simulate(t, n_traj=3000, threads=THREADS)
-    s, mn, mx = _pop_from_traj(o["traj_g"])
+    s, mn, mx, nf = _pop_from_traj(o["traj_g"])
+    assert not nf.any() and not p["pop_nonfinite"].any()
     assert np.allclose(p["pop_mean"], s / (3000 * 4294967296.0), rtol=1e-9)
     assert np.allclose(p["pop_min"], mn, rtol=1e-9) and np.allclose(p["pop_max"], mx, rtol=1e-9)
     assert np.all(p["pop_min"] <= p["pop_mean"]) and np.all(p["pop_mean"] <= p["pop_max"])
