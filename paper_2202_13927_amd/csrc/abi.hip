@@ -539,20 +539,31 @@ vct_status vct_mlp_normalize(const float *rows_dev, int64_t n_rows, double box_q
     return VCT_OK;
 }
 
+// Arguments shared by the single-step and multi-step training entry points.
+static vct_status check_train_buffers(const char *fn, const float *rows_dev, int64_t n_rows, const int32_t *idx_dev,
+                                      int32_t batch, void *train_dev, void *blob_dev)
+{
+    if (!rows_dev || !train_dev || !blob_dev)
+        return fail(VCT_EINVAL, "%s: null buffer", fn);
+    if ((uintptr_t)train_dev % 256 != 0 || (uintptr_t)blob_dev % 16 != 0 || (uintptr_t)rows_dev % 4 != 0 ||
+        (uintptr_t)idx_dev % 4 != 0)
+        return fail(VCT_EINVAL, "%s: misaligned buffer", fn);
+    if (n_rows < 1 || n_rows > ((int64_t)1 << 32))
+        return fail(VCT_EINVAL, "%s: n_rows %lld out of [1, 2^32]", fn, (long long)n_rows);
+    if (batch < 64 || batch > kMaxBatch || batch % 64 != 0)
+        return fail(VCT_EINVAL, "%s: batch %d (a multiple of 64 in [64, %d])", fn, batch, kMaxBatch);
+    return VCT_OK;
+}
+
 vct_status vct_mlp_train_step(const float *rows_dev, int64_t n_rows, const int32_t *idx_dev, uint64_t seed,
                               int32_t step, int32_t batch, double lr, int32_t apply, void *train_dev,
                               void *blob_dev, void *stream)
 {
     g_err.clear();
-    if (!rows_dev || !train_dev || !blob_dev)
-        return fail(VCT_EINVAL, "vct_mlp_train_step: null buffer");
-    if ((uintptr_t)train_dev % 256 != 0 || (uintptr_t)blob_dev % 16 != 0 || (uintptr_t)rows_dev % 4 != 0 ||
-        (uintptr_t)idx_dev % 4 != 0)
-        return fail(VCT_EINVAL, "vct_mlp_train_step: misaligned buffer");
-    if (n_rows < 1 || n_rows > ((int64_t)1 << 32))
-        return fail(VCT_EINVAL, "vct_mlp_train_step: n_rows %lld out of [1, 2^32]", (long long)n_rows);
-    if (batch < 64 || batch > kMaxBatch || batch % 64 != 0)
-        return fail(VCT_EINVAL, "vct_mlp_train_step: batch %d (a multiple of 64 in [64, %d])", batch, kMaxBatch);
+    const vct_status st = check_train_buffers("vct_mlp_train_step", rows_dev, n_rows, idx_dev, batch, train_dev,
+                                              blob_dev);
+    if (st != VCT_OK)
+        return st;
     if (step < 0)
         return fail(VCT_EINVAL, "vct_mlp_train_step: step %d < 0", step);
     if (!(std::isfinite(lr) && lr >= 0.0))
@@ -568,6 +579,13 @@ vct_status vct_mlp_train_step(const float *rows_dev, int64_t n_rows, const int32
     return VCT_OK;
 }
 
+// Learning rate of step i of a vct_mlp_train call: cosine decay from lr to lr_min over
+// sched_total steps.
+static double cosine_lr(double lr, double lr_min, int32_t sched_offset, int32_t i, int32_t sched_total)
+{
+    return lr_min + 0.5 * (lr - lr_min) * (1.0 + std::cos(M_PI * (double)(sched_offset + i) / (double)sched_total));
+}
+
 vct_status vct_mlp_train(const float *rows_dev, int64_t n_rows, uint64_t seed, int32_t first_step, int32_t n_steps,
                          int32_t sched_offset, int32_t sched_total, int32_t batch, double lr, double lr_min,
                          void *train_dev, void *blob_dev, void *stream)
@@ -577,14 +595,15 @@ vct_status vct_mlp_train(const float *rows_dev, int64_t n_rows, uint64_t seed, i
         return fail(VCT_EINVAL, "vct_mlp_train: steps or schedule out of range");
     if (!(std::isfinite(lr_min) && lr_min >= 0.0 && std::isfinite(lr) && lr >= lr_min))
         return fail(VCT_EINVAL, "vct_mlp_train: need finite 0 <= lr_min <= lr");
+    const vct_status st = check_train_buffers("vct_mlp_train", rows_dev, n_rows, nullptr, batch, train_dev, blob_dev);
+    if (st != VCT_OK)
+        return st;
     for (int32_t i = 0; i < n_steps; ++i) {
-        // cosine decay from lr to lr_min over sched_total steps
-        const double a = lr_min + 0.5 * (lr - lr_min) * (1.0 + std::cos(M_PI * (double)(sched_offset + i) /
-                                                                            (double)sched_total));
-        const vct_status st = vct_mlp_train_step(rows_dev, n_rows, nullptr, seed, first_step + i, batch, a, 1,
-                                                 train_dev, blob_dev, stream);
-        if (st != VCT_OK)
-            return st;
+        const vct_status s = vct_mlp_train_step(rows_dev, n_rows, nullptr, seed, first_step + i, batch,
+                                                cosine_lr(lr, lr_min, sched_offset, i, sched_total), 1, train_dev,
+                                                blob_dev, stream);
+        if (s != VCT_OK)
+            return s;
     }
     return VCT_OK;
 }

@@ -207,66 +207,100 @@ constexpr int kLd = 72, kLd16 = 24;
 struct TrainLds {
     uint16_t w1[64 * kLd16], w2[64 * kLd], w3[64 * kLd], w4[16 * kLd];   // [out][in]
     uint16_t w1t[16 * kLd], w2t[64 * kLd], w3t[64 * kLd];                // [in][out]
-    float b1[64], b2[64], b3[64];
+    alignas(16) float b1[64], b2[64], b3[64];
     uint16_t xs[64 * kLd16], xst[16 * kLd];                              // inputs [s][v], [v][s]
     uint16_t h[3][64 * kLd], ht[3][64 * kLd];                            // activations [s][u], [u][s]
     uint16_t g[2][64 * kLd], gt[2][64 * kLd];                            // gradients [s][u], [u][s]
-    float o[64], target[64], dout[64], red[4][64];
+    alignas(16) float o[64], target[64], dout[64], red[4][64];
 };
 
-// Stores the lane's four values (units u0..u0+3 of sample s, or samples s0..s0+3 of unit u)
-// of a C fragment in both layouts.
-__device__ __forceinline__ void store_both(uint16_t *rowmajor, uint16_t *colmajor, int s, int u0, const uint16_t r[4])
+// Workgroup barrier for LDS data only: waits for this wave's LDS operations, not for its
+// global stores, so the partial gradients stream out while the next layer runs.
+__device__ __forceinline__ void lds_barrier()
 {
-    *(uint2 *)(rowmajor + s * kLd + u0) =
-        uint2{(uint32_t)r[0] | ((uint32_t)r[1] << 16), (uint32_t)r[2] | ((uint32_t)r[3] << 16)};
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-        colmajor[(u0 + e) * kLd + s] = r[e];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
-// Y^T = relu(W X^T + b) for units 16w..16w+15 and all 64 samples (K = 16 or 64).
-template <int K>
-__device__ __forceinline__ void fwd_quarter(const uint16_t *W, int ldw, const float *bias, const uint16_t *X, int ldx,
-                                            uint16_t *H, uint16_t *HT, int w, int lane)
+// Stores the lane's four BF16 values (units u0..u0+3 of sample s, or samples s0..s0+3 of unit
+// u; packed in pairs, low half first) of a C fragment in both layouts.
+__device__ __forceinline__ void store_both(uint16_t *rowmajor, uint16_t *colmajor, int s, int u0, uint32_t p01,
+                                           uint32_t p23)
 {
-    const float4 bb = *(const float4 *)(bias + 16 * w + 4 * (lane >> 4));
+    *(uint2 *)(rowmajor + s * kLd + u0) = uint2{p01, p23};
+    colmajor[u0 * kLd + s] = (uint16_t)(p01 & 0xFFFFu);
+    colmajor[(u0 + 1) * kLd + s] = (uint16_t)(p01 >> 16);
+    colmajor[(u0 + 2) * kLd + s] = (uint16_t)(p23 & 0xFFFFu);
+    colmajor[(u0 + 3) * kLd + s] = (uint16_t)(p23 >> 16);
+}
+
+// Keeps the low / high BF16 half of a packed pair where the flag is set, zero elsewhere.
+__device__ __forceinline__ uint32_t keep_halves(uint32_t p, bool lo, bool hi)
+{
+    return p & ((lo ? 0x0000FFFFu : 0u) | (hi ? 0xFFFF0000u : 0u));
+}
+
+// Eight BF16 values at row-major (r, c0..c0+7) and transposed (c0..c0+7, r).
+__device__ __forceinline__ void put8_both(uint16_t *rowmajor, int ldr, uint16_t *colmajor, int r, int c0, uint4 v)
+{
+    *(uint4 *)(rowmajor + r * ldr + c0) = v;
+    const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        colmajor[(c0 + 2 * e) * kLd + r] = (uint16_t)(wd[e] & 0xFFFFu);
+        colmajor[(c0 + 2 * e + 1) * kLd + r] = (uint16_t)(wd[e] >> 16);
+    }
+}
+
+// Wave-local ordering of LDS accesses (the hardware keeps a wave's LDS operations in order;
+// this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_lds_order()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// H = relu(W X^T + b)^T for the wave's samples 16w..16w+15 and all 64 units (K = 16 or 64):
+// four 16-unit tiles, each element from the same MFMA operands and K order whichever wave
+// computes it.
+template <int K>
+__device__ __forceinline__ void fwd_rows(const uint16_t *W, int ldw, const float *bias, const uint16_t *X, int ldx,
+                                         uint16_t *H, uint16_t *HT, int w, int lane)
+{
     f32x4 acc[4];
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
-        acc[st] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    for (int ut = 0; ut < 4; ++ut) {
+        const float4 bb = *(const float4 *)(bias + 16 * ut + 4 * (lane >> 4));
+        acc[ut] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    }
     if (K == 16) {
-        const bf16x4 a = frag_rows(W, ldw, 16 * w, 0, lane);
+        const bf16x4 b = frag_rows(X, ldx, 16 * w, 0, lane);
 #pragma unroll
-        for (int st = 0; st < 4; ++st)
-            acc[st] = mfma16(a, frag_rows(X, ldx, 16 * st, 0, lane), acc[st]);
+        for (int ut = 0; ut < 4; ++ut)
+            acc[ut] = mfma16(frag_rows(W, ldw, 16 * ut, 0, lane), b, acc[ut]);
     } else {
 #pragma unroll
         for (int kb = 0; kb < K / 32; ++kb) {
-            const bf16x8 a = frag8_rows(W, ldw, 16 * w, 32 * kb, lane);
+            const bf16x8 b = frag8_rows(X, ldx, 16 * w, 32 * kb, lane);
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
-                acc[st] = mfma32(a, frag8_rows(X, ldx, 16 * st, 32 * kb, lane), acc[st]);
+            for (int ut = 0; ut < 4; ++ut)
+                acc[ut] = mfma32(frag8_rows(W, ldw, 16 * ut, 32 * kb, lane), b, acc[ut]);
         }
     }
 #pragma unroll
-    for (int st = 0; st < 4; ++st) {
-        uint16_t r[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            r[e] = f2bf(fmaxf(acc[st][e], 0.f));
-        store_both(H, HT, 16 * st + (lane & 15), 16 * w + 4 * (lane >> 4), r);
-    }
+    for (int ut = 0; ut < 4; ++ut)
+        store_both(H, HT, 16 * w + (lane & 15), 16 * ut + 4 * (lane >> 4),
+                   pack_bf16(fmaxf(acc[ut][0], 0.f), fmaxf(acc[ut][1], 0.f)),
+                   pack_bf16(fmaxf(acc[ut][2], 0.f), fmaxf(acc[ut][3], 0.f)));
 }
 
-// Gradients of one hidden layer, the wave's quarter: dW rows 16w.. (NV columns), db of units
-// 16w.., and (dHin != null) the input gradient of samples 16w.. through the previous ReLU.
-// dH / dHT: the layer's output gradient in both layouts; HinT: its input [v][s]; WT: its
-// weights [v][u].
+// Weight and bias gradients of one hidden layer, the wave's quarter of its units: dW rows
+// 16w.. (NV columns) and db of units 16w... dHT: the layer's output gradient [u][s]; HinT:
+// its input [v][s] (both over all 64 samples).
 template <int NV>
-__device__ __forceinline__ void bwd_quarter(const uint16_t *dH, const uint16_t *dHT, const uint16_t *HinT,
-                                            const uint16_t *WT, float *gW, float *gb, uint16_t *dHin, uint16_t *dHinT,
-                                            int w, int lane)
+__device__ __forceinline__ void bwd_dw(const uint16_t *dHT, const uint16_t *HinT, float *gW, float *gb, int w,
+                                       int lane)
 {
     // dW[u][v] = sum_s dH[s][u] Hin[s][v]: A = dH^T (rows u), B = Hin (K = samples)
 #pragma unroll
@@ -282,26 +316,29 @@ __device__ __forceinline__ void bwd_quarter(const uint16_t *dH, const uint16_t *
     }
     // db[u] = sum_s dH[s][u]: lane l sums samples 16q..16q+15 (q = l / 16) of unit 16w + l % 16,
     // then the four quarters are added in a fixed order
-    {
-        const uint16_t *p = dHT + (16 * w + (lane & 15)) * kLd + 16 * (lane >> 4);
-        const uint4 v0 = *(const uint4 *)p, v1 = *(const uint4 *)(p + 8);
-        const uint32_t wd[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
-        float acc = 0.f;
+    const uint16_t *p = dHT + (16 * w + (lane & 15)) * kLd + 16 * (lane >> 4);
+    const uint4 v0 = *(const uint4 *)p, v1 = *(const uint4 *)(p + 8);
+    const uint32_t wd[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
+    float acc = 0.f;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            acc += bf2f((uint16_t)(wd[q] & 0xFFFFu));
-            acc += bf2f((uint16_t)(wd[q] >> 16));
-        }
-        acc += __shfl_xor(acc, 16);
-        acc += __shfl_xor(acc, 32);
-        if (lane < 16)
-            gb[16 * w + lane] = acc;
+    for (int q = 0; q < 8; ++q) {
+        acc += bf2f((uint16_t)(wd[q] & 0xFFFFu));
+        acc += bf2f((uint16_t)(wd[q] >> 16));
     }
-    if (!dHin)
-        return;
-    // dHin[s][v] = sum_u dH[s][u] W[u][v] where Hin[s][v] > 0: A = dH (rows s), B = W (K = units)
+    acc += __shfl_xor(acc, 16);
+    acc += __shfl_xor(acc, 32);
+    if (lane < 16)
+        gb[16 * w + lane] = acc;
+}
+
+// Input gradient of one hidden layer for the wave's samples 16w..16w+15 through the previous
+// ReLU: dHin[s][v] = sum_u dH[s][u] W[u][v] where Hin[s][v] > 0 (A = dH rows s, B = W^T rows
+// v, K = units), in both layouts. Reads and writes only the wave's own samples.
+__device__ __forceinline__ void bwd_dh(const uint16_t *dH, const uint16_t *HinT, const uint16_t *WT, uint16_t *dHin,
+                                       uint16_t *dHinT, int w, int lane)
+{
 #pragma unroll
-    for (int vt = 0; vt < NV / 16; ++vt) {
+    for (int vt = 0; vt < kMlpH / 16; ++vt) {
         f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
@@ -309,14 +346,172 @@ __device__ __forceinline__ void bwd_quarter(const uint16_t *dH, const uint16_t *
         // lane j + 16g holds samples 16w + 4g .. +3 of input unit 16vt + j
         const int v = 16 * vt + (lane & 15), s0 = 16 * w + 4 * (lane >> 4);
         const uint2 hin = *(const uint2 *)(HinT + v * kLd + s0);
-        const uint16_t hv[4] = {(uint16_t)(hin.x & 0xFFFFu), (uint16_t)(hin.x >> 16), (uint16_t)(hin.y & 0xFFFFu),
-                                (uint16_t)(hin.y >> 16)};
-        uint16_t r[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-            r[e] = bf2f(hv[e]) > 0.f ? f2bf(acc[e]) : (uint16_t)0;
-        store_both(dHinT, dHin, v, s0, r);   // [v][s] takes the four consecutive samples
+        const uint32_t p01 = keep_halves(pack_bf16(acc[0], acc[1]), bf2f((uint16_t)(hin.x & 0xFFFFu)) > 0.f,
+                                         bf2f((uint16_t)(hin.x >> 16)) > 0.f);
+        const uint32_t p23 = keep_halves(pack_bf16(acc[2], acc[3]), bf2f((uint16_t)(hin.y & 0xFFFFu)) > 0.f,
+                                         bf2f((uint16_t)(hin.y >> 16)) > 0.f);
+        store_both(dHinT, dHin, v, s0, p01, p23);   // [v][s] takes the four consecutive samples
     }
+}
+
+// The raw features and the target of one minibatch row (thread s < 64 of a tile).
+struct TileRow {
+    float x[kMlpIn];
+    float target;
+};
+
+__device__ __forceinline__ void fetch_row(const float *__restrict__ data, int64_t n_rows, const int32_t *idx,
+                                          uint32_t k0, uint32_t k1, int32_t step, int64_t gi, TileRow &r)
+{
+    int64_t row;
+    bool valid = true;
+    if (idx) {
+        row = idx[gi];
+        valid = row >= 0 && row < n_rows;
+        row = valid ? row : 0;   // an invalid index poisons the loss instead of reading outside
+    } else {   // uniform with replacement: floor(x n / 2^32) for a Philox word x
+        const U4 q = philox4x32_10((uint32_t)step, (uint32_t)gi, 5u, 0u, k0, k1);
+        row = (int64_t)(((uint64_t)q.x * (uint64_t)n_rows) >> 32);
+    }
+#pragma unroll
+    for (int f = 0; f < kMlpIn; ++f)
+        r.x[f] = data[row * kRow + f];
+    r.target = valid ? data[row * kRow + kMlpIn] : NAN;
+}
+
+// Gradient of one 64-row tile (256 threads): stages the network from the blob into LDS in
+// both layouts (16-byte loads), normalises the tile's rows, runs the forward pass and
+// back-propagates, writing the tile's partial gradient (all parameters) and partial loss.
+__device__ __forceinline__ void grad_tile(TrainLds &L, const float *__restrict__ data, int64_t n_rows,
+                                          const int32_t *idx, uint32_t k0, uint32_t k1, int32_t step, int32_t batch,
+                                          int64_t tile, const unsigned char *blob, float *__restrict__ partial,
+                                          float *__restrict__ loss_partial)
+{
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    TileRow row;
+    if (t < 64)
+        fetch_row(data, n_rows, idx, k0, k1, step, tile * 64 + t, row);
+    // weights: W2, W3 as 512 chunks of eight each, W1 and W4 as 128 each, b1..b3 as 48 float4
+    const uint4 *W2 = (const uint4 *)(blob + kOffW2), *W3 = (const uint4 *)(blob + kOffW3);
+    const uint4 a0 = W2[t], a1 = W2[t + 256], c0 = W3[t], c1 = W3[t + 256];
+    const uint4 e0 = t < 128 ? ((const uint4 *)(blob + kOffW1))[t] : ((const uint4 *)(blob + kOffW4))[t - 128];
+    float4 bb = float4{0.f, 0.f, 0.f, 0.f};
+    if (t < 48)
+        bb = ((const float4 *)(blob + kOffB1))[t];   // b1, b2, b3 are contiguous in the blob
+    const float *mean = (const float *)(blob + kOffMean), *istd = (const float *)(blob + kOffIstd);
+    put8_both(L.w2, kLd, L.w2t, t >> 3, (t & 7) * 8, a0);
+    put8_both(L.w2, kLd, L.w2t, (t + 256) >> 3, (t & 7) * 8, a1);
+    put8_both(L.w3, kLd, L.w3t, t >> 3, (t & 7) * 8, c0);
+    put8_both(L.w3, kLd, L.w3t, (t + 256) >> 3, (t & 7) * 8, c1);
+    if (t < 128)
+        put8_both(L.w1, kLd16, L.w1t, t >> 1, (t & 1) * 8, e0);
+    else
+        *(uint4 *)(L.w4 + ((t - 128) >> 3) * kLd + ((t - 128) & 7) * 8) = e0;
+    if (t < 48) {
+        float *dst = t < 16 ? L.b1 : (t < 32 ? L.b2 : L.b3);
+        *(float4 *)(dst + 4 * (t & 15)) = bb;
+    }
+    if (t < 64) {
+        static_assert(kMlpIn % 2 == 0 && kMlpInP == 16, "input pairs, one 16-element row");
+        uint32_t xp[kMlpInP / 2];
+#pragma unroll
+        for (int f = 0; f < kMlpInP; f += 2)
+            xp[f / 2] = f < kMlpIn ? pack_bf16((row.x[f] - mean[f]) * istd[f], (row.x[f + 1] - mean[f + 1]) * istd[f + 1])
+                                   : 0u;
+        *(uint4 *)(L.xs + t * kLd16) = uint4{xp[0], xp[1], xp[2], xp[3]};
+        *(uint4 *)(L.xs + t * kLd16 + 8) = uint4{xp[4], xp[5], xp[6], xp[7]};
+#pragma unroll
+        for (int f = 0; f < kMlpInP; ++f)
+            L.xst[f * kLd + t] = (uint16_t)(xp[f / 2] >> (16 * (f & 1)));
+        L.target[t] = row.target;
+    }
+    lds_barrier();
+
+    // Forward pass and the propagation of the output gradient back to layer 1, each wave on
+    // its own 16 samples (no workgroup barrier): activations h1..h3, gradients d3 (g[0]),
+    // d2 (g[1]) and d1 (into h[2], whose h3 the wave no longer reads), all in both layouts.
+    fwd_rows<kMlpInP>(L.w1, kLd16, L.b1, L.xs, kLd16, L.h[0], L.ht[0], w, lane);
+    wave_lds_order();
+    fwd_rows<kMlpH>(L.w2, kLd, L.b2, L.h[0], kLd, L.h[1], L.ht[1], w, lane);
+    wave_lds_order();
+    fwd_rows<kMlpH>(L.w3, kLd, L.b3, L.h[1], kLd, L.h[2], L.ht[2], w, lane);
+    wave_lds_order();
+    {   // output unit for samples 16w..16w+15: row 0 of W4 H3^T sits in lanes 0..15
+        const float b4 = ((const float *)(blob + kOffB4))[0];
+        f32x4 acc = f32x4{b4, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 2; ++kb)
+            acc = mfma32(frag8_rows(L.w4, kLd, 0, 32 * kb, lane), frag8_rows(L.h[2], kLd, 16 * w, 32 * kb, lane), acc);
+        if (lane < 16) {
+            const int s = 16 * w + lane;
+            const float r = acc[0] - L.target[s];
+            L.o[s] = acc[0];
+            L.dout[s] = 2.f * r / (float)batch;
+        }
+    }
+    wave_lds_order();
+    {   // output layer, the wave's samples (quarter q = w): gW4[u] = sum_s dout[s] h3[s][u] in
+        // sample order within the quarter, and d3 = dout w4 through the ReLU
+        const int u = lane, q = w;
+        const float w4u = bf2f(L.w4[u]);
+        const uint16_t *hp = L.ht[2] + u * kLd + 16 * q;
+        const uint4 h0 = *(const uint4 *)hp, h1 = *(const uint4 *)(hp + 8);
+        const uint32_t hw[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
+        float dv[16];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 d = *(const float4 *)(L.dout + 16 * q + 4 * i);
+            dv[4 * i] = d.x;
+            dv[4 * i + 1] = d.y;
+            dv[4 * i + 2] = d.z;
+            dv[4 * i + 3] = d.w;
+        }
+        float acc = 0.f;
+        uint32_t dw[8];
+#pragma unroll
+        for (int i = 0; i < 16; i += 2) {
+            const float h0v = bf2f((uint16_t)(hw[i >> 1] & 0xFFFFu)), h1v = bf2f((uint16_t)(hw[i >> 1] >> 16));
+            acc += dv[i] * h0v;
+            acc += dv[i + 1] * h1v;
+            dw[i >> 1] = keep_halves(pack_bf16(dv[i] * w4u, dv[i + 1] * w4u), h0v > 0.f, h1v > 0.f);
+            L.g[0][(16 * q + i) * kLd + u] = (uint16_t)(dw[i >> 1] & 0xFFFFu);
+            L.g[0][(16 * q + i + 1) * kLd + u] = (uint16_t)(dw[i >> 1] >> 16);
+        }
+        uint16_t *gp = L.gt[0] + u * kLd + 16 * q;
+        *(uint4 *)gp = uint4{dw[0], dw[1], dw[2], dw[3]};
+        *(uint4 *)(gp + 8) = uint4{dw[4], dw[5], dw[6], dw[7]};
+        L.red[q][u] = acc;
+    }
+    wave_lds_order();
+    bwd_dh(L.g[0], L.ht[1], L.w3t, L.g[1], L.gt[1], w, lane);    // d2
+    wave_lds_order();
+    bwd_dh(L.g[1], L.ht[0], L.w2t, L.h[2], L.ht[2], w, lane);    // d1
+    float *g = partial + tile * kMlpParams;
+    for (int i = t; i < (kMlpOutP - 1) * kMlpH; i += 256)   // output rows 1..15: padding
+        g[kPW4 + kMlpH + i] = 0.f;
+    lds_barrier();
+
+    // Contractions over all 64 samples, each wave a quarter of the units
+    if (t < 64) {   // loss partial: sum over the 64 rows of r^2 / B (butterfly, fixed order)
+        const float r = L.o[t] - L.target[t];
+        float q = r * r / (float)batch;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1)
+            q += __shfl_xor(q, off);
+        if (t == 0)
+            loss_partial[tile] = q;
+        g[kPW4 + t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+    } else if (t < 64 + kMlpOutP) {
+        float sb = 0.f;
+        if (t == 64)
+            for (int s = 0; s < 64; ++s)
+                sb += L.dout[s];
+        g[kPB4 + (t - 64)] = sb;
+    }
+    bwd_dw<kMlpH>(L.gt[0], L.ht[1], g + kPW3, g + kPB3, w, lane);
+    bwd_dw<kMlpH>(L.gt[1], L.ht[0], g + kPW2, g + kPB2, w, lane);
+    bwd_dw<kMlpInP>(L.ht[2], L.xst, g + kPW1, g + kPB1, w, lane);
+    lds_barrier();   // the tile's LDS may be reused
 }
 
 __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *__restrict__ data, int64_t n_rows,
@@ -326,165 +521,80 @@ __global__ __launch_bounds__(256) void mlp_grad_kernel(const float *__restrict__
                                                        float *__restrict__ partial, float *__restrict__ loss_partial)
 {
     __shared__ __align__(16) TrainLds L;
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
-    // weights in both layouts, biases
-    const uint16_t *W1 = (const uint16_t *)(blob + kOffW1), *W2 = (const uint16_t *)(blob + kOffW2);
-    const uint16_t *W3 = (const uint16_t *)(blob + kOffW3), *W4 = (const uint16_t *)(blob + kOffW4);
-    for (int i = t; i < 64 * 64; i += 256) {
-        const int u = i >> 6, v = i & 63;
-        const uint16_t a = W2[i], b = W3[i];
-        L.w2[u * kLd + v] = a;
-        L.w2t[v * kLd + u] = a;
-        L.w3[u * kLd + v] = b;
-        L.w3t[v * kLd + u] = b;
-    }
-    for (int i = t; i < 64 * kMlpInP; i += 256) {
-        const int u = i / kMlpInP, v = i % kMlpInP;
-        L.w1[u * kLd16 + v] = W1[i];
-        L.w1t[v * kLd + u] = W1[i];
-    }
-    for (int i = t; i < kMlpOutP * 64; i += 256)
-        L.w4[(i >> 6) * kLd + (i & 63)] = W4[i];
-    if (t < 64) {
-        L.b1[t] = ((const float *)(blob + kOffB1))[t];
-        L.b2[t] = ((const float *)(blob + kOffB2))[t];
-        L.b3[t] = ((const float *)(blob + kOffB3))[t];
-    }
-    // the tile's rows: thread s < 64 takes sample s
-    const int64_t tile = blockIdx.x;
-    if (t < 64) {
-        const int64_t gi = tile * 64 + t;
-        int64_t row;
-        bool valid = true;
-        if (idx) {
-            row = idx[gi];
-            valid = row >= 0 && row < n_rows;
-            row = valid ? row : 0;   // an invalid index poisons the loss instead of reading outside
-        } else {   // uniform with replacement: floor(x n / 2^32) for a Philox word x
-            const U4 r = philox4x32_10((uint32_t)step, (uint32_t)gi, 5u, 0u, k0, k1);
-            row = (int64_t)(((uint64_t)r.x * (uint64_t)n_rows) >> 32);
-        }
-        const float *mean = (const float *)(blob + kOffMean), *istd = (const float *)(blob + kOffIstd);
-        for (int f = 0; f < kMlpInP; ++f) {
-            const uint16_t x = f < kMlpIn ? f2bf((data[row * kRow + f] - mean[f]) * istd[f]) : (uint16_t)0;
-            L.xs[t * kLd16 + f] = x;
-            L.xst[f * kLd + t] = x;
-        }
-        L.target[t] = valid ? data[row * kRow + kMlpIn] : NAN;
-    }
-    __syncthreads();
-
-    // forward: each wave a quarter of the units of every layer
-    fwd_quarter<kMlpInP>(L.w1, kLd16, L.b1, L.xs, kLd16, L.h[0], L.ht[0], w, lane);
-    __syncthreads();
-    fwd_quarter<kMlpH>(L.w2, kLd, L.b2, L.h[0], kLd, L.h[1], L.ht[1], w, lane);
-    __syncthreads();
-    fwd_quarter<kMlpH>(L.w3, kLd, L.b3, L.h[1], kLd, L.h[2], L.ht[2], w, lane);
-    __syncthreads();
-    {   // output unit for samples 16w..16w+15: row 0 of W4 H3^T sits in lanes 0..15
-        const float b4 = ((const float *)(blob + kOffB4))[0];
-        f32x4 acc = f32x4{b4, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
-            acc = mfma32(frag8_rows(L.w4, kLd, 0, 32 * kb, lane), frag8_rows(L.h[2], kLd, 16 * w, 32 * kb, lane), acc);
-        if (lane < 16)
-            L.o[16 * w + lane] = acc[0];
-    }
-    __syncthreads();
-
-    float *g = partial + tile * kMlpParams;
-    if (t < 64) {   // loss partial: sum over the 64 rows of r^2 / B (butterfly, fixed order)
-        const float r = L.o[t] - L.target[t];
-        L.dout[t] = 2.f * r / (float)batch;
-        float q = r * r / (float)batch;
-#pragma unroll
-        for (int off = 32; off > 0; off >>= 1)
-            q += __shfl_xor(q, off);
-        if (t == 0)
-            loss_partial[tile] = q;
-    }
-    __syncthreads();
-    {   // output layer: gW4[u] = sum_s dout[s] h3[s][u] over four sample quarters; the gradient
-        // of h3 through the ReLU, in both layouts
-        const int u = t & 63, q = t >> 6;
-        const float w4u = bf2f(L.w4[u]);
-        float acc = 0.f;
-        for (int s = 16 * q; s < 16 * q + 16; ++s) {
-            const float hv = bf2f(L.h[2][s * kLd + u]);
-            acc += L.dout[s] * hv;
-            const uint16_t d = hv > 0.f ? f2bf(L.dout[s] * w4u) : (uint16_t)0;
-            L.g[0][s * kLd + u] = d;
-            L.gt[0][u * kLd + s] = d;
-        }
-        L.red[q][u] = acc;
-    }
-    for (int i = t; i < (kMlpOutP - 1) * kMlpH; i += 256)   // output rows 1..15: padding
-        g[kPW4 + kMlpH + i] = 0.f;
-    __syncthreads();
-    if (t < 64)
-        g[kPW4 + t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
-    else if (t < 64 + kMlpOutP) {
-        float sb = 0.f;
-        if (t == 64)
-            for (int s = 0; s < 64; ++s)
-                sb += L.dout[s];
-        g[kPB4 + (t - 64)] = sb;
-    }
-    bwd_quarter<kMlpH>(L.g[0], L.gt[0], L.ht[1], L.w3t, g + kPW3, g + kPB3, L.g[1], L.gt[1], w, lane);
-    __syncthreads();
-    bwd_quarter<kMlpH>(L.g[1], L.gt[1], L.ht[0], L.w2t, g + kPW2, g + kPB2, L.g[0], L.gt[0], w, lane);
-    __syncthreads();
-    bwd_quarter<kMlpInP>(L.g[0], L.gt[0], L.xst, L.w1t, g + kPW1, g + kPB1, nullptr, nullptr, w, lane);
+    grad_tile(L, data, n_rows, idx, k0, k1, step, batch, blockIdx.x, blob, partial, loss_partial);
 }
 
 // ------------------------------------------------------------------ update ----
-// Sums the per-tile partials in a fixed order (four threads per parameter each add a quarter
-// of the tiles in sequence, then the quarters are added pairwise), then Adam on the FP32
-// master weights and the BF16 / FP32 inference copy.
-constexpr int kUpdSplit = 4;
+// Parameters 256 pb .. 256 pb + 255 (one block of 256 threads): thread (g, q) = (t / 4,
+// t % 4) sums tiles q per .. (q + 1) per - 1 in order (per = ceil(tiles / 4)) for the four
+// parameters 256 pb + 4g .., with 16-byte loads, the quarters are added pairwise
+// ((q0 + q1) + (q2 + q3), the same in all four lanes), and lane q takes the Adam step of
+// parameter 4g + q on the FP32 master weights and the BF16 / FP32 inference copy.
+constexpr int kParamBlocks = (kMlpParams + 255) / 256;
+static_assert(kMlpParams % 4 == 0, "parameters are summed four at a time");
 
-__global__ __launch_bounds__(256) void mlp_update_kernel(const float *__restrict__ partial, int n_parts,
-                                                         const float *__restrict__ loss_partial, float *master,
-                                                         float *m, float *v, float *grad, float *loss,
-                                                         unsigned char *blob, float lr, float bc1, float bc2, int apply)
+__device__ __forceinline__ void update_block(int pb, int t, const float *__restrict__ partial, int n_parts,
+                                             float *master, float *m, float *v, float *grad, unsigned char *blob,
+                                             float lr, float bc1, float bc2, int apply)
 {
-    const int gt = blockIdx.x * blockDim.x + threadIdx.x;
-    const int p = gt / kUpdSplit, part = gt % kUpdSplit;
-    if (gt == 0) {
-        float l = 0.f;
-        for (int b = 0; b < n_parts; ++b)
-            l += loss_partial[b];
-        *loss = l;
-    }
-    const int per = (n_parts + kUpdSplit - 1) / kUpdSplit;
-    const int b0 = part * per, b1 = min(n_parts, b0 + per);
-    float gs = 0.f;
-    if (p < kMlpParams) {
-#pragma unroll 16
-        for (int b = b0; b < b1; ++b)
-            gs += partial[(int64_t)b * kMlpParams + p];
-    }
-    // (q0 + q1) + (q2 + q3) across the four consecutive lanes of a parameter
-    gs += __shfl_xor(gs, 1);
-    gs += __shfl_xor(gs, 2);
-    if (p >= kMlpParams || part != 0)
+    const int q = t & 3, p0 = pb * 256 + 4 * (t >> 2);
+    if (p0 >= kMlpParams)   // the four lanes of a group leave together
         return;
+    const int p = p0 + q;
+    const float m0 = m[p], v0 = v[p], w0 = master[p];   // in flight with the partials
+    const int per = (n_parts + 3) / 4;
+    const int b0 = q * per, b1 = min(n_parts, b0 + per);
+    float4 sum = float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 16
+    for (int b = b0; b < b1; ++b) {
+        const float4 x = *(const float4 *)(partial + (int64_t)b * kMlpParams + p0);
+        sum.x += x.x;
+        sum.y += x.y;
+        sum.z += x.z;
+        sum.w += x.w;
+    }
+    float s4[4] = {sum.x, sum.y, sum.z, sum.w};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        s4[e] += __shfl_xor(s4[e], 1);
+        s4[e] += __shfl_xor(s4[e], 2);
+    }
+    float gs = q == 0 ? s4[0] : (q == 1 ? s4[1] : (q == 2 ? s4[2] : s4[3]));
     if (padded_param(p))
         gs = 0.f;
     grad[p] = gs;
     if (!apply || padded_param(p))
         return;
     const float be1 = 0.9f, be2 = 0.999f, eps = 1e-8f;
-    const float mm = be1 * m[p] + (1.f - be1) * gs;
-    const float vv = be2 * v[p] + (1.f - be2) * gs * gs;
+    const float mm = be1 * m0 + (1.f - be1) * gs;
+    const float vv = be2 * v0 + (1.f - be2) * gs * gs;
     m[p] = mm;
     v[p] = vv;
-    const float wn = master[p] - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
+    const float wn = w0 - lr * (mm / bc1) / (sqrtf(vv / bc2) + eps);
     master[p] = wn;
     if (p < kPB1)
         ((uint16_t *)blob)[p] = f2bf(wn);
     else
         ((float *)(blob + kOffB1))[p - kPB1] = wn;
+}
+
+__device__ __forceinline__ void sum_loss(const float *loss_partial, int n_parts, float *loss)
+{
+    float l = 0.f;
+#pragma unroll 16
+    for (int b = 0; b < n_parts; ++b)
+        l += loss_partial[b];
+    *loss = l;
+}
+
+__global__ __launch_bounds__(256) void mlp_update_kernel(const float *__restrict__ partial, int n_parts,
+                                                         const float *__restrict__ loss_partial, float *master,
+                                                         float *m, float *v, float *grad, float *loss,
+                                                         unsigned char *blob, float lr, float bc1, float bc2, int apply)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        sum_loss(loss_partial, n_parts, loss);
+    update_block(blockIdx.x, threadIdx.x, partial, n_parts, master, m, v, grad, blob, lr, bc1, bc2, apply);
 }
 
 // -------------------------------------------------------------- batched forward ----
@@ -546,8 +656,8 @@ hipError_t launch_mlp_step(const MlpTrain &t, const float *data, int64_t n_rows,
     const int parts = batch / 64;
     hipLaunchKernelGGL(mlp_grad_kernel, dim3(parts), dim3(256), 0, s, data, n_rows, idx, k0, k1, step, batch, t.blob,
                        t.partial, t.loss_partial);
-    hipLaunchKernelGGL(mlp_update_kernel, dim3((kMlpParams * kUpdSplit + 255) / 256), dim3(256), 0, s, t.partial,
-                       parts, t.loss_partial, t.master, t.m, t.v, t.grad, t.loss, t.blob, lr, bc1, bc2, apply);
+    hipLaunchKernelGGL(mlp_update_kernel, dim3(kParamBlocks), dim3(256), 0, s, t.partial, parts, t.loss_partial,
+                       t.master, t.m, t.v, t.grad, t.loss, t.blob, lr, bc1, bc2, apply);
     return hipGetLastError();
 }
 

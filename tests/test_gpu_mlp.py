@@ -417,20 +417,23 @@ def test_training_reduces_loss_and_is_deterministic(G):
     assert np.array_equal(blobs[0], blobs[1])
 
 
-def test_multi_step_training_equals_single_steps(G):
+@pytest.mark.parametrize("batch,steps", [(512, 120), (4096, 300), (32768, 20)])
+def test_multi_step_training_equals_single_steps(G, batch, steps):
     """vct_mlp_train (many steps per call, the cosine schedule computed in the library) gives
-    the same weights, Adam moments and loss bit for bit as the same steps one call each."""
+    the same weights, Adam moments and loss bit for bit as the same steps one call each, for
+    small and large batches (8 to 512 tiles of 64 rows per step)."""
     import math
     torch, policy, _ = G
     rows = torch.tensor(_f32(W.synthetic_policy_rows(82, 50_000)), dtype=torch.float32, device="cuda")
-    steps, lr, lr_min = 120, 2e-3, 1e-4
+    lr, lr_min = 2e-3, 1e-4
     pols = []
     for multi in (False, True):
-        pol = policy.Policy(batch=512)
+        _say(f"[gpu] mlp training batch {batch}, {steps} steps, {'one call' if multi else 'one call per step'}")
+        pol = policy.Policy(batch=batch)
         pol.init(seed=5)
         pol.normalize(rows, 0.0)
         if multi:
-            pol.train(rows, steps=steps, seed=11, lr=lr, lr_min=lr_min, log_every=37)
+            pol.train(rows, steps=steps, seed=11, lr=lr, lr_min=lr_min, log_every=37 if steps < 256 else 0)
         else:
             for s in range(steps):
                 pol.step(rows, 11, lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * s / steps)))
