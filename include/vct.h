@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define VCT_ABI_VERSION 4
+#define VCT_ABI_VERSION 5  /* 5: the population-BG buffer gained the per-sample non-finite counts */
 #define VCT_NP 15          /* sampled parameters per patient                         */
 #define VCT_NX 11          /* model states per patient                               */
 #define VCT_NPARAM_ROWS 19 /* rows of the population buffer: 15 parameters, u_b, I*, attempts, status */

@@ -24,7 +24,7 @@ def test_library_exports_every_symbol():
     L = vct.lib()
     for name in header_symbols():
         assert hasattr(L, name), name
-    assert vct.vct_abi_version() == 4
+    assert vct.vct_abi_version() == 5
 
 
 def test_sizes():
