@@ -34,7 +34,6 @@ constexpr int kOffIstd = kOffMean + 16 * 4;                // f32 [16] 1 / featu
 constexpr int kOffLo = kOffIstd + 16 * 4;                  // f32 [16] 0.1 % quantile (raw)
 constexpr int kOffHi = kOffLo + 16 * 4;                    // f32 [16] 99.9 % quantile (raw)
 constexpr int kMlpBlobBytes = kOffHi + 16 * 4;
-constexpr int kMlpNetBytes = kOffMean;                     // weights + biases (staged into LDS)
 
 // FP32 parameter vector (master weights, Adam moments, gradients): same order, FP32.
 constexpr int kPW1 = 0, kPW2 = kPW1 + kMlpH * kMlpInP, kPW3 = kPW2 + kMlpH * kMlpH, kPW4 = kPW3 + kMlpH * kMlpH;
@@ -78,19 +77,6 @@ __device__ __forceinline__ bf16x8 frag8_rows(const uint16_t *M, int ld, int r0, 
     return __builtin_bit_cast(bf16x8, *(const uint4 *)p);
 }
 
-// B fragment of a row-major K x N matrix M: rows (k) r0.., columns c0..; also the A
-// fragment of M^T (rows of M^T = columns of M).
-__device__ __forceinline__ bf16x4 frag_cols(const uint16_t *M, int ld, int r0, int c0, int lane)
-{
-    const uint16_t *p = M + (r0 + 4 * (lane >> 4)) * ld + c0 + (lane & 15);
-    bf16x4 r;
-    r[0] = (short)p[0];
-    r[1] = (short)p[ld];
-    r[2] = (short)p[2 * ld];
-    r[3] = (short)p[3 * ld];
-    return r;
-}
-
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -105,143 +91,7 @@ __device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
 template <int LDI, int LDW1, int LDW, int LDH> struct MlpLayout {
     static constexpr int ldi = LDI, ldw1 = LDW1, ldw = LDW, ldh = LDH;
 };
-using DenseLayout = MlpLayout<kMlpInP, kMlpInP, kMlpH, kMlpH>;   // the blob's own layout
 using PaddedLayout = MlpLayout<24, 24, 72, 72>;                 // 48- and 144-byte rows
-
-// Y[64][64] = relu(X[64][K] W^T + b) for one wave; W row-major [64][K]. Computed as
-// Y^T = W X^T (A = W, B = X^T) with the bias as the accumulators' initial value, so each
-// lane ends with four consecutive units of one sample and writes them with one 8-byte
-// store. K = 16 uses v_mfma_f32_16x16x16_bf16, K = 64 v_mfma_f32_16x16x32_bf16. The result
-// is written as BF16 into `out` after `sync()` (so out may alias X); two passes of 32 units
-// keep 32 accumulator registers live.
-template <int K, int LDX, int LDW, int LDO, typename Sync>
-__device__ __forceinline__ void dense64_relu(const uint16_t *X, const uint16_t *W, const float *bias, uint16_t *out,
-                                             int lane, Sync sync)
-{
-    uint2 res[2][2][4];
-#pragma unroll
-    for (int half = 0; half < 2; ++half) {
-        f32x4 acc[2][4];   // [unit tile][sample tile]
-#pragma unroll
-        for (int ut = 0; ut < 2; ++ut) {
-            const float4 bb = *(const float4 *)(bias + 32 * half + 16 * ut + 4 * (lane >> 4));
-#pragma unroll
-            for (int st = 0; st < 4; ++st)
-                acc[ut][st] = f32x4{bb.x, bb.y, bb.z, bb.w};
-        }
-        if (K == 16) {
-            bf16x4 a[2], b[4];
-#pragma unroll
-            for (int ut = 0; ut < 2; ++ut)
-                a[ut] = frag_rows(W, LDW, 32 * half + 16 * ut, 0, lane);
-#pragma unroll
-            for (int st = 0; st < 4; ++st)
-                b[st] = frag_rows(X, LDX, 16 * st, 0, lane);
-#pragma unroll
-            for (int ut = 0; ut < 2; ++ut)
-#pragma unroll
-                for (int st = 0; st < 4; ++st)
-                    acc[ut][st] = mfma16(a[ut], b[st], acc[ut][st]);
-        } else {
-#pragma unroll
-            for (int kb = 0; kb < K / 32; ++kb) {
-                bf16x8 a[2], b[4];
-#pragma unroll
-                for (int ut = 0; ut < 2; ++ut)
-                    a[ut] = frag8_rows(W, LDW, 32 * half + 16 * ut, 32 * kb, lane);
-#pragma unroll
-                for (int st = 0; st < 4; ++st)
-                    b[st] = frag8_rows(X, LDX, 16 * st, 32 * kb, lane);
-#pragma unroll
-                for (int ut = 0; ut < 2; ++ut)
-#pragma unroll
-                    for (int st = 0; st < 4; ++st)
-                        acc[ut][st] = mfma32(a[ut], b[st], acc[ut][st]);
-            }
-        }
-#pragma unroll
-        for (int ut = 0; ut < 2; ++ut)
-#pragma unroll
-            for (int st = 0; st < 4; ++st)
-                res[half][ut][st] = uint2{pack_bf16(fmaxf(acc[ut][st][0], 0.f), fmaxf(acc[ut][st][1], 0.f)),
-                                          pack_bf16(fmaxf(acc[ut][st][2], 0.f), fmaxf(acc[ut][st][3], 0.f))};
-    }
-    sync();
-#pragma unroll
-    for (int half = 0; half < 2; ++half)
-#pragma unroll
-        for (int ut = 0; ut < 2; ++ut)
-#pragma unroll
-            for (int st = 0; st < 4; ++st)
-                *(uint2 *)(out + (16 * st + (lane & 15)) * LDO + 32 * half + 16 * ut + 4 * (lane >> 4)) =
-                    res[half][ut][st];
-}
-
-// Output layer: o[s] = H3[s][:] . W4[0][:] + b4[0] for the 64 samples, written to o (FP32).
-// A = W4 (row 0 is the output unit), B = H3^T: row 0 of the product sits in element 0 of
-// lanes 0..15.
-template <int LDH, int LDW, typename Sync>
-__device__ __forceinline__ void dense_out(const uint16_t *H, const uint16_t *W4, const float *b4, float *o, int lane,
-                                          Sync sync)
-{
-    f32x4 acc[4];
-    const float b = b4[0];
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-        acc[st] = f32x4{b, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int kb = 0; kb < kMlpH / 32; ++kb) {
-        const bf16x8 a = frag8_rows(W4, LDW, 0, 32 * kb, lane);
-#pragma unroll
-        for (int st = 0; st < 4; ++st)
-            acc[st] = mfma32(a, frag8_rows(H, LDH, 16 * st, 32 * kb, lane), acc[st]);
-    }
-    sync();
-    if (lane < 16) {
-#pragma unroll
-        for (int st = 0; st < 4; ++st)
-            o[16 * st + lane] = acc[st][0];
-    }
-}
-
-// Network pointers into LDS (or global) memory.
-struct MlpNet {
-    const uint16_t *W1, *W2, *W3, *W4;
-    const float *b1, *b2, *b3, *b4;
-};
-
-// Views of a blob (the unpadded layout).
-__device__ __forceinline__ MlpNet mlp_net(const unsigned char *base)
-{
-    MlpNet n;
-    n.W1 = (const uint16_t *)(base + kOffW1);
-    n.W2 = (const uint16_t *)(base + kOffW2);
-    n.W3 = (const uint16_t *)(base + kOffW3);
-    n.W4 = (const uint16_t *)(base + kOffW4);
-    n.b1 = (const float *)(base + kOffB1);
-    n.b2 = (const float *)(base + kOffB2);
-    n.b3 = (const float *)(base + kOffB3);
-    n.b4 = (const float *)(base + kOffB4);
-    return n;
-}
-
-// Forward pass of one wave: xs holds the 64 normalised samples (BF16 [64][L::ldi]); h1, h2,
-// h3 receive the hidden activations (BF16 [64][L::ldh]; they may alias each other and xs
-// when they are not needed later); o receives the outputs. sync() must order LDS writes
-// before reads across the wave.
-template <typename L, typename Sync>
-__device__ __forceinline__ void mlp_forward(const MlpNet &n, const uint16_t *xs, uint16_t *h1, uint16_t *h2,
-                                            uint16_t *h3, float *o, int lane, Sync sync)
-{
-    dense64_relu<kMlpInP, L::ldi, L::ldw1, L::ldh>(xs, n.W1, n.b1, h1, lane, sync);
-    sync();
-    dense64_relu<kMlpH, L::ldh, L::ldw, L::ldh>(h1, n.W2, n.b2, h2, lane, sync);
-    sync();
-    dense64_relu<kMlpH, L::ldh, L::ldw, L::ldh>(h2, n.W3, n.b3, h3, lane, sync);
-    sync();
-    dense_out<L::ldh, L::ldw>(h3, n.W4, n.b4, o, lane, sync);
-    sync();
-}
 
 // ------------------------------------------------ register-resident inference ----
 // The C fragment of Y^T = W X^T leaves lane j + 16 g holding units 4g..4g+3 of every 16-unit
