@@ -1,7 +1,7 @@
 // mlp.hip -- training of the learned controller (behaviour cloning of the MPC) on BF16 MFMA.
 //
 // One training step over a minibatch of B rows (B a multiple of 64):
-//  1. mlp_grad_kernel: one four-wave workgroup per 64 rows draws its rows (Philox, with
+//  1. mlp_grad_kernel: one eight-wave workgroup per 64 rows draws its rows (Philox, with
 //     replacement, or an explicit index list), normalises the 12 raw features, runs the
 //     forward pass, and back-propagates the mean squared error sum (o - t)^2 / B through the
 //     three hidden layers with MFMA GEMMs (activations and their gradients in BF16,
@@ -195,13 +195,15 @@ __global__ void mlp_quantile_kernel(const uint32_t *hist, const float *range, in
 }
 
 // -------------------------------------------------------------- forward+backward ----
-// One workgroup of four waves per 64-row tile of the minibatch; each wave takes a quarter of
-// every layer (16 output units in the forward pass and in the weight gradients, 16 samples in
-// the input gradients), so the 64 tiles of a 4096-row step run as 256 waves. Every MFMA
-// operand is one 16-byte LDS read: activations and gradients are kept both as [sample][unit]
-// and as [unit][sample] (the weight gradient contracts over samples), and the weights both as
-// [out][in] and as [in][out] (the input gradient contracts over output units). Row strides are
-// padded (72 and 24 elements) so the 16 rows a fragment reads fall on distinct banks.
+// One workgroup of eight waves per 64-row tile of the minibatch (two waves per SIMD). Wave
+// (b, h) = (w % 4, w / 4) owns samples 16b..16b+15 and the half h of the units (32 of 64) in
+// the forward pass and in the propagation of the gradient; the weight gradients, which
+// contract over all 64 samples, are split by output tiles. Every MFMA operand is one 16-byte
+// LDS read: activations and gradients are kept both as [sample][unit] and as [unit][sample]
+// (the weight gradient contracts over samples), and the weights both as [out][in] and as
+// [in][out] (the input gradient contracts over output units). Row strides are padded (72 and
+// 24 elements) so the 16 rows a fragment reads fall on distinct banks.
+constexpr int kGradThreads = 512;
 constexpr int kLd = 72, kLd16 = 24;
 
 struct TrainLds {
@@ -211,7 +213,7 @@ struct TrainLds {
     uint16_t xs[64 * kLd16], xst[16 * kLd];                              // inputs [s][v], [v][s]
     uint16_t h[3][64 * kLd], ht[3][64 * kLd];                            // activations [s][u], [u][s]
     uint16_t g[2][64 * kLd], gt[2][64 * kLd];                            // gradients [s][u], [u][s]
-    alignas(16) float o[64], target[64], dout[64], red[4][64];
+    alignas(16) float o[64], target[64], dout[64], red[8][64];
 };
 
 // Workgroup barrier for LDS data only: waits for this wave's LDS operations, not for its
@@ -261,62 +263,65 @@ __device__ __forceinline__ void wave_lds_order()
     __builtin_amdgcn_wave_barrier();
 }
 
-// H = relu(W X^T + b)^T for the wave's samples 16w..16w+15 and all 64 units (K = 16 or 64):
-// four 16-unit tiles, each element from the same MFMA operands and K order whichever wave
+// H = relu(W X^T + b)^T for samples 16b..16b+15 and units 32h..32h+31 (K = 16 or 64): two
+// 16-unit tiles, each element from the same MFMA operands and K order whichever wave
 // computes it.
 template <int K>
 __device__ __forceinline__ void fwd_rows(const uint16_t *W, int ldw, const float *bias, const uint16_t *X, int ldx,
-                                         uint16_t *H, uint16_t *HT, int w, int lane)
+                                         uint16_t *H, uint16_t *HT, int b, int h, int lane)
 {
-    f32x4 acc[4];
+    f32x4 acc[2];
 #pragma unroll
-    for (int ut = 0; ut < 4; ++ut) {
-        const float4 bb = *(const float4 *)(bias + 16 * ut + 4 * (lane >> 4));
-        acc[ut] = f32x4{bb.x, bb.y, bb.z, bb.w};
+    for (int i = 0; i < 2; ++i) {
+        const float4 bb = *(const float4 *)(bias + 16 * (2 * h + i) + 4 * (lane >> 4));
+        acc[i] = f32x4{bb.x, bb.y, bb.z, bb.w};
     }
     if (K == 16) {
-        const bf16x4 b = frag_rows(X, ldx, 16 * w, 0, lane);
+        const bf16x4 x = frag_rows(X, ldx, 16 * b, 0, lane);
 #pragma unroll
-        for (int ut = 0; ut < 4; ++ut)
-            acc[ut] = mfma16(frag_rows(W, ldw, 16 * ut, 0, lane), b, acc[ut]);
+        for (int i = 0; i < 2; ++i)
+            acc[i] = mfma16(frag_rows(W, ldw, 16 * (2 * h + i), 0, lane), x, acc[i]);
     } else {
 #pragma unroll
         for (int kb = 0; kb < K / 32; ++kb) {
-            const bf16x8 b = frag8_rows(X, ldx, 16 * w, 32 * kb, lane);
+            const bf16x8 x = frag8_rows(X, ldx, 16 * b, 32 * kb, lane);
 #pragma unroll
-            for (int ut = 0; ut < 4; ++ut)
-                acc[ut] = mfma32(frag8_rows(W, ldw, 16 * ut, 32 * kb, lane), b, acc[ut]);
+            for (int i = 0; i < 2; ++i)
+                acc[i] = mfma32(frag8_rows(W, ldw, 16 * (2 * h + i), 32 * kb, lane), x, acc[i]);
         }
     }
 #pragma unroll
-    for (int ut = 0; ut < 4; ++ut)
-        store_both(H, HT, 16 * w + (lane & 15), 16 * ut + 4 * (lane >> 4),
-                   pack_bf16(fmaxf(acc[ut][0], 0.f), fmaxf(acc[ut][1], 0.f)),
-                   pack_bf16(fmaxf(acc[ut][2], 0.f), fmaxf(acc[ut][3], 0.f)));
+    for (int i = 0; i < 2; ++i)
+        store_both(H, HT, 16 * b + (lane & 15), 16 * (2 * h + i) + 4 * (lane >> 4),
+                   pack_bf16(fmaxf(acc[i][0], 0.f), fmaxf(acc[i][1], 0.f)),
+                   pack_bf16(fmaxf(acc[i][2], 0.f), fmaxf(acc[i][3], 0.f)));
 }
 
-// Weight and bias gradients of one hidden layer, the wave's quarter of its units: dW rows
-// 16w.. (NV columns) and db of units 16w... dHT: the layer's output gradient [u][s]; HinT:
-// its input [v][s] (both over all 64 samples).
-template <int NV>
-__device__ __forceinline__ void bwd_dw(const uint16_t *dHT, const uint16_t *HinT, float *gW, float *gb, int w,
-                                       int lane)
+// Weight gradient of one hidden layer for output units 16ut..16ut+15 and input tiles
+// vt0..vt0+NVT-1 (NV inputs in all), and with `bias` the bias gradient of those units. dHT:
+// the layer's output gradient [u][s]; HinT: its input [v][s] (both over all 64 samples).
+template <int NV, int NVT>
+__device__ __forceinline__ void bwd_dw(const uint16_t *dHT, const uint16_t *HinT, float *gW, float *gb, int ut,
+                                       int vt0, bool bias, int lane)
 {
     // dW[u][v] = sum_s dH[s][u] Hin[s][v]: A = dH^T (rows u), B = Hin (K = samples)
 #pragma unroll
-    for (int vt = 0; vt < NV / 16; ++vt) {
+    for (int i = 0; i < NVT; ++i) {
+        const int vt = vt0 + i;
         f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
-            acc = mfma32(frag8_rows(dHT, kLd, 16 * w, 32 * kb, lane), frag8_rows(HinT, kLd, 16 * vt, 32 * kb, lane),
+            acc = mfma32(frag8_rows(dHT, kLd, 16 * ut, 32 * kb, lane), frag8_rows(HinT, kLd, 16 * vt, 32 * kb, lane),
                          acc);
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-            gW[(16 * w + 4 * (lane >> 4) + e) * NV + 16 * vt + (lane & 15)] = acc[e];
+            gW[(16 * ut + 4 * (lane >> 4) + e) * NV + 16 * vt + (lane & 15)] = acc[e];
     }
-    // db[u] = sum_s dH[s][u]: lane l sums samples 16q..16q+15 (q = l / 16) of unit 16w + l % 16,
+    if (!bias)
+        return;
+    // db[u] = sum_s dH[s][u]: lane l sums samples 16q..16q+15 (q = l / 16) of unit 16ut + l % 16,
     // then the four quarters are added in a fixed order
-    const uint16_t *p = dHT + (16 * w + (lane & 15)) * kLd + 16 * (lane >> 4);
+    const uint16_t *p = dHT + (16 * ut + (lane & 15)) * kLd + 16 * (lane >> 4);
     const uint4 v0 = *(const uint4 *)p, v1 = *(const uint4 *)(p + 8);
     const uint32_t wd[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
     float acc = 0.f;
@@ -328,23 +333,24 @@ __device__ __forceinline__ void bwd_dw(const uint16_t *dHT, const uint16_t *HinT
     acc += __shfl_xor(acc, 16);
     acc += __shfl_xor(acc, 32);
     if (lane < 16)
-        gb[16 * w + lane] = acc;
+        gb[16 * ut + lane] = acc;
 }
 
-// Input gradient of one hidden layer for the wave's samples 16w..16w+15 through the previous
-// ReLU: dHin[s][v] = sum_u dH[s][u] W[u][v] where Hin[s][v] > 0 (A = dH rows s, B = W^T rows
-// v, K = units), in both layouts. Reads and writes only the wave's own samples.
+// Input gradient of one hidden layer for samples 16b..16b+15 and inputs 32h..32h+31 through
+// the previous ReLU: dHin[s][v] = sum_u dH[s][u] W[u][v] where Hin[s][v] > 0 (A = dH rows s,
+// B = W^T rows v, K = all 64 units), in both layouts.
 __device__ __forceinline__ void bwd_dh(const uint16_t *dH, const uint16_t *HinT, const uint16_t *WT, uint16_t *dHin,
-                                       uint16_t *dHinT, int w, int lane)
+                                       uint16_t *dHinT, int b, int h, int lane)
 {
 #pragma unroll
-    for (int vt = 0; vt < kMlpH / 16; ++vt) {
+    for (int i = 0; i < 2; ++i) {
+        const int vt = 2 * h + i;
         f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
-            acc = mfma32(frag8_rows(dH, kLd, 16 * w, 32 * kb, lane), frag8_rows(WT, kLd, 16 * vt, 32 * kb, lane), acc);
-        // lane j + 16g holds samples 16w + 4g .. +3 of input unit 16vt + j
-        const int v = 16 * vt + (lane & 15), s0 = 16 * w + 4 * (lane >> 4);
+            acc = mfma32(frag8_rows(dH, kLd, 16 * b, 32 * kb, lane), frag8_rows(WT, kLd, 16 * vt, 32 * kb, lane), acc);
+        // lane j + 16g holds samples 16b + 4g .. +3 of input unit 16vt + j
+        const int v = 16 * vt + (lane & 15), s0 = 16 * b + 4 * (lane >> 4);
         const uint2 hin = *(const uint2 *)(HinT + v * kLd + s0);
         const uint32_t p01 = keep_halves(pack_bf16(acc[0], acc[1]), bf2f((uint16_t)(hin.x & 0xFFFFu)) > 0.f,
                                          bf2f((uint16_t)(hin.x >> 16)) > 0.f);
@@ -379,37 +385,37 @@ __device__ __forceinline__ void fetch_row(const float *__restrict__ data, int64_
     r.target = valid ? data[row * kRow + kMlpIn] : NAN;
 }
 
-// Gradient of one 64-row tile (256 threads): stages the network from the blob into LDS in
-// both layouts (16-byte loads), normalises the tile's rows, runs the forward pass and
+// Gradient of one 64-row tile (kGradThreads threads): stages the network from the blob into
+// LDS in both layouts (16-byte loads), normalises the tile's rows, runs the forward pass and
 // back-propagates, writing the tile's partial gradient (all parameters) and partial loss.
 __device__ __forceinline__ void grad_tile(TrainLds &L, const float *__restrict__ data, int64_t n_rows,
                                           const int32_t *idx, uint32_t k0, uint32_t k1, int32_t step, int32_t batch,
                                           int64_t tile, const unsigned char *blob, float *__restrict__ partial,
                                           float *__restrict__ loss_partial)
 {
-    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, b = w & 3, h = w >> 2;
     TileRow row;
     if (t < 64)
         fetch_row(data, n_rows, idx, k0, k1, step, tile * 64 + t, row);
     // weights: W2, W3 as 512 chunks of eight each, W1 and W4 as 128 each, b1..b3 as 48 float4
-    const uint4 *W2 = (const uint4 *)(blob + kOffW2), *W3 = (const uint4 *)(blob + kOffW3);
-    const uint4 a0 = W2[t], a1 = W2[t + 256], c0 = W3[t], c1 = W3[t + 256];
-    const uint4 e0 = t < 128 ? ((const uint4 *)(blob + kOffW1))[t] : ((const uint4 *)(blob + kOffW4))[t - 128];
+    const uint4 a0 = ((const uint4 *)(blob + kOffW2))[t], c0 = ((const uint4 *)(blob + kOffW3))[t];
+    uint4 e0 = uint4{0u, 0u, 0u, 0u};
+    if (t < 256)
+        e0 = t < 128 ? ((const uint4 *)(blob + kOffW1))[t] : ((const uint4 *)(blob + kOffW4))[t - 128];
     float4 bb = float4{0.f, 0.f, 0.f, 0.f};
-    if (t < 48)
-        bb = ((const float4 *)(blob + kOffB1))[t];   // b1, b2, b3 are contiguous in the blob
+    if (t >= 256 && t < 256 + 48)
+        bb = ((const float4 *)(blob + kOffB1))[t - 256];   // b1, b2, b3 are contiguous in the blob
     const float *mean = (const float *)(blob + kOffMean), *istd = (const float *)(blob + kOffIstd);
     put8_both(L.w2, kLd, L.w2t, t >> 3, (t & 7) * 8, a0);
-    put8_both(L.w2, kLd, L.w2t, (t + 256) >> 3, (t & 7) * 8, a1);
     put8_both(L.w3, kLd, L.w3t, t >> 3, (t & 7) * 8, c0);
-    put8_both(L.w3, kLd, L.w3t, (t + 256) >> 3, (t & 7) * 8, c1);
     if (t < 128)
         put8_both(L.w1, kLd16, L.w1t, t >> 1, (t & 1) * 8, e0);
-    else
+    else if (t < 256)
         *(uint4 *)(L.w4 + ((t - 128) >> 3) * kLd + ((t - 128) & 7) * 8) = e0;
-    if (t < 48) {
-        float *dst = t < 16 ? L.b1 : (t < 32 ? L.b2 : L.b3);
-        *(float4 *)(dst + 4 * (t & 15)) = bb;
+    else if (t < 256 + 48) {
+        const int c = t - 256;
+        float *dst = c < 16 ? L.b1 : (c < 32 ? L.b2 : L.b3);
+        *(float4 *)(dst + 4 * (c & 15)) = bb;
     }
     if (t < 64) {
         static_assert(kMlpIn % 2 == 0 && kMlpInP == 16, "input pairs, one 16-element row");
@@ -427,71 +433,64 @@ __device__ __forceinline__ void grad_tile(TrainLds &L, const float *__restrict__
     }
     lds_barrier();
 
-    // Forward pass and the propagation of the output gradient back to layer 1, each wave on
-    // its own 16 samples (no workgroup barrier): activations h1..h3, gradients d3 (g[0]),
-    // d2 (g[1]) and d1 (into h[2], whose h3 the wave no longer reads), all in both layouts.
-    fwd_rows<kMlpInP>(L.w1, kLd16, L.b1, L.xs, kLd16, L.h[0], L.ht[0], w, lane);
-    wave_lds_order();
-    fwd_rows<kMlpH>(L.w2, kLd, L.b2, L.h[0], kLd, L.h[1], L.ht[1], w, lane);
-    wave_lds_order();
-    fwd_rows<kMlpH>(L.w3, kLd, L.b3, L.h[1], kLd, L.h[2], L.ht[2], w, lane);
-    wave_lds_order();
-    {   // output unit for samples 16w..16w+15: row 0 of W4 H3^T sits in lanes 0..15
+    // Forward pass and the propagation of the gradient back to layer 1: wave (b, h) computes
+    // samples 16b.. for the unit half h; a barrier before each layer that reads all 64 units
+    // of the previous one. Activations h1..h3, gradients d3 (g[0]), d2 (g[1]) and d1 (into
+    // h[2], whose h3 nobody reads any more by then), all in both layouts.
+    fwd_rows<kMlpInP>(L.w1, kLd16, L.b1, L.xs, kLd16, L.h[0], L.ht[0], b, h, lane);
+    lds_barrier();
+    fwd_rows<kMlpH>(L.w2, kLd, L.b2, L.h[0], kLd, L.h[1], L.ht[1], b, h, lane);
+    lds_barrier();
+    fwd_rows<kMlpH>(L.w3, kLd, L.b3, L.h[1], kLd, L.h[2], L.ht[2], b, h, lane);
+    lds_barrier();
+    {   // output unit for samples 16b..16b+15 (row 0 of W4 H3^T in lanes 0..15); both waves of
+        // the sample block compute it and store the same values, so each reads its own
         const float b4 = ((const float *)(blob + kOffB4))[0];
         f32x4 acc = f32x4{b4, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int kb = 0; kb < 2; ++kb)
-            acc = mfma32(frag8_rows(L.w4, kLd, 0, 32 * kb, lane), frag8_rows(L.h[2], kLd, 16 * w, 32 * kb, lane), acc);
+            acc = mfma32(frag8_rows(L.w4, kLd, 0, 32 * kb, lane), frag8_rows(L.h[2], kLd, 16 * b, 32 * kb, lane), acc);
         if (lane < 16) {
-            const int s = 16 * w + lane;
+            const int s = 16 * b + lane;
             const float r = acc[0] - L.target[s];
             L.o[s] = acc[0];
             L.dout[s] = 2.f * r / (float)batch;
         }
     }
     wave_lds_order();
-    {   // output layer, the wave's samples (quarter q = w): gW4[u] = sum_s dout[s] h3[s][u] in
-        // sample order within the quarter, and d3 = dout w4 through the ReLU
-        const int u = lane, q = w;
+    {   // output layer for units 32h + l % 32 and samples 16b + 8(l / 32) .. +7: the partial
+        // gW4[u] over those eight samples (in order) and d3 = dout w4 through the ReLU
+        const int u = 32 * h + (lane & 31), s0 = 16 * b + 8 * (lane >> 5);
         const float w4u = bf2f(L.w4[u]);
-        const uint16_t *hp = L.ht[2] + u * kLd + 16 * q;
-        const uint4 h0 = *(const uint4 *)hp, h1 = *(const uint4 *)(hp + 8);
-        const uint32_t hw[8] = {h0.x, h0.y, h0.z, h0.w, h1.x, h1.y, h1.z, h1.w};
-        float dv[16];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const float4 d = *(const float4 *)(L.dout + 16 * q + 4 * i);
-            dv[4 * i] = d.x;
-            dv[4 * i + 1] = d.y;
-            dv[4 * i + 2] = d.z;
-            dv[4 * i + 3] = d.w;
-        }
+        const uint4 hq = *(const uint4 *)(L.ht[2] + u * kLd + s0);
+        const uint32_t hw[4] = {hq.x, hq.y, hq.z, hq.w};
+        const float4 d0 = *(const float4 *)(L.dout + s0), d1 = *(const float4 *)(L.dout + s0 + 4);
+        const float dv[8] = {d0.x, d0.y, d0.z, d0.w, d1.x, d1.y, d1.z, d1.w};
         float acc = 0.f;
-        uint32_t dw[8];
+        uint32_t dw[4];
 #pragma unroll
-        for (int i = 0; i < 16; i += 2) {
+        for (int i = 0; i < 8; i += 2) {
             const float h0v = bf2f((uint16_t)(hw[i >> 1] & 0xFFFFu)), h1v = bf2f((uint16_t)(hw[i >> 1] >> 16));
             acc += dv[i] * h0v;
             acc += dv[i + 1] * h1v;
             dw[i >> 1] = keep_halves(pack_bf16(dv[i] * w4u, dv[i + 1] * w4u), h0v > 0.f, h1v > 0.f);
-            L.g[0][(16 * q + i) * kLd + u] = (uint16_t)(dw[i >> 1] & 0xFFFFu);
-            L.g[0][(16 * q + i + 1) * kLd + u] = (uint16_t)(dw[i >> 1] >> 16);
+            L.g[0][(s0 + i) * kLd + u] = (uint16_t)(dw[i >> 1] & 0xFFFFu);
+            L.g[0][(s0 + i + 1) * kLd + u] = (uint16_t)(dw[i >> 1] >> 16);
         }
-        uint16_t *gp = L.gt[0] + u * kLd + 16 * q;
-        *(uint4 *)gp = uint4{dw[0], dw[1], dw[2], dw[3]};
-        *(uint4 *)(gp + 8) = uint4{dw[4], dw[5], dw[6], dw[7]};
-        L.red[q][u] = acc;
+        *(uint4 *)(L.gt[0] + u * kLd + s0) = uint4{dw[0], dw[1], dw[2], dw[3]};
+        L.red[2 * b + (lane >> 5)][u] = acc;
     }
-    wave_lds_order();
-    bwd_dh(L.g[0], L.ht[1], L.w3t, L.g[1], L.gt[1], w, lane);    // d2
-    wave_lds_order();
-    bwd_dh(L.g[1], L.ht[0], L.w2t, L.h[2], L.ht[2], w, lane);    // d1
+    lds_barrier();
+    bwd_dh(L.g[0], L.ht[1], L.w3t, L.g[1], L.gt[1], b, h, lane);    // d2
+    lds_barrier();
+    bwd_dh(L.g[1], L.ht[0], L.w2t, L.h[2], L.ht[2], b, h, lane);    // d1
     float *g = partial + tile * kMlpParams;
-    for (int i = t; i < (kMlpOutP - 1) * kMlpH; i += 256)   // output rows 1..15: padding
+    for (int i = t; i < (kMlpOutP - 1) * kMlpH; i += kGradThreads)   // output rows 1..15: padding
         g[kPW4 + kMlpH + i] = 0.f;
     lds_barrier();
 
-    // Contractions over all 64 samples, each wave a quarter of the units
+    // Contractions over all 64 samples: wave w takes output tile w % 4 of each layer and half
+    // w / 4 of its input tiles (the bias gradient with the first half)
     if (t < 64) {   // loss partial: sum over the 64 rows of r^2 / B (butterfly, fixed order)
         const float r = L.o[t] - L.target[t];
         float q = r * r / (float)batch;
@@ -500,7 +499,8 @@ __device__ __forceinline__ void grad_tile(TrainLds &L, const float *__restrict__
             q += __shfl_xor(q, off);
         if (t == 0)
             loss_partial[tile] = q;
-        g[kPW4 + t] = (L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t]);
+        g[kPW4 + t] = ((L.red[0][t] + L.red[1][t]) + (L.red[2][t] + L.red[3][t])) +
+                      ((L.red[4][t] + L.red[5][t]) + (L.red[6][t] + L.red[7][t]));
     } else if (t < 64 + kMlpOutP) {
         float sb = 0.f;
         if (t == 64)
@@ -508,44 +508,47 @@ __device__ __forceinline__ void grad_tile(TrainLds &L, const float *__restrict__
                 sb += L.dout[s];
         g[kPB4 + (t - 64)] = sb;
     }
-    bwd_dw<kMlpH>(L.gt[0], L.ht[1], g + kPW3, g + kPB3, w, lane);
-    bwd_dw<kMlpH>(L.gt[1], L.ht[0], g + kPW2, g + kPB2, w, lane);
-    bwd_dw<kMlpInP>(L.ht[2], L.xst, g + kPW1, g + kPB1, w, lane);
-    lds_barrier();   // the tile's LDS may be reused
+    bwd_dw<kMlpH, 2>(L.gt[0], L.ht[1], g + kPW3, g + kPB3, b, 2 * h, h == 0, lane);
+    bwd_dw<kMlpH, 2>(L.gt[1], L.ht[0], g + kPW2, g + kPB2, b, 2 * h, h == 0, lane);
+    if (h == 0)
+        bwd_dw<kMlpInP, 1>(L.ht[2], L.xst, g + kPW1, g + kPB1, b, 0, true, lane);
 }
 
-__global__ __launch_bounds__(256) void mlp_grad_kernel(const float *__restrict__ data, int64_t n_rows,
-                                                       const int32_t *__restrict__ idx, uint32_t k0, uint32_t k1,
-                                                       int32_t step, int32_t batch,
-                                                       const unsigned char *__restrict__ blob,
-                                                       float *__restrict__ partial, float *__restrict__ loss_partial)
+__global__ __launch_bounds__(kGradThreads) void mlp_grad_kernel(const float *__restrict__ data, int64_t n_rows,
+                                                                const int32_t *__restrict__ idx, uint32_t k0,
+                                                                uint32_t k1, int32_t step, int32_t batch,
+                                                                const unsigned char *__restrict__ blob,
+                                                                float *__restrict__ partial,
+                                                                float *__restrict__ loss_partial)
 {
     __shared__ __align__(16) TrainLds L;
     grad_tile(L, data, n_rows, idx, k0, k1, step, batch, blockIdx.x, blob, partial, loss_partial);
 }
 
 // ------------------------------------------------------------------ update ----
-// Parameters 256 pb .. 256 pb + 255 (one block of 256 threads): thread (g, q) = (t / 4,
-// t % 4) sums tiles q per .. (q + 1) per - 1 in order (per = ceil(tiles / 4)) for the four
-// parameters 256 pb + 4g .., with 16-byte loads, the quarters are added pairwise
-// ((q0 + q1) + (q2 + q3), the same in all four lanes), and lane q takes the Adam step of
-// parameter 4g + q on the FP32 master weights and the BF16 / FP32 inference copy.
-constexpr int kParamBlocks = (kMlpParams + 255) / 256;
+// Parameters 64 pb .. 64 pb + 63 (one block of 256 threads): thread (g, q) = (t / 16, t % 16)
+// sums tiles q per .. (q + 1) per - 1 in order (per = ceil(tiles / 16)) for the four
+// parameters 64 pb + 4g .., with 16-byte loads; the 16 parts are added by a butterfly over
+// the lanes of the group (lane bits 0..3, the same sum in all 16 lanes), and lane q < 4 takes
+// the Adam step of parameter 4g + q on the FP32 master weights and the BF16 / FP32 inference
+// copy.
+constexpr int kUpdParts = 16;
+constexpr int kParamBlocks = (kMlpParams + 63) / 64;
 static_assert(kMlpParams % 4 == 0, "parameters are summed four at a time");
 
 __device__ __forceinline__ void update_block(int pb, int t, const float *__restrict__ partial, int n_parts,
                                              float *master, float *m, float *v, float *grad, unsigned char *blob,
                                              float lr, float bc1, float bc2, int apply)
 {
-    const int q = t & 3, p0 = pb * 256 + 4 * (t >> 2);
-    if (p0 >= kMlpParams)   // the four lanes of a group leave together
+    const int q = t & (kUpdParts - 1), p0 = pb * 64 + 4 * (t / kUpdParts);
+    if (p0 >= kMlpParams)   // the 16 lanes of a group leave together
         return;
-    const int p = p0 + q;
+    const int p = p0 + (q & 3);
     const float m0 = m[p], v0 = v[p], w0 = master[p];   // in flight with the partials
-    const int per = (n_parts + 3) / 4;
+    const int per = (n_parts + kUpdParts - 1) / kUpdParts;
     const int b0 = q * per, b1 = min(n_parts, b0 + per);
     float4 sum = float4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 16
+#pragma unroll 4
     for (int b = b0; b < b1; ++b) {
         const float4 x = *(const float4 *)(partial + (int64_t)b * kMlpParams + p0);
         sum.x += x.x;
@@ -555,10 +558,12 @@ __device__ __forceinline__ void update_block(int pb, int t, const float *__restr
     }
     float s4[4] = {sum.x, sum.y, sum.z, sum.w};
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        s4[e] += __shfl_xor(s4[e], 1);
-        s4[e] += __shfl_xor(s4[e], 2);
-    }
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+        for (int off = 1; off < kUpdParts; off <<= 1)
+            s4[e] += __shfl_xor(s4[e], off);
+    if (q >= 4)
+        return;
     float gs = q == 0 ? s4[0] : (q == 1 ? s4[1] : (q == 2 ? s4[2] : s4[3]));
     if (padded_param(p))
         gs = 0.f;
@@ -578,13 +583,18 @@ __device__ __forceinline__ void update_block(int pb, int t, const float *__restr
         ((float *)(blob + kOffB1))[p - kPB1] = wn;
 }
 
-__device__ __forceinline__ void sum_loss(const float *loss_partial, int n_parts, float *loss)
+// Minibatch loss = the sum of the per-tile partials, by one wave: lane l adds tiles l, l + 64,
+// .. in order (one round of loads for up to 64 tiles), then a butterfly in a fixed order.
+__device__ __forceinline__ void sum_loss(const float *loss_partial, int n_parts, float *loss, int lane)
 {
     float l = 0.f;
-#pragma unroll 16
-    for (int b = 0; b < n_parts; ++b)
+    for (int b = lane; b < n_parts; b += 64)
         l += loss_partial[b];
-    *loss = l;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1)
+        l += __shfl_xor(l, off);
+    if (lane == 0)
+        *loss = l;
 }
 
 __global__ __launch_bounds__(256) void mlp_update_kernel(const float *__restrict__ partial, int n_parts,
@@ -592,8 +602,8 @@ __global__ __launch_bounds__(256) void mlp_update_kernel(const float *__restrict
                                                          float *m, float *v, float *grad, float *loss,
                                                          unsigned char *blob, float lr, float bc1, float bc2, int apply)
 {
-    if (blockIdx.x == 0 && threadIdx.x == 0)
-        sum_loss(loss_partial, n_parts, loss);
+    if (blockIdx.x == 0 && threadIdx.x < 64)
+        sum_loss(loss_partial, n_parts, loss, threadIdx.x);
     update_block(blockIdx.x, threadIdx.x, partial, n_parts, master, m, v, grad, blob, lr, bc1, bc2, apply);
 }
 
@@ -654,7 +664,7 @@ hipError_t launch_mlp_step(const MlpTrain &t, const float *data, int64_t n_rows,
                            hipStream_t s)
 {
     const int parts = batch / 64;
-    hipLaunchKernelGGL(mlp_grad_kernel, dim3(parts), dim3(256), 0, s, data, n_rows, idx, k0, k1, step, batch, t.blob,
+    hipLaunchKernelGGL(mlp_grad_kernel, dim3(parts), dim3(kGradThreads), 0, s, data, n_rows, idx, k0, k1, step, batch, t.blob,
                        t.partial, t.loss_partial);
     hipLaunchKernelGGL(mlp_update_kernel, dim3(kParamBlocks), dim3(256), 0, s, t.partial, parts, t.loss_partial,
                        t.master, t.m, t.v, t.grad, t.loss, t.blob, lr, bc1, bc2, apply);
