@@ -140,7 +140,7 @@ def _check_grads(g_gpu, g_orc, g_emul, batch):
     assert not np.any(g_gpu["W1"][:, 12:]) and not np.any(g_gpu["W4"][1:]) and not np.any(g_gpu["b4"][1:])
 
 
-@pytest.mark.parametrize("batch", [64, 1024])
+@pytest.mark.parametrize("batch", [64, 1024, 65536])
 def test_gradient_matches_oracle(G, orc, batch):
     torch, policy, _ = G
     net = _dense_net(31)
