@@ -345,6 +345,34 @@ def test_always_fallback_is_mpc(G, orc):
     assert np.all(g["fallback"] == g["K"])
 
 
+@pytest.mark.parametrize("ctrl", ["mpc", "mlp"])
+def test_slices_equal_whole_controllers(G, ctrl):
+    """The MPC and the learned controller: one patient alone, a ragged slice and the rest each
+    give, patient by patient, the whole run's results bit for bit (a one-lane tile, ragged
+    tiles whose padding lanes replay a patient and write nothing, the partition of the
+    patients by the box recomputed per slice, the wave-cooperative fallback solve)."""
+    torch, policy, trial = G
+    t = _mlp_trial(precision=W.FP32, n_patients=130, n_days=2)
+    if ctrl == "mpc":
+        t = W.with_(t, ctrl_kind=W.CTRL_MPC)
+    net = W.synthetic_policy_net(71)
+
+    def run(tt):
+        _say(f"[gpu] {ctrl} slice first {tt.get('first_patient', 0)} n {tt['n_patients']}")
+        if ctrl == "mlp":
+            return _run_mlp(G, tt, net)[0]
+        return trial.to_host(trial.run(tt)[1])
+
+    whole = run(t)
+    parts = [run(W.with_(t, first_patient=f, n_patients=n)) for f, n in ((0, 1), (1, 65), (66, 64))]
+    keys = ("bins", "events", "sum_g", "min_g", "argmin_k", "sum_u", "status")
+    if ctrl == "mlp":
+        keys += ("fallback",)
+        assert whole["fallback"].sum() > 0 and (whole["fallback"] == 0).sum() > 0
+    for k in keys:
+        assert np.array_equal(whole[k], np.concatenate([p[k] for p in parts])), k
+
+
 @pytest.mark.parametrize("precision", [W.FP64, W.FP32])
 def test_closed_loop_matches_oracle(G, orc, precision):
     """A proportional-law network with a random perturbation and a box that leaves some
