@@ -1201,11 +1201,14 @@ __device__ __forceinline__ void run_patient(const SimArgs &a, int64_t j, bool li
 
 // Waves per SIMD the plain kernels are compiled for: the FP32 open-loop and PID loops
 // without per-sample outputs fit in 128 registers without spilling, which lets four waves
-// share a SIMD; the rest keep the compiler's choice.
+// share a SIMD; the FP32 dual-hormone loop fits in 168 (three waves; 186 registers and two
+// waves by the compiler's own choice, 8 % slower); the rest keep the compiler's choice.
 template <typename R, int CTRL, int OUT>
 constexpr int sim_waves_per_simd()
 {
-    return (sizeof(R) == 4 && CTRL <= kCtrlPid && OUT == 0) ? 4 : 1;
+    if (sizeof(R) == 4 && OUT == 0)
+        return CTRL <= kCtrlPid ? 4 : (CTRL == kCtrlDual ? 3 : 1);
+    return 1;
 }
 
 // Workgroup size of simulate_kernel: one wave with the population curves on (its 14.4 KB of
