@@ -104,6 +104,17 @@ def test_dual_full_size_sampled(gpu, orc):
     assert s["n_patients"] == t["n_patients"] and sum(s["bins"]) == t["n_patients"] * K
 
 
+def test_dual_slices_equal_whole(gpu):
+    """The dual-hormone AP on the extended model with exercise: one patient alone, a ragged
+    slice and the rest give, patient by patient, the whole run's results and doses bit for
+    bit (every draw, the arrangement and the sessions keyed by the global patient index)."""
+    t = W.with_(W.dual_hormone_year(), n_patients=130, n_days=14)
+    _, whole = _run(gpu, t)
+    parts = [_run(gpu, W.with_(t, first_patient=f, n_patients=n))[1] for f, n in ((0, 1), (1, 65), (66, 64))]
+    for k in ("bins", "events", "sum_g", "min_g", "argmin_k", "sum_u", "status", "doses"):
+        assert np.array_equal(whole[k], np.concatenate([p[k] for p in parts])), k
+
+
 def test_ext_rejects_unsupported_settings(gpu):
     from paper_2202_13927_amd import trial as T, vct
     t = W.with_(W.dual_hormone_year(), n_patients=64, n_days=1)
